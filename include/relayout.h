@@ -1,0 +1,354 @@
+/*
+ * relayout: schema-driven conversion of object collections between memory
+ * layouts on AMD Instinct MI355X (gfx950), and the host <-> device transfers
+ * that carry those conversions.
+ *
+ * The operation is the data movement behind the layout abstraction of the
+ * Marionette paper (arXiv 2511.04853): a collection is described once as a
+ * list of properties (Sec. VI), its storage is chosen separately as a layout
+ * (Sec. V and VII-B), and transfers between layouts copy every property of
+ * every object (Sec. VII-B, the default transfers), possibly across memory
+ * contexts (Sec. VII-A).
+ *
+ * Conventions for every entry point:
+ *  - No call throws; each returns an rl_status.  On a status other than
+ *    RL_OK, rl_last_error() gives a message (thread-local, valid until the
+ *    next call on that thread).
+ *  - Validation failures found on the host return at once and enqueue no
+ *    work.  Failures that only the device can see (a member total beyond a
+ *    capacity, an offset-type overflow, a member block outside its pool)
+ *    are recorded in a per-device status word and returned by rl_sync().
+ *  - The caller owns every data buffer; the library never frees them.
+ *    Handles (schemas, layouts, batches, servers) are owned by the library
+ *    until their destroy call; schemas and layouts are immutable and may be
+ *    shared between threads.
+ *  - Streams are borrowed hipStream_t values passed as void*; NULL is the
+ *    null stream.  Work is asynchronous on that stream: buffers must stay
+ *    alive and unmodified until the stream has been synchronised.
+ *  - Device pointers must point to memory of the current HIP device.
+ */
+#ifndef RELAYOUT_H
+#define RELAYOUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rl_status {
+  RL_OK = 0,
+  RL_EINVAL = 1,        /* malformed argument */
+  RL_EALIGN = 2,        /* a buffer not aligned as the layout needs */
+  RL_EOVERLAP = 3,      /* source and destination buffers overlap */
+  RL_ECAPACITY = 4,     /* members do not fit the destination capacity */
+  RL_EOVERFLOW = 5,     /* a member total does not fit the offset type */
+  RL_ENOMEM = 6,        /* an allocation of the library failed */
+  RL_EBUDGET = 7,       /* a request larger than the serving budget */
+  RL_EUNSUPPORTED = 8,  /* a valid request this library does not perform */
+  RL_EHIP = 9,          /* a HIP runtime call failed (message has its text) */
+  RL_EBUSY = 10,        /* the object is in use (e.g. ticket not complete) */
+  RL_EBOUNDS = 11       /* a source member block outside its pool/columns, or misaligned */
+} rl_status;
+
+/* Scalar types of a property (Sec. VI: per-item properties hold one native
+   type).  The numeric values are part of the ABI. */
+typedef enum rl_type {
+  RL_U8 = 0, RL_I8 = 1, RL_U16 = 2, RL_I16 = 3, RL_U32 = 4, RL_I32 = 5,
+  RL_U64 = 6, RL_I64 = 7, RL_F32 = 8, RL_F64 = 9
+} rl_type;
+
+/* ------------------------------------------------------------------ schema */
+
+/* One property of a schema (Sec. VI).
+ *  - extent == 1: per-item property, one leaf value per object;
+ *    extent  > 1: array property, E leaf values kept as E separate leaves.
+ *  - group == -1: the value belongs to the object;
+ *    group == g >= 0: the field is a member property of jagged vector group
+ *    g (each object holds a variable number of members).
+ *  - subgroup == -1: top level; subgroup == s >= 0: the field belongs to
+ *    sub-group s, whose fields must be consecutive.  Sub-group members are
+ *    separate leaves (kept in separate columns in SoA layouts) and form a
+ *    nested struct in natural record layouts.
+ *  - name: informational, may be NULL; copied. */
+typedef struct rl_field {
+  const char* name;
+  rl_type type;
+  uint32_t extent;
+  int32_t group;
+  int32_t subgroup;
+} rl_field;
+
+/* A jagged vector group (Sec. VI): the type of the prefix sum of member
+   counts, which may be narrower than the object index type.  One of RL_U32,
+   RL_I32, RL_U64. */
+typedef struct rl_jagged {
+  rl_type offset_type;
+} rl_jagged;
+
+typedef struct rl_schema rl_schema;
+
+/* Register a schema.  Fields are flattened in declaration order into
+ * per-object leaves (extent E gives E consecutive leaves) and, per jagged
+ * group, member leaves.  Limits: at most 64 per-object leaves, 8 member
+ * leaves per group, 4 groups, extent <= 64.
+ * Errors: RL_EINVAL (bad type/extent/group index, non-consecutive sub-group,
+ * a member field inside a sub-group, a group with no member field, an
+ * offset type other than U32/I32/U64, a limit exceeded). */
+rl_status rl_schema_create(const rl_field* fields, uint32_t n_fields,
+                           const rl_jagged* groups, uint32_t n_groups,
+                           rl_schema** out);
+void rl_schema_destroy(rl_schema* schema);
+
+/* Leaf counts of a schema.  Any out pointer may be NULL. */
+rl_status rl_schema_info(const rl_schema* schema, uint32_t* n_leaves,
+                         uint32_t* n_groups, uint32_t* n_slots);
+
+/* ------------------------------------------------------------------ layouts */
+
+typedef enum rl_kind {
+  RL_AOS = 0,    /* records: object i at i * stride, leaf at a byte offset;
+                    each jagged group as a (u64 byte offset into a member
+                    pool, u32 member count) pair in the record, the pool
+                    holding member records */
+  RL_SOA = 1,    /* one column per leaf; each jagged group as an offsets
+                    column (n + 1 entries, exclusive prefix sum) and one
+                    column per member leaf */
+  RL_AOSOA = 2   /* blocks of W objects; inside a block each leaf is a run
+                    of W values, runs in leaf order; the block stride is
+                    W * (sum of leaf sizes); the unused slots of a last
+                    partial block are zero.  Jagged groups as in RL_SOA. */
+} rl_kind;
+
+typedef enum rl_space {
+  RL_SPACE_DEVICE = 0,       /* device memory of the current device */
+  RL_SPACE_HOST = 1,         /* pageable host memory */
+  RL_SPACE_HOST_PINNED = 2   /* page-locked host memory (hipHostMalloc) */
+} rl_space;
+
+/* Description of a layout (Sec. VII-B: the layout decides where each
+ * property's values live; Sec. VII-A: its memory context).
+ *  - block_width: RL_AOSOA only, W >= 1.
+ *  - record_stride / slot_offsets: RL_AOS only.  A record has n_slots
+ *    slots: every per-object leaf in order and, where a jagged group's
+ *    first field is declared, its (ptr u64, len u32) pair.  NULL / 0 select
+ *    C natural alignment (scalars at multiples of their size, sub-groups as
+ *    nested structs aligned to their largest member, stride rounded up to
+ *    the largest alignment).  Explicit offsets describe a pre-existing
+ *    struct; slots may not overlap and must fit the stride.
+ *  - storage_type: per per-object leaf, the type stored in this layout;
+ *    NULL = the schema's type.  RL_F32 for an RL_F64 leaf stores it
+ *    narrowed (round to nearest even; overflow to infinity; subnormals
+ *    kept); RL_F64 for an RL_F32 leaf widens it (exact).  No other change.
+ *  - member pools (RL_AOS with jagged groups) use natural alignment of the
+ *    group's member leaves. */
+typedef struct rl_layout_desc {
+  rl_kind kind;
+  rl_space space;
+  uint32_t block_width;
+  uint64_t record_stride;
+  const uint64_t* slot_offsets;
+  const rl_type* storage_type;
+} rl_layout_desc;
+
+typedef struct rl_layout rl_layout;
+
+/* Errors: RL_EINVAL (bad kind/space, W == 0 for AoSoA, overlapping or
+ * out-of-stride slots, an unsupported storage change, a stride over 2^31). */
+rl_status rl_layout_create(const rl_schema* schema, const rl_layout_desc* desc,
+                           rl_layout** out);
+void rl_layout_destroy(rl_layout* layout);
+
+/* Buffers of a layout holding n_objects objects and n_members[g] members of
+ * each jagged group (n_members may be NULL without groups), in order:
+ *   RL_AOS:   records, then one member pool per group;
+ *   RL_SOA:   one column per per-object leaf, then per group the offsets
+ *             column and one column per member leaf;
+ *   RL_AOSOA: the blocks, then per group as RL_SOA.
+ * *n_buffers receives the count; bytes (may be NULL) receives each buffer's
+ * byte size and must have room for rl_layout_info's max_buffers entries. */
+rl_status rl_layout_buffers(const rl_layout* layout, uint64_t n_objects,
+                            const uint64_t* n_members, uint32_t* n_buffers,
+                            uint64_t* bytes);
+
+/* The resolved record layout of an RL_AOS layout: slot offsets (room for
+ * n_slots entries, may be NULL) and stride; and the buffer count. */
+rl_status rl_layout_info(const rl_layout* layout, uint64_t* slot_offsets,
+                         uint64_t* record_stride, uint32_t* max_buffers);
+
+/* ------------------------------------------------------------------ views */
+
+/* A collection stored in a layout: the buffers (see rl_layout_buffers) able
+ * to hold `capacity` objects and member_capacity[g] members per group
+ * (NULL without groups; for an RL_AOS pool, in member records). */
+typedef struct rl_view {
+  const rl_layout* layout;
+  uint64_t capacity;
+  const uint64_t* member_capacity;
+  void* const* buffers;
+} rl_view;
+
+/* ------------------------------------------------------------------ conversion */
+
+/* Convert objects 0..n-1 of src into dst (Sec. VII-B transfers between
+ * layouts): every leaf value is copied (or narrowed/widened as the two
+ * storage types say); jagged members are moved with their objects, the
+ * destination's member storage packed in object order from index 0
+ * (offsets rebased to start at 0; record pointers = first member index *
+ * member record size).  Padding bytes and unused block slots of dst are
+ * zero.  Both views must use device memory; the schemas must be the same
+ * object.  Asynchronous on `stream`.
+ * Host errors: RL_EINVAL (n over a capacity, mismatched schemas, NULL
+ * buffers), RL_EALIGN (a buffer not aligned to its element size, or a
+ * record buffer to its largest slot), RL_EOVERLAP (a destination buffer
+ * overlapping any source buffer), RL_EUNSUPPORTED (host spaces; AoS -> AoS
+ * with jagged groups; unsupported storage change).
+ * Device errors (rl_sync): RL_EOVERFLOW, RL_ECAPACITY, RL_EBOUNDS; dst is
+ * then unspecified but no memory outside the views is touched.
+ * n == 0: RL_OK, nothing enqueued. */
+rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t n,
+                     void* stream);
+
+/* The offsets step alone (Sec. VI: the prefix sum of the member counts of
+ * jagged group `group`): reads the counts of objects 0..n-1 from src
+ * (RL_AOS records, or an offsets column) and writes the n + 1 exclusive
+ * offsets into dst's offsets column (dst must be RL_SOA or RL_AOSOA).
+ * If total_host is not NULL the call synchronises the stream and stores
+ * the total there.  Device errors as rl_convert (RL_EOVERFLOW). */
+rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t group,
+                     uint64_t n, uint64_t* total_host, void* stream);
+
+/* Options of rl_transfer. */
+typedef enum rl_xfer_mode {
+  RL_XFER_AUTO = 0,      /* choose by size and spaces */
+  RL_XFER_STAGED = 1,    /* SDMA copies into device staging slots,
+                            overlapped with conversion kernels */
+  RL_XFER_ZERO_COPY = 2  /* kernels read/write pinned host memory directly */
+} rl_xfer_mode;
+
+typedef struct rl_xfer_opts {
+  rl_xfer_mode mode;
+  uint64_t chunk_bytes;  /* staged: bytes of source per chunk (0 = 4 MiB) */
+  uint32_t n_slots;      /* staged: staging slots in flight (0 = 3, max 8) */
+} rl_xfer_opts;
+
+/* Convert objects 0..n-1 between a host view and a device view (Sec. VII-A:
+ * copies between memory contexts, with extra arguments controlling the
+ * copy; Sec. VII-B: copy with conversion).  Exactly one side must be on
+ * the host (RL_SPACE_HOST or RL_SPACE_HOST_PINNED).  Results are the same
+ * bytes rl_convert would give.  The call returns once the work is
+ * enqueued; `stream` is ordered with it: work enqueued earlier on `stream`
+ * happens before the transfer, later work after it.  Host buffers must
+ * stay alive until then.  opts may be NULL (RL_XFER_AUTO).
+ * Zero-copy needs pinned host memory.  Errors as rl_convert. */
+rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n,
+                      void* stream, const rl_xfer_opts* opts);
+
+/* Wait for `stream`, then return (and clear) the device status word of the
+ * current device: RL_EOVERFLOW, RL_ECAPACITY or RL_EBOUNDS (in that order
+ * of precedence) if any conversion since the last rl_sync on this device
+ * found one, else RL_OK; RL_EHIP if the wait failed. */
+rl_status rl_sync(void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* rl_last_error(void);
+
+/* ------------------------------------------------------------------ batches */
+
+typedef struct rl_batch rl_batch;
+
+typedef struct rl_batch_opts {
+  int autotune;          /* 1: time candidate tile shapes (and block widths
+                            of destinations whose width is 0) and keep the
+                            fastest; 0: use the tuning cache or defaults */
+  const char* tune_cache;/* JSON file of tuned choices; NULL: $RL_TUNE_CACHE
+                            or no cache */
+} rl_batch_opts;
+
+/* A batch converts many collections with one launch of a captured HIP graph
+ * whose kernels walk a device-resident table of all items.  Items are added
+ * with the same arguments as rl_convert and must be device views.  An
+ * AoSoA destination layout whose block width is 0 lets the batch choose the
+ * width ("auto"); the chosen width is readable with rl_batch_item_width. */
+rl_status rl_batch_create(const rl_batch_opts* opts, rl_batch** out);
+rl_status rl_batch_add(rl_batch* batch, const rl_view* src, const rl_view* dst,
+                       uint64_t n);
+/* Plan every item, tune if asked, upload the table, capture the graph on
+   `stream`.  Items cannot be added afterwards. */
+rl_status rl_batch_finalize(rl_batch* batch, void* stream);
+rl_status rl_batch_launch(rl_batch* batch, void* stream);
+/* Run the same items one rl_convert call at a time (the launch loop the
+   batch replaces), for comparison. */
+rl_status rl_batch_launch_loop(rl_batch* batch, void* stream);
+rl_status rl_batch_item_width(const rl_batch* batch, uint32_t item,
+                              uint32_t* block_width);
+/* Tile shape chosen for the batch: objects per tile, threads per block,
+   persistent blocks. */
+rl_status rl_batch_shape(const rl_batch* batch, uint32_t* tile_objects,
+                         uint32_t* block_threads, uint32_t* grid_blocks);
+void rl_batch_destroy(rl_batch* batch);
+
+/* ------------------------------------------------------------------ serving */
+
+typedef struct rl_server rl_server;
+
+typedef struct rl_server_opts {
+  uint64_t budget_bytes;   /* device memory for resident results */
+  uint32_t max_in_flight;  /* events converting at once (slots) */
+  uint32_t n_streams;      /* streams the events are spread over */
+} rl_server_opts;
+
+/* One collection of an event: a pinned host source and the device layout
+   its result is to have. */
+typedef struct rl_event_item {
+  rl_view src;
+  const rl_layout* dst_layout;
+  uint64_t n;
+} rl_event_item;
+
+typedef struct rl_event {
+  const rl_event_item* items;
+  uint32_t n_items;
+} rl_event;
+
+typedef struct rl_event_result {
+  uint32_t n_items;
+  uint64_t latency_ns;                /* submit -> last conversion done */
+  uint64_t bytes;                     /* device bytes held */
+  void* const* const* buffers;        /* per item: the device buffers */
+  const uint64_t* member_capacity;    /* per item and group, flattened */
+  rl_status status;                   /* device status of this event */
+} rl_event_result;
+
+typedef struct rl_server_stats {
+  uint64_t completed;
+  uint64_t submitted;
+  double p50_ms, p99_ms, max_ms;
+  double events_per_s;                /* completed / (last done - first submit) */
+  uint64_t peak_bytes;                /* largest resident + in-flight bytes */
+  uint64_t h2d_bytes;
+} rl_server_stats;
+
+/* A serving loop: events are admitted in arrival order while their result
+ * bytes fit the budget and a slot is free; admitted events convert
+ * concurrently on the server's streams; results stay resident until
+ * released.  The caller keeps each event's host sources alive until its
+ * wait returns. */
+rl_status rl_server_create(const rl_server_opts* opts, rl_server** out);
+/* Errors: RL_EBUDGET (the event alone exceeds the budget), RL_EINVAL. */
+rl_status rl_server_submit(rl_server* server, const rl_event* event,
+                           uint64_t* ticket);
+/* Block until the event is done (timeout_ms < 0: forever); RL_EBUSY on
+   timeout. */
+rl_status rl_server_wait(rl_server* server, uint64_t ticket, int64_t timeout_ms,
+                         rl_event_result* result);
+rl_status rl_server_release(rl_server* server, uint64_t ticket);
+rl_status rl_server_stats_get(rl_server* server, rl_server_stats* stats);
+void rl_server_destroy(rl_server* server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RELAYOUT_H */

@@ -1,0 +1,283 @@
+"""Python binding of librelayout (the C ABI in include/relayout.h).
+
+Argument marshalling only: every step of a conversion runs in the library's
+HIP kernels.  The binding loads ``librelayout.so`` from this package's
+directory and raises if it is missing; there is no fallback.
+
+Low-level names mirror the C ABI (``rl_schema_create``, ``rl_convert``, ...);
+the small helper classes below build their arguments from a
+``workloads.SchemaDecl`` and from device/host tensors (torch is only used as
+a memory and stream provider).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librelayout.so")
+
+RL_OK, RL_EINVAL, RL_EALIGN, RL_EOVERLAP, RL_ECAPACITY, RL_EOVERFLOW = 0, 1, 2, 3, 4, 5
+RL_ENOMEM, RL_EBUDGET, RL_EUNSUPPORTED, RL_EHIP, RL_EBUSY, RL_EBOUNDS = 6, 7, 8, 9, 10, 11
+STATUS_NAMES = {0: "RL_OK", 1: "RL_EINVAL", 2: "RL_EALIGN", 3: "RL_EOVERLAP", 4: "RL_ECAPACITY",
+                5: "RL_EOVERFLOW", 6: "RL_ENOMEM", 7: "RL_EBUDGET", 8: "RL_EUNSUPPORTED",
+                9: "RL_EHIP", 10: "RL_EBUSY", 11: "RL_EBOUNDS"}
+TYPES = ["u8", "i8", "u16", "i16", "u32", "i32", "u64", "i64", "f32", "f64"]
+KINDS = {"aos": 0, "soa": 1, "aosoa": 2}
+SPACES = {"device": 0, "host": 1, "pinned": 2}
+XFER_MODES = {"auto": 0, "staged": 1, "zero_copy": 2}
+
+
+class RelayoutError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {rl_last_error()}")
+
+
+# ------------------------------------------------------------------ C structs
+
+class rl_field(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("type", ctypes.c_int), ("extent", ctypes.c_uint32),
+                ("group", ctypes.c_int32), ("subgroup", ctypes.c_int32)]
+
+
+class rl_jagged(ctypes.Structure):
+    _fields_ = [("offset_type", ctypes.c_int)]
+
+
+class rl_layout_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("space", ctypes.c_int), ("block_width", ctypes.c_uint32),
+                ("record_stride", ctypes.c_uint64),
+                ("slot_offsets", ctypes.POINTER(ctypes.c_uint64)),
+                ("storage_type", ctypes.POINTER(ctypes.c_int))]
+
+
+class rl_view(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("member_capacity", ctypes.POINTER(ctypes.c_uint64)),
+                ("buffers", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class rl_xfer_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("chunk_bytes", ctypes.c_uint64),
+                ("n_slots", ctypes.c_uint32)]
+
+
+class rl_batch_opts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+
+
+class rl_server_opts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_in_flight", ctypes.c_uint32),
+                ("n_streams", ctypes.c_uint32)]
+
+
+class rl_event_item(ctypes.Structure):
+    _fields_ = [("src", rl_view), ("dst_layout", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class rl_event(ctypes.Structure):
+    _fields_ = [("items", ctypes.POINTER(rl_event_item)), ("n_items", ctypes.c_uint32)]
+
+
+class rl_event_result(ctypes.Structure):
+    _fields_ = [("n_items", ctypes.c_uint32), ("latency_ns", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64),
+                ("buffers", ctypes.POINTER(ctypes.POINTER(ctypes.c_void_p))),
+                ("member_capacity", ctypes.POINTER(ctypes.c_uint64)),
+                ("status", ctypes.c_int)]
+
+
+class rl_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("submitted", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("events_per_s", ctypes.c_double),
+                ("peak_bytes", ctypes.c_uint64), ("h2d_bytes", ctypes.c_uint64)]
+
+
+# Every symbol the header declares, with its ctypes signature.
+_VP = ctypes.c_void_p
+_P = ctypes.POINTER
+SIGNATURES = {
+    "rl_schema_create": (ctypes.c_int, [_P(rl_field), ctypes.c_uint32, _P(rl_jagged), ctypes.c_uint32, _P(_VP)]),
+    "rl_schema_destroy": (None, [_VP]),
+    "rl_schema_info": (ctypes.c_int, [_VP, _P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
+    "rl_layout_create": (ctypes.c_int, [_VP, _P(rl_layout_desc), _P(_VP)]),
+    "rl_layout_destroy": (None, [_VP]),
+    "rl_layout_buffers": (ctypes.c_int, [_VP, ctypes.c_uint64, _P(ctypes.c_uint64), _P(ctypes.c_uint32), _P(ctypes.c_uint64)]),
+    "rl_layout_info": (ctypes.c_int, [_VP, _P(ctypes.c_uint64), _P(ctypes.c_uint64), _P(ctypes.c_uint32)]),
+    "rl_convert": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP]),
+    "rl_offsets": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint32, ctypes.c_uint64, _P(ctypes.c_uint64), _VP]),
+    "rl_transfer": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
+    "rl_sync": (ctypes.c_int, [_VP]),
+    "rl_last_error": (ctypes.c_char_p, []),
+    "rl_batch_create": (ctypes.c_int, [_P(rl_batch_opts), _P(_VP)]),
+    "rl_batch_add": (ctypes.c_int, [_VP, _P(rl_view), _P(rl_view), ctypes.c_uint64]),
+    "rl_batch_finalize": (ctypes.c_int, [_VP, _VP]),
+    "rl_batch_launch": (ctypes.c_int, [_VP, _VP]),
+    "rl_batch_launch_loop": (ctypes.c_int, [_VP, _VP]),
+    "rl_batch_item_width": (ctypes.c_int, [_VP, ctypes.c_uint32, _P(ctypes.c_uint32)]),
+    "rl_batch_shape": (ctypes.c_int, [_VP, _P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
+    "rl_batch_destroy": (None, [_VP]),
+    "rl_server_create": (ctypes.c_int, [_P(rl_server_opts), _P(_VP)]),
+    "rl_server_submit": (ctypes.c_int, [_VP, _P(rl_event), _P(ctypes.c_uint64)]),
+    "rl_server_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int64, _P(rl_event_result)]),
+    "rl_server_release": (ctypes.c_int, [_VP, ctypes.c_uint64]),
+    "rl_server_stats_get": (ctypes.c_int, [_VP, _P(rl_server_stats)]),
+    "rl_server_destroy": (None, [_VP]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"librelayout.so is not built ({LIB_PATH}); "
+                               "run `python -m paper_2511_04853_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def rl_last_error():
+    return (lib().rl_last_error() or b"").decode()
+
+
+def check(status, where):
+    if status != RL_OK:
+        raise RelayoutError(status, where)
+    return status
+
+
+def __getattr__(name):
+    # rl_* names resolve to the library's functions
+    if name.startswith("rl_") and name in SIGNATURES:
+        return getattr(lib(), name)
+    raise AttributeError(name)
+
+
+# ------------------------------------------------------------------ helpers
+
+class Schema:
+    """An rl_schema registered from a workloads.SchemaDecl."""
+
+    def __init__(self, decl):
+        self.decl = decl
+        fields = (rl_field * max(1, len(decl.fields)))()
+        self._names = []
+        for k, f in enumerate(decl.fields):
+            nm = f.name.encode()
+            self._names.append(nm)
+            fields[k] = rl_field(nm, TYPES.index(f.type), f.extent, f.group, f.subgroup)
+        groups = (rl_jagged * max(1, len(decl.offset_types)))()
+        for g, t in enumerate(decl.offset_types):
+            groups[g] = rl_jagged(TYPES.index(t))
+        h = ctypes.c_void_p()
+        check(lib().rl_schema_create(fields, len(decl.fields), groups, len(decl.offset_types),
+                                     ctypes.byref(h)), "rl_schema_create")
+        self.handle = h
+        nl, ng, ns = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        check(lib().rl_schema_info(h, ctypes.byref(nl), ctypes.byref(ng), ctypes.byref(ns)), "rl_schema_info")
+        self.n_leaves, self.n_groups, self.n_slots = nl.value, ng.value, ns.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rl_schema_destroy(self.handle)
+            self.handle = None
+
+
+class Layout:
+    """An rl_layout of a Schema."""
+
+    def __init__(self, schema: Schema, kind: str, space: str = "device", width: int = 0,
+                 storage=None, slot_offsets=None, stride: int = 0):
+        self.schema, self.kind, self.space, self.width = schema, kind, space, width
+        d = rl_layout_desc()
+        d.kind = KINDS[kind]
+        d.space = SPACES[space]
+        d.block_width = width
+        d.record_stride = stride
+        self._keep = []
+        if slot_offsets is not None:
+            arr = (ctypes.c_uint64 * len(slot_offsets))(*slot_offsets)
+            self._keep.append(arr)
+            d.slot_offsets = arr
+        if storage is not None:
+            arr = (ctypes.c_int * len(storage))(*[TYPES.index(t) for t in storage])
+            self._keep.append(arr)
+            d.storage_type = arr
+        h = ctypes.c_void_p()
+        check(lib().rl_layout_create(schema.handle, ctypes.byref(d), ctypes.byref(h)), "rl_layout_create")
+        self.handle = h
+        nb = ctypes.c_uint32()
+        stride_out = ctypes.c_uint64()
+        offs = (ctypes.c_uint64 * max(1, schema.n_slots))()
+        check(lib().rl_layout_info(h, offs, ctypes.byref(stride_out), ctypes.byref(nb)), "rl_layout_info")
+        self.max_buffers = nb.value
+        self.stride = stride_out.value
+        self.slot_offsets = list(offs)[:schema.n_slots] if kind == "aos" else None
+
+    def buffer_bytes(self, n, members=()):
+        nb = ctypes.c_uint32()
+        out = (ctypes.c_uint64 * max(1, self.max_buffers))()
+        mem = (ctypes.c_uint64 * max(1, len(members)))(*members)
+        check(lib().rl_layout_buffers(self.handle, n, mem, ctypes.byref(nb), out), "rl_layout_buffers")
+        return list(out)[:nb.value]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rl_layout_destroy(self.handle)
+            self.handle = None
+
+
+class View:
+    """An rl_view over raw buffers (torch tensors, numpy arrays or ints)."""
+
+    def __init__(self, layout: Layout, capacity: int, buffers, member_capacity=()):
+        self.layout = layout
+        self.tensors = list(buffers)      # keeps the memory alive
+        ptrs = [_ptr(b) for b in buffers]
+        self._bufs = (ctypes.c_void_p * max(1, len(ptrs)))(*ptrs)
+        self._mcap = (ctypes.c_uint64 * max(1, len(member_capacity)))(*member_capacity)
+        self.c = rl_view(layout.handle, capacity,
+                         self._mcap if len(member_capacity) else None, self._bufs)
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def _ptr(b):
+    if b is None:
+        return None
+    if isinstance(b, int):
+        return b
+    if hasattr(b, "data_ptr"):
+        return b.data_ptr()
+    return b.ctypes.data
+
+
+def stream_ptr(stream=None):
+    """hipStream_t of a torch stream (default: the current stream)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def convert(src: View, dst: View, n: int, stream=None):
+    check(lib().rl_convert(src.ref(), dst.ref(), n, stream_ptr(stream)), "rl_convert")
+
+
+def sync(stream=None):
+    return lib().rl_sync(stream_ptr(stream))
+
+
+def transfer(src: View, dst: View, n: int, stream=None, mode="auto", chunk_bytes=0, n_slots=0):
+    o = rl_xfer_opts(XFER_MODES[mode], chunk_bytes, n_slots)
+    check(lib().rl_transfer(src.ref(), dst.ref(), n, stream_ptr(stream), ctypes.byref(o)), "rl_transfer")

@@ -1,0 +1,516 @@
+// Schema and layout descriptors, validation, conversion planning and the
+// synchronous entry points of librelayout.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "plan.h"
+#include "rl_internal.h"
+
+namespace rl {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+rl_status fail(rl_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+rl_status hip_fail(hipError_t e, const char* what) {
+  return fail(RL_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ device state
+
+static std::mutex g_dev_mu;
+static uint32_t* g_status[64] = {};
+static uint32_t* g_status_host[64] = {};
+
+uint32_t* device_status(int device) {
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if (!g_status[device]) {
+    uint32_t* p = nullptr;
+    if (hipMalloc(&p, 256) != hipSuccess) return nullptr;
+    if (hipMemset(p, 0, 256) != hipSuccess) return nullptr;
+    if (hipHostMalloc(&g_status_host[device], 256, hipHostMallocDefault) != hipSuccess) return nullptr;
+    g_status[device] = p;
+  }
+  return g_status[device];
+}
+
+static uint32_t* device_status_host(int device) { return g_status_host[device]; }
+
+uint32_t type_size(rl_type t) {
+  switch (t) {
+    case RL_U8: case RL_I8: return 1;
+    case RL_U16: case RL_I16: return 2;
+    case RL_U32: case RL_I32: case RL_F32: return 4;
+    default: return 8;
+  }
+}
+
+static bool valid_type(int t) { return t >= RL_U8 && t <= RL_F64; }
+
+static uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace rl
+
+using namespace rl;
+
+// ------------------------------------------------------------------ schema
+
+extern "C" rl_status rl_schema_create(const rl_field* fields, uint32_t n_fields,
+                                      const rl_jagged* groups, uint32_t n_groups,
+                                      rl_schema** out) {
+  if (!out) return fail(RL_EINVAL, "rl_schema_create: out is NULL");
+  *out = nullptr;
+  if (n_fields && !fields) return fail(RL_EINVAL, "rl_schema_create: fields is NULL");
+  if (n_groups && !groups) return fail(RL_EINVAL, "rl_schema_create: groups is NULL");
+  if (n_groups > (uint32_t)kMaxGroups) return fail(RL_EINVAL, "at most %d jagged groups", kMaxGroups);
+  auto* s = new rl_schema();
+  std::vector<int> group_seen(n_groups, 0);
+  int32_t prev_sub = -1;
+  std::vector<int> sub_closed;
+  for (uint32_t k = 0; k < n_fields; ++k) {
+    const rl_field& f = fields[k];
+    if (!valid_type(f.type)) { delete s; return fail(RL_EINVAL, "field %u: bad type %d", k, (int)f.type); }
+    if (f.extent < 1 || f.extent > (uint32_t)kMaxExtent) {
+      delete s; return fail(RL_EINVAL, "field %u: extent %u outside 1..%d", k, f.extent, kMaxExtent);
+    }
+    if (f.group < -1 || f.group >= (int32_t)n_groups) {
+      delete s; return fail(RL_EINVAL, "field %u: group %d out of range", k, f.group);
+    }
+    if (f.subgroup < -1) { delete s; return fail(RL_EINVAL, "field %u: bad subgroup", k); }
+    if (f.group >= 0 && f.subgroup >= 0) {
+      delete s; return fail(RL_EINVAL, "field %u: a member field cannot be in a sub-group", k);
+    }
+    // sub-groups label consecutive runs of per-object fields
+    if (f.group < 0) {
+      if (f.subgroup >= 0 && f.subgroup != prev_sub) {
+        if (std::find(sub_closed.begin(), sub_closed.end(), f.subgroup) != sub_closed.end()) {
+          delete s; return fail(RL_EINVAL, "field %u: sub-group %d is not consecutive", k, f.subgroup);
+        }
+      }
+      if (prev_sub >= 0 && f.subgroup != prev_sub) sub_closed.push_back(prev_sub);
+      prev_sub = f.subgroup;
+    }
+    s->fields.push_back(f);
+    s->names.push_back(f.name ? f.name : "");
+  }
+  for (uint32_t g = 0; g < n_groups; ++g) {
+    const rl_type t = groups[g].offset_type;
+    if (t != RL_U32 && t != RL_I32 && t != RL_U64) {
+      delete s; return fail(RL_EINVAL, "group %u: offset type must be U32, I32 or U64", g);
+    }
+    s->offset_types.push_back(t);
+  }
+  s->members.resize(n_groups);
+  for (uint32_t k = 0; k < n_fields; ++k) {
+    const rl_field& f = fields[k];
+    if (f.group < 0) {
+      for (uint32_t e = 0; e < f.extent; ++e) {
+        s->slots.push_back({0, (int)s->leaves.size(), f.subgroup});
+        s->leaves.push_back({f.type, type_size(f.type), (int32_t)k, e, f.subgroup});
+      }
+    } else {
+      if (!group_seen[f.group]) {
+        group_seen[f.group] = 1;
+        s->slots.push_back({1, f.group, -1});
+        s->slots.push_back({2, f.group, -1});
+      }
+      for (uint32_t e = 0; e < f.extent; ++e)
+        s->members[f.group].push_back({f.type, type_size(f.type), (int32_t)k, e, -1});
+    }
+  }
+  for (uint32_t g = 0; g < n_groups; ++g) {
+    if (!group_seen[g]) { delete s; return fail(RL_EINVAL, "group %u has no member field", g); }
+    if (s->members[g].size() > (size_t)kMaxMembers) {
+      delete s; return fail(RL_EINVAL, "group %u: at most %d member leaves", g, kMaxMembers);
+    }
+  }
+  if (s->leaves.size() + 2 * n_groups > (size_t)kMaxLeaves) {
+    delete s; return fail(RL_EINVAL, "at most %d per-object leaves (plus 2 per group)", kMaxLeaves);
+  }
+  *out = s;
+  return RL_OK;
+}
+
+extern "C" void rl_schema_destroy(rl_schema* schema) { delete schema; }
+
+extern "C" rl_status rl_schema_info(const rl_schema* s, uint32_t* n_leaves, uint32_t* n_groups,
+                                    uint32_t* n_slots) {
+  if (!s) return fail(RL_EINVAL, "schema is NULL");
+  if (n_leaves) *n_leaves = (uint32_t)s->leaves.size();
+  if (n_groups) *n_groups = (uint32_t)s->offset_types.size();
+  if (n_slots) *n_slots = (uint32_t)s->slots.size();
+  return RL_OK;
+}
+
+// ------------------------------------------------------------------ layouts
+
+// C natural alignment of the record slots (sub-groups as nested structs).
+static void natural_record(const rl_schema* s, const std::vector<rl_type>& storage,
+                           std::vector<uint64_t>& offs, uint64_t& stride) {
+  offs.assign(s->slots.size(), 0);
+  auto slot_size = [&](const rl_schema::Slot& sl) -> uint64_t {
+    if (sl.kind == 0) return type_size(storage[sl.index]);
+    return sl.kind == 1 ? 8 : 4;
+  };
+  uint64_t pos = 0, max_align = 1;
+  size_t k = 0;
+  while (k < s->slots.size()) {
+    const int32_t sub = s->slots[k].subgroup;
+    if (sub < 0) {
+      const uint64_t sz = slot_size(s->slots[k]);
+      pos = round_up(pos, sz);
+      offs[k] = pos;
+      pos += sz;
+      max_align = std::max(max_align, sz);
+      ++k;
+      continue;
+    }
+    // nested struct: the run of slots with this sub-group id
+    size_t e = k;
+    uint64_t inner = 0, ia = 1;
+    std::vector<uint64_t> local;
+    while (e < s->slots.size() && s->slots[e].subgroup == sub) {
+      const uint64_t sz = slot_size(s->slots[e]);
+      inner = round_up(inner, sz);
+      local.push_back(inner);
+      inner += sz;
+      ia = std::max(ia, sz);
+      ++e;
+    }
+    inner = round_up(inner, ia);
+    pos = round_up(pos, ia);
+    for (size_t j = k; j < e; ++j) offs[j] = pos + local[j - k];
+    pos += inner;
+    max_align = std::max(max_align, ia);
+    k = e;
+  }
+  stride = pos ? round_up(pos, max_align) : 0;
+}
+
+extern "C" rl_status rl_layout_create(const rl_schema* schema, const rl_layout_desc* desc,
+                                      rl_layout** out) {
+  if (!schema || !desc || !out) return fail(RL_EINVAL, "rl_layout_create: NULL argument");
+  *out = nullptr;
+  if (desc->kind < RL_AOS || desc->kind > RL_AOSOA) return fail(RL_EINVAL, "bad layout kind %d", (int)desc->kind);
+  if (desc->space < RL_SPACE_DEVICE || desc->space > RL_SPACE_HOST_PINNED)
+    return fail(RL_EINVAL, "bad memory space %d", (int)desc->space);
+  auto* L = new rl_layout();
+  L->schema = schema;
+  L->kind = desc->kind;
+  L->space = desc->space;
+  L->width = desc->block_width;
+  L->stride = 0;
+  L->record_align = 1;
+  L->has_gaps = false;
+  const size_t nl = schema->leaves.size();
+  for (size_t c = 0; c < nl; ++c) {
+    const rl_type st = desc->storage_type ? desc->storage_type[c] : schema->leaves[c].type;
+    const rl_type t = schema->leaves[c].type;
+    if (!valid_type(st)) { delete L; return fail(RL_EINVAL, "leaf %zu: bad storage type", c); }
+    if (st != t && !((t == RL_F64 && st == RL_F32) || (t == RL_F32 && st == RL_F64))) {
+      delete L; return fail(RL_EINVAL, "leaf %zu: storage type may only change f64<->f32", c);
+    }
+    L->storage.push_back(st);
+  }
+  uint32_t acc = 0;
+  for (size_t c = 0; c < nl; ++c) {
+    L->prefix.push_back(acc);
+    acc += type_size(L->storage[c]);
+  }
+  L->obj_bytes = acc;
+  if (acc > (uint32_t)kMaxObjBytes) { delete L; return fail(RL_EINVAL, "more than %d bytes per object", kMaxObjBytes); }
+  if (L->kind == RL_AOSOA) {
+    if (L->width < 1 || L->width >= 65536) { delete L; return fail(RL_EINVAL, "AoSoA block width must be 1..65535"); }
+  }
+  if (L->kind == RL_AOS) {
+    std::vector<uint64_t> nat;
+    uint64_t nat_stride;
+    natural_record(schema, L->storage, nat, nat_stride);
+    if (desc->slot_offsets) {
+      L->slot_offsets.assign(desc->slot_offsets, desc->slot_offsets + schema->slots.size());
+      L->stride = desc->record_stride;
+    } else {
+      L->slot_offsets = nat;
+      L->stride = desc->record_stride ? desc->record_stride : nat_stride;
+    }
+    if (L->stride >= (1ull << 31)) { delete L; return fail(RL_EINVAL, "record stride too large"); }
+    if (!schema->members.empty() && L->stride % 8)
+      { delete L; return fail(RL_EINVAL, "records with jagged groups need a stride that is a multiple of 8"); }
+    // slots inside the stride, not overlapping
+    std::vector<std::pair<uint64_t, uint64_t>> spans;
+    uint64_t covered = 0;
+    for (size_t k = 0; k < schema->slots.size(); ++k) {
+      const auto& sl = schema->slots[k];
+      const uint64_t sz = sl.kind == 0 ? type_size(L->storage[sl.index]) : (sl.kind == 1 ? 8 : 4);
+      const uint64_t o = L->slot_offsets[k];
+      if (o + sz > L->stride) { delete L; return fail(RL_EINVAL, "slot %zu does not fit the record stride", k); }
+      spans.push_back({o, o + sz});
+      covered += sz;
+      if (o % sz == 0) L->record_align = std::max<uint32_t>(L->record_align, (uint32_t)sz);
+      if (sl.kind == 1 && o % 8) { delete L; return fail(RL_EINVAL, "group pointer slot must be 8-byte aligned"); }
+      if (sl.kind == 2 && o % 4) { delete L; return fail(RL_EINVAL, "group count slot must be 4-byte aligned"); }
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+      if (spans[k].first < spans[k - 1].second) { delete L; return fail(RL_EINVAL, "record slots overlap"); }
+    L->has_gaps = covered < L->stride;
+    L->leaf_offset.assign(nl, 0);
+    L->ptr_off.assign(schema->offset_types.size(), 0);
+    L->len_off.assign(schema->offset_types.size(), 0);
+    for (size_t k = 0; k < schema->slots.size(); ++k) {
+      const auto& sl = schema->slots[k];
+      if (sl.kind == 0) L->leaf_offset[sl.index] = (uint32_t)L->slot_offsets[k];
+      else if (sl.kind == 1) L->ptr_off[sl.index] = (uint32_t)L->slot_offsets[k];
+      else L->len_off[sl.index] = (uint32_t)L->slot_offsets[k];
+    }
+    for (size_t g = 0; g < schema->members.size(); ++g) {
+      uint32_t pos = 0, ma = 1;
+      std::vector<uint32_t> mo;
+      for (const auto& m : schema->members[g]) {
+        pos = (uint32_t)round_up(pos, m.size);
+        mo.push_back(pos);
+        pos += m.size;
+        ma = std::max(ma, m.size);
+      }
+      L->moff.push_back(mo);
+      L->mstride.push_back((uint32_t)round_up(pos, ma));
+      L->malign.push_back(ma);
+    }
+  }
+  *out = L;
+  return RL_OK;
+}
+
+extern "C" void rl_layout_destroy(rl_layout* layout) { delete layout; }
+
+namespace rl {
+
+uint32_t layout_n_buffers(const rl_layout* L) {
+  const rl_schema* s = L->schema;
+  uint32_t n = 0;
+  if (L->kind == RL_AOS) return 1 + (uint32_t)s->members.size();
+  n = L->kind == RL_SOA ? (uint32_t)s->leaves.size() : 1;
+  for (const auto& m : s->members) n += 1 + (uint32_t)m.size();
+  return n;
+}
+
+void layout_buffer_bytes(const rl_layout* L, uint64_t n, const uint64_t* members, uint64_t* bytes) {
+  const rl_schema* s = L->schema;
+  uint32_t k = 0;
+  if (L->kind == RL_AOS) {
+    bytes[k++] = n * L->stride;
+    for (size_t g = 0; g < s->members.size(); ++g) bytes[k++] = (members ? members[g] : 0) * L->mstride[g];
+    return;
+  }
+  if (L->kind == RL_SOA) {
+    for (size_t c = 0; c < s->leaves.size(); ++c) bytes[k++] = n * type_size(L->storage[c]);
+  } else {
+    bytes[k++] = (n + L->width - 1) / L->width * L->width * (uint64_t)L->obj_bytes;
+  }
+  for (size_t g = 0; g < s->members.size(); ++g) {
+    bytes[k++] = (n + 1) * type_size(s->offset_types[g]);
+    for (const auto& m : s->members[g]) bytes[k++] = (members ? members[g] : 0) * m.size;
+  }
+}
+
+// Alignment each buffer needs.
+void layout_buffer_align(const rl_layout* L, uint64_t* align) {
+  const rl_schema* s = L->schema;
+  uint32_t k = 0;
+  if (L->kind == RL_AOS) {
+    align[k++] = L->record_align;
+    for (size_t g = 0; g < s->members.size(); ++g) align[k++] = L->malign[g];
+    return;
+  }
+  if (L->kind == RL_SOA) {
+    for (size_t c = 0; c < s->leaves.size(); ++c) align[k++] = type_size(L->storage[c]);
+  } else {
+    uint64_t a = 1;
+    for (auto t : L->storage) a = std::max<uint64_t>(a, type_size(t));
+    align[k++] = a;
+  }
+  for (size_t g = 0; g < s->members.size(); ++g) {
+    align[k++] = type_size(s->offset_types[g]);
+    for (const auto& m : s->members[g]) align[k++] = m.size;
+  }
+}
+
+// First buffer index of group g's storage.
+uint32_t group_buffer(const rl_layout* L, uint32_t g) {
+  const rl_schema* s = L->schema;
+  if (L->kind == RL_AOS) return 1 + g;
+  uint32_t k = L->kind == RL_SOA ? (uint32_t)s->leaves.size() : 1;
+  for (uint32_t h = 0; h < g; ++h) k += 1 + (uint32_t)s->members[h].size();
+  return k;
+}
+
+}  // namespace rl
+
+extern "C" rl_status rl_layout_buffers(const rl_layout* L, uint64_t n, const uint64_t* n_members,
+                                       uint32_t* n_buffers, uint64_t* bytes) {
+  if (!L || !n_buffers) return fail(RL_EINVAL, "rl_layout_buffers: NULL argument");
+  if (!L->schema->members.empty() && !n_members && bytes)
+    return fail(RL_EINVAL, "rl_layout_buffers: n_members needed for jagged groups");
+  *n_buffers = layout_n_buffers(L);
+  if (bytes) layout_buffer_bytes(L, n, n_members, bytes);
+  return RL_OK;
+}
+
+extern "C" rl_status rl_layout_info(const rl_layout* L, uint64_t* slot_offsets, uint64_t* stride,
+                                    uint32_t* max_buffers) {
+  if (!L) return fail(RL_EINVAL, "layout is NULL");
+  if (slot_offsets && L->kind == RL_AOS)
+    std::copy(L->slot_offsets.begin(), L->slot_offsets.end(), slot_offsets);
+  if (stride) *stride = L->stride;
+  if (max_buffers) *max_buffers = layout_n_buffers(L);
+  return RL_OK;
+}
+
+// ------------------------------------------------------------------ validation
+
+namespace rl {
+
+rl_status validate_view(const rl_view* v, uint64_t n, const char* which, std::vector<Range>* ranges,
+                        bool want_device) {
+  if (!v || !v->layout) return fail(RL_EINVAL, "%s: view or layout is NULL", which);
+  const rl_layout* L = v->layout;
+  const size_t ng = L->schema->members.size();
+  if (ng && !v->member_capacity) return fail(RL_EINVAL, "%s: member_capacity needed", which);
+  if (n > v->capacity) return fail(RL_EINVAL, "%s: n = %llu exceeds capacity %llu", which,
+                                   (unsigned long long)n, (unsigned long long)v->capacity);
+  if (want_device && L->space != RL_SPACE_DEVICE)
+    return fail(RL_EUNSUPPORTED, "%s: expected device memory", which);
+  const uint32_t nb = layout_n_buffers(L);
+  if (nb && !v->buffers) return fail(RL_EINVAL, "%s: buffers is NULL", which);
+  std::vector<uint64_t> bytes(nb), align(nb);
+  layout_buffer_bytes(L, n, v->member_capacity, bytes.data());
+  layout_buffer_align(L, align.data());
+  for (uint32_t b = 0; b < nb; ++b) {
+    const uintptr_t p = (uintptr_t)v->buffers[b];
+    if (bytes[b] == 0) continue;
+    if (!p) return fail(RL_EINVAL, "%s: buffer %u is NULL", which, b);
+    if (p % align[b]) return fail(RL_EALIGN, "%s: buffer %u not aligned to %llu bytes", which, b,
+                                  (unsigned long long)align[b]);
+    if (ranges) ranges->push_back({p, p + bytes[b]});
+  }
+  return RL_OK;
+}
+
+rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>& dst) {
+  for (size_t i = 0; i < dst.size(); ++i) {
+    for (const auto& s : src)
+      if (dst[i].lo < s.hi && s.lo < dst[i].hi) return fail(RL_EOVERLAP, "a destination buffer overlaps a source buffer");
+    for (size_t j = 0; j < i; ++j)
+      if (dst[i].lo < dst[j].hi && dst[j].lo < dst[i].hi) return fail(RL_EOVERLAP, "destination buffers overlap");
+  }
+  return RL_OK;
+}
+
+}  // namespace rl
+
+// ------------------------------------------------------------------ convert
+
+namespace rl {
+// Tile shape override for experiments and the tile-independence tests:
+// RL_TILE_OBJECTS (objects per tile), RL_BLOCK_THREADS, RL_GRID_BLOCKS.
+PlanShape shape_from_env() {
+  PlanShape s;
+  if (const char* v = getenv("RL_TILE_OBJECTS")) s.tile = (uint32_t)strtoul(v, nullptr, 10);
+  if (const char* v = getenv("RL_BLOCK_THREADS")) {
+    const uint32_t t = (uint32_t)strtoul(v, nullptr, 10);
+    if (t >= 64 && t <= 1024 && t % 64 == 0) s.threads = t;
+  }
+  if (const char* v = getenv("RL_GRID_BLOCKS")) s.grid = (uint32_t)strtoul(v, nullptr, 10);
+  return s;
+}
+}  // namespace rl
+
+extern "C" rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t n, void* stream) {
+  std::vector<Range> rs, rd;
+  rl_status st = validate_view(src, n, "src", &rs, true);
+  if (st) return st;
+  st = validate_view(dst, n, "dst", &rd, true);
+  if (st) return st;
+  if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
+  if ((st = check_overlap(rs, rd))) return st;
+  if (!src->layout->schema->members.empty() && src->layout->kind == RL_AOS && dst->layout->kind == RL_AOS)
+    return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
+  if (n == 0) return RL_OK;
+  Plan plan;
+  if ((st = make_plan(*src, *dst, n, shape_from_env(), &plan))) return st;
+  return enqueue_plan(plan, (hipStream_t)stream);
+}
+
+extern "C" rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t group, uint64_t n,
+                                uint64_t* total_host, void* stream) {
+  std::vector<Range> rs, rd;
+  rl_status st = validate_view(src, n, "src", &rs, true);
+  if (st) return st;
+  st = validate_view(dst, n, "dst", &rd, true);
+  if (st) return st;
+  if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
+  if (group >= src->layout->schema->members.size()) return fail(RL_EINVAL, "no jagged group %u", group);
+  if (dst->layout->kind == RL_AOS) return fail(RL_EUNSUPPORTED, "rl_offsets writes an offsets column (SoA/AoSoA dst)");
+  // only the offsets column of dst is written
+  const uint32_t ob = group_buffer(dst->layout, group);
+  std::vector<Range> rd1;
+  for (const auto& r : rd)
+    if (r.lo == (uintptr_t)dst->buffers[ob]) rd1.push_back(r);
+  if ((st = check_overlap(rs, rd1))) return st;
+  Plan plan;
+  if ((st = make_offsets_plan(*src, *dst, group, n, shape_from_env(), &plan))) return st;
+  if ((st = enqueue_plan(plan, (hipStream_t)stream))) return st;
+  if (total_host) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const rl_type ot = src->layout->schema->offset_types[group];
+    uint64_t v = 0;
+    e = hipMemcpy(&v, (const uint8_t*)dst->buffers[ob] + n * type_size(ot), type_size(ot), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    if (ot == RL_I32) v = (uint64_t)(int64_t)(int32_t)(uint32_t)v;
+    *total_host = v;
+  }
+  return RL_OK;
+}
+
+extern "C" rl_status rl_sync(void* stream) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  uint32_t* ds = device_status(dev);
+  if (!ds) return fail(RL_ENOMEM, "device status word");
+  uint32_t* hs = device_status_host(dev);
+  if ((e = hipMemcpyAsync(hs, ds, 4, hipMemcpyDeviceToHost, (hipStream_t)stream)) != hipSuccess)
+    return hip_fail(e, "hipMemcpyAsync(status)");
+  if ((e = launch_clear_status(ds, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "clear status");
+  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  const uint32_t f = *hs;
+  if (f & ST_FLAG_OVERFLOW) return fail(RL_EOVERFLOW, "a member total does not fit the offset type");
+  if (f & ST_FLAG_CAPACITY) return fail(RL_ECAPACITY, "members exceed the destination capacity");
+  if (f & ST_FLAG_BOUNDS) return fail(RL_EBOUNDS, "a source member block lies outside its storage or is misaligned");
+  return RL_OK;
+}
+
+extern "C" const char* rl_last_error(void) { return g_err; }

@@ -1,0 +1,512 @@
+// HIP kernels of librelayout for gfx950 (CDNA4, wave64).
+//
+// Dense conversion (every per-object leaf value moves from the source
+// address map to the destination address map, Sec. VII-B default transfer):
+// a work-group takes a tile of T objects, copies the source bytes of the
+// tile into an LDS image with 16-byte global loads, moves every
+// (object, leaf) value from the source image to the destination image
+// inside LDS, then writes the destination image out with 16-byte global
+// stores.  Both global sides are contiguous runs per tile (AoS: one run of
+// T records; AoSoA: T/W whole blocks; SoA: one run per column), so both
+// reads and writes coalesce whatever the field widths.
+//
+// Jagged groups (Sec. VI, prefix sum of member counts): the counts of an AoS
+// record source are scanned per tile inside the dense kernel (wave prefix
+// sums + an LDS pass over waves), a one-work-group pass scans the tile
+// totals, and a third pass adds tile prefixes and gathers each tile's
+// members from the member pool.
+#include <hip/hip_runtime.h>
+
+#include "rl_internal.h"
+
+namespace rl {
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint64_t load_off(const uint8_t* p, uint32_t type, uint64_t i) {
+  if (type == RL_U64) return reinterpret_cast<const uint64_t*>(p)[i];
+  if (type == RL_I32) return (uint64_t)(int64_t)reinterpret_cast<const int32_t*>(p)[i];
+  return reinterpret_cast<const uint32_t*>(p)[i];
+}
+
+__device__ __forceinline__ void store_off(uint8_t* p, uint32_t type, uint64_t i, uint64_t v) {
+  if (type == RL_U64) reinterpret_cast<uint64_t*>(p)[i] = v;
+  else if (type == RL_I32) reinterpret_cast<int32_t*>(p)[i] = (int32_t)v;
+  else reinterpret_cast<uint32_t*>(p)[i] = (uint32_t)v;
+}
+
+__device__ __forceinline__ uint64_t off_limit(uint32_t type) {
+  if (type == RL_U64) return ~0ull;
+  if (type == RL_I32) return 0x7fffffffull;
+  return 0xffffffffull;
+}
+
+__device__ __forceinline__ void flag(uint32_t* status, uint32_t f) {
+  if (status) atomicOr(status, f);
+}
+
+// Copy `bytes` from global memory to LDS (the LDS side is 16-byte aligned).
+// All threads of the work-group take part.
+__device__ __forceinline__ void g2l(uint8_t* lds, const uint8_t* g, uint32_t bytes,
+                                    uint32_t tid, uint32_t nt) {
+  if ((reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+    const uint32_t nv = bytes >> 4;
+    const v4u* gv = reinterpret_cast<const v4u*>(g);
+    v4u* lv = reinterpret_cast<v4u*>(lds);
+    for (uint32_t v = tid; v < nv; v += nt) lv[v] = gv[v];
+    for (uint32_t b = (nv << 4) + tid; b < bytes; b += nt) lds[b] = g[b];
+  } else if ((reinterpret_cast<uintptr_t>(g) & 3) == 0) {
+    const uint32_t nw = bytes >> 2;
+    const uint32_t* gw = reinterpret_cast<const uint32_t*>(g);
+    uint32_t* lw = reinterpret_cast<uint32_t*>(lds);
+    for (uint32_t v = tid; v < nw; v += nt) lw[v] = gw[v];
+    for (uint32_t b = (nw << 2) + tid; b < bytes; b += nt) lds[b] = g[b];
+  } else {
+    for (uint32_t b = tid; b < bytes; b += nt) lds[b] = g[b];
+  }
+}
+
+// Copy `bytes` from LDS (16-byte aligned) to global memory.
+__device__ __forceinline__ void l2g(uint8_t* g, const uint8_t* lds, uint32_t bytes,
+                                    uint32_t tid, uint32_t nt) {
+  if ((reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+    const uint32_t nv = bytes >> 4;
+    v4u* gv = reinterpret_cast<v4u*>(g);
+    const v4u* lv = reinterpret_cast<const v4u*>(lds);
+    for (uint32_t v = tid; v < nv; v += nt) gv[v] = lv[v];
+    for (uint32_t b = (nv << 4) + tid; b < bytes; b += nt) g[b] = lds[b];
+  } else if ((reinterpret_cast<uintptr_t>(g) & 3) == 0) {
+    const uint32_t nw = bytes >> 2;
+    uint32_t* gw = reinterpret_cast<uint32_t*>(g);
+    const uint32_t* lw = reinterpret_cast<const uint32_t*>(lds);
+    for (uint32_t v = tid; v < nw; v += nt) gw[v] = lw[v];
+    for (uint32_t b = (nw << 2) + tid; b < bytes; b += nt) g[b] = lds[b];
+  } else {
+    for (uint32_t b = tid; b < bytes; b += nt) g[b] = lds[b];
+  }
+}
+
+// Byte address of leaf value `obj` inside a side's LDS image.
+__device__ __forceinline__ uint32_t image_addr(const SideDesc& s, uint32_t obj, uint32_t off,
+                                               uint32_t size) {
+  if (s.kind == KIND_AOS) return obj * s.stride + off;
+  if (s.kind == KIND_SOA) return off + obj * size;
+  const uint32_t blk = s.width == 1 ? obj : __umulhi(obj, s.width_magic);
+  const uint32_t lane = obj - blk * s.width;
+  return blk * s.width * s.obj_bytes + off + lane * size;
+}
+
+// Bytes of a side's image that hold `cnt` objects (runs are contiguous for
+// AoS and AoSoA; for SoA this is only used for zeroing).
+__device__ __forceinline__ uint32_t image_used(const SideDesc& s, uint32_t cnt) {
+  if (s.kind == KIND_AOS) return cnt * s.stride;
+  if (s.kind == KIND_AOSOA) {
+    const uint32_t nblk = s.width == 1 ? cnt : __umulhi(cnt + s.width - 1, s.width_magic);
+    return nblk * s.width * s.obj_bytes;
+  }
+  return s.image_bytes;
+}
+
+__device__ __forceinline__ void copy_bytes(uint8_t* d, const uint8_t* s, uint32_t n) {
+  for (uint32_t k = 0; k < n; ++k) d[k] = s[k];
+}
+
+// Move one value inside LDS.
+__device__ __forceinline__ void move_value(uint8_t* dst, const uint8_t* src, const LeafDesc& L) {
+  if (L.op == OP_COPY) {
+    if (L.byte_wise) { copy_bytes(dst, src, L.src_size); return; }
+    switch (L.src_size) {
+      case 1: *dst = *src; break;
+      case 2: *reinterpret_cast<uint16_t*>(dst) = *reinterpret_cast<const uint16_t*>(src); break;
+      case 4: *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src); break;
+      default: *reinterpret_cast<uint64_t*>(dst) = *reinterpret_cast<const uint64_t*>(src); break;
+    }
+  } else if (L.op == OP_NARROW) {
+    double x;
+    if (L.byte_wise) copy_bytes(reinterpret_cast<uint8_t*>(&x), src, 8);
+    else x = *reinterpret_cast<const double*>(src);
+    const float y = (float)x;   // v_cvt_f32_f64: IEEE round to nearest even
+    if (L.byte_wise) copy_bytes(dst, reinterpret_cast<const uint8_t*>(&y), 4);
+    else *reinterpret_cast<float*>(dst) = y;
+  } else {  // OP_WIDEN
+    float x;
+    if (L.byte_wise) copy_bytes(reinterpret_cast<uint8_t*>(&x), src, 4);
+    else x = *reinterpret_cast<const float*>(src);
+    const double y = (double)x;
+    if (L.byte_wise) copy_bytes(dst, reinterpret_cast<const uint8_t*>(&y), 8);
+    else *reinterpret_cast<double*>(dst) = y;
+  }
+}
+
+// Block-wide exclusive scan of one u64 per thread (wave64 prefix with
+// cross-lane shuffles, then an LDS pass over the wave totals).  Returns the
+// exclusive prefix; *total receives the block total.  `wsum` has room for
+// one u64 per wave.  Must be called by every thread of the block.
+__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* wsum, uint64_t* total) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t nwaves = (blockDim.x + 63) >> 6;
+  uint64_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = __shfl_up(inc, d, 64);
+    if (lane >= (uint32_t)d) inc += o;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t run = 0;
+    for (uint32_t w = 0; w < nwaves; ++w) {
+      const uint64_t t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+    wsum[nwaves] = run;
+  }
+  __syncthreads();
+  const uint64_t r = wsum[wave] + inc - v;
+  *total = wsum[nwaves];
+  __syncthreads();
+  return r;
+}
+
+// LDS carve-up of the dense kernel.
+struct DenseLds {
+  uint8_t* src;
+  uint8_t* dst;
+  uint64_t* wsum;
+};
+
+__host__ __device__ __forceinline__ uint32_t round16(uint32_t x) { return (x + 15u) & ~15u; }
+
+// Load one side's tile into its LDS image.  `idx0` is the index of the
+// tile's first object on that side.
+__device__ void load_side(const DenseDesc& d, uint8_t* img, uint64_t idx0, uint32_t cnt,
+                          bool full) {
+  const SideDesc& s = d.src;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  if (s.kind == KIND_AOS) {
+    g2l(img, s.base + idx0 * s.stride, cnt * s.stride, tid, nt);
+  } else if (s.kind == KIND_AOSOA) {
+    g2l(img, s.base + idx0 * s.obj_bytes, image_used(s, cnt), tid, nt);
+  } else if (full && d.units_src) {
+    // SoA, full tile: the image is the columns' runs back to back (column c
+    // at tile * prefix(c)); walk it in 16-byte vectors, finding the column
+    // of each vector from the byte-unit table.
+    const uint32_t vt = d.tile >> 4;           // vectors per byte of object size
+    const uint32_t nv = vt * s.obj_bytes;
+    v4u* lv = reinterpret_cast<v4u*>(img);
+    for (uint32_t v = tid; v < nv; v += nt) {
+      const uint32_t u = v / vt;
+      const uint32_t c = d.unit_src[u];
+      const LeafDesc& L = d.leaf[c];
+      const uint32_t first_v = L.src_off >> 4;   // tile * prefix / 16
+      const v4u* col = reinterpret_cast<const v4u*>(L.src_col + idx0 * L.src_size);
+      lv[v] = col[v - first_v];
+    }
+  } else {
+    for (uint32_t c = 0; c < d.n_leaves; ++c) {
+      const LeafDesc& L = d.leaf[c];
+      if (L.op == OP_PTR || L.op == OP_LEN) continue;  // not in SoA images
+      g2l(img + L.src_off, L.src_col + idx0 * L.src_size, cnt * L.src_size, tid, nt);
+    }
+  }
+}
+
+__device__ void store_side(const DenseDesc& d, const uint8_t* img, uint64_t idx0, uint32_t cnt,
+                           bool full) {
+  const SideDesc& s = d.dst;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  if (s.kind == KIND_AOS) {
+    l2g(s.base + idx0 * s.stride, img, cnt * s.stride, tid, nt);
+  } else if (s.kind == KIND_AOSOA) {
+    l2g(s.base + idx0 * s.obj_bytes, img, image_used(s, cnt), tid, nt);
+  } else if (full && d.units_dst) {
+    const uint32_t vt = d.tile >> 4;
+    const uint32_t nv = vt * s.obj_bytes;
+    const v4u* lv = reinterpret_cast<const v4u*>(img);
+    for (uint32_t v = tid; v < nv; v += nt) {
+      const uint32_t u = v / vt;
+      const uint32_t c = d.unit_dst[u];
+      const LeafDesc& L = d.leaf[c];
+      const uint32_t first_v = L.dst_off >> 4;
+      v4u* col = reinterpret_cast<v4u*>(L.dst_col + idx0 * L.dst_size);
+      col[v - first_v] = lv[v];
+    }
+  } else {
+    for (uint32_t c = 0; c < d.n_leaves; ++c) {
+      const LeafDesc& L = d.leaf[c];
+      if (L.op == OP_PTR || L.op == OP_LEN) continue;  // not in SoA images
+      l2g(L.dst_col + idx0 * L.dst_size, img + L.dst_off, cnt * L.dst_size, tid, nt);
+    }
+  }
+}
+
+// Convert one tile.  `d` is read from kernel arguments or global memory
+// (uniform fields through the scalar cache).  `count` is the number of objects to
+// convert, `base` the source index of object 0 (device-side member bases).
+__device__ void dense_tile(const DenseDesc& d, const DenseLds& m, uint64_t tile, uint64_t count,
+                           uint64_t base) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t i0 = tile * d.tile;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, count - i0);
+  const bool full = cnt == d.tile;
+  // Source index alignment: a device-side base breaks the 16-byte runs of
+  // SoA columns; the per-column path then handles any alignment.
+  const bool aligned_src = full && (base == 0);
+
+  load_side(d, m.src, i0 + base, cnt, aligned_src);
+  if (d.zero_dst || (!full && d.dst.kind == KIND_AOSOA)) {
+    v4u* z = reinterpret_cast<v4u*>(m.dst);
+    const uint32_t nv = d.dst.image_bytes >> 4;
+    for (uint32_t v = tid; v < nv; v += nt) z[v] = v4u{0u, 0u, 0u, 0u};
+  }
+  __syncthreads();
+
+  // Fused local scan of jagged counts held in the source records.
+  if (d.scan_offsets) {
+    const uint32_t per = (d.tile + nt - 1) / nt;
+    const uint32_t o0 = tid * per;
+    uint64_t sum = 0;
+    for (uint32_t k = 0; k < per; ++k) {
+      const uint32_t o = o0 + k;
+      if (o < cnt) sum += *reinterpret_cast<const uint32_t*>(m.src + o * d.src.stride + d.scan_len_off);
+    }
+    uint64_t total;
+    uint64_t run = block_exclusive_scan(sum, m.wsum, &total);
+    for (uint32_t k = 0; k < per; ++k) {
+      const uint32_t o = o0 + k;
+      if (o < cnt) {
+        // entry i0 of a tile holds the tile total until the totals pass
+        store_off(d.scan_offsets, d.scan_off_type, i0 + o, o == 0 ? total : run);
+        run += *reinterpret_cast<const uint32_t*>(m.src + o * d.src.stride + d.scan_len_off);
+      }
+    }
+    if (tid == 0 && total > off_limit(d.scan_off_type)) flag(d.status, ST_FLAG_OVERFLOW);
+  }
+
+  for (uint32_t c = 0; c < d.n_leaves; ++c) {
+    const LeafDesc& L = d.leaf[c];
+    if (L.op == OP_PTR || L.op == OP_LEN) {
+      const uint32_t ot = L.aux >> 24;
+      const uint64_t first = load_off(L.src_col, ot, 0);
+      for (uint32_t o = tid; o < cnt; o += nt) {
+        const uint64_t i = i0 + o;
+        const uint64_t a = load_off(L.src_col, ot, i);
+        uint8_t* dp = m.dst + image_addr(d.dst, o, L.dst_off, L.dst_size);
+        if (L.op == OP_PTR) {
+          const uint64_t v = (a - first) * (uint64_t)(L.aux & 0xffffffu);
+          if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 8);
+          else *reinterpret_cast<uint64_t*>(dp) = v;
+        } else {
+          const uint32_t v = (uint32_t)(load_off(L.src_col, ot, i + 1) - a);
+          if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 4);
+          else *reinterpret_cast<uint32_t*>(dp) = v;
+        }
+      }
+      continue;
+    }
+    for (uint32_t o = tid; o < cnt; o += nt) {
+      const uint8_t* sp = m.src + image_addr(d.src, o, L.src_off, L.src_size);
+      uint8_t* dp = m.dst + image_addr(d.dst, o, L.dst_off, L.dst_size);
+      move_value(dp, sp, L);
+    }
+  }
+  __syncthreads();
+  store_side(d, m.dst, i0, cnt, full);
+  __syncthreads();
+}
+
+__device__ __forceinline__ DenseLds carve(uint8_t* smem, const DenseDesc& d) {
+  DenseLds m;
+  uint32_t off = 0;
+  m.src = smem + off;
+  off += round16(d.src.image_bytes);
+  m.dst = smem + off;
+  off += round16(d.dst.image_bytes);
+  m.wsum = reinterpret_cast<uint64_t*>(smem + off);
+  return m;
+}
+
+// Count and source base of a conversion: host-given, or read on the device
+// from an offsets column (member columns of a jagged group).
+__device__ __forceinline__ void dense_count(const DenseDesc& d, uint64_t* count, uint64_t* base) {
+  if (d.count_offsets) {
+    const uint64_t b = load_off(d.count_offsets, d.count_off_type, 0);
+    const uint64_t e = load_off(d.count_offsets, d.count_off_type, d.count_index);
+    uint64_t c = e >= b ? e - b : 0;
+    if (c > d.n) c = d.n;   // never beyond the destination capacity
+    if (b > d.src_capacity) c = 0;
+    else if (c > d.src_capacity - b) c = d.src_capacity - b;  // nor the source's
+    *count = c;
+    *base = b;
+  } else {
+    *count = d.n;
+    *base = 0;
+  }
+}
+
+__global__ void __launch_bounds__(1024) dense_kernel(const DenseDesc d) {
+  extern __shared__ uint4 smem_raw[];
+  uint8_t* smem = reinterpret_cast<uint8_t*>(smem_raw);
+  const DenseLds m = carve(smem, d);
+  uint64_t count, base;
+  dense_count(d, &count, &base);
+  const uint64_t ntiles = (count + d.tile - 1) / d.tile;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) dense_tile(d, m, t, count, base);
+}
+
+// ------------------------------------------------------------------ offsets
+
+// Exclusive scan of the per-tile totals left by the dense kernel's fused
+// scan (stored at entry tile * T), writing each tile's prefix there and the
+// grand total at entry n.  One work-group.
+__global__ void __launch_bounds__(1024) scan_totals_kernel(const ScanTotalsDesc d) {
+  __shared__ uint64_t wsum[17];
+  const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
+  uint64_t carry = 0;
+  for (uint64_t c0 = 0; c0 < ntiles; c0 += blockDim.x) {
+    const uint64_t k = c0 + threadIdx.x;
+    const uint64_t v = k < ntiles ? load_off(d.offsets, d.off_type, k * d.tile) : 0;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(v, wsum, &total);
+    if (k < ntiles) store_off(d.offsets, d.off_type, k * d.tile, carry + ex);
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    store_off(d.offsets, d.off_type, d.n, carry);
+    if (carry > off_limit(d.off_type)) flag(d.status, ST_FLAG_OVERFLOW);
+    else if (carry > d.capacity) flag(d.status, ST_FLAG_CAPACITY);
+  }
+}
+
+// Add tile prefixes, then copy the members of the tile's objects from the
+// pool into the member columns.  One work-group per tile (grid-stride).
+__global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
+  extern __shared__ uint4 smem_raw[];
+  uint64_t* offs = reinterpret_cast<uint64_t*>(smem_raw);          // tile + 1
+  uint64_t* ptrs = offs + (d.tile + 1);                             // tile
+  uint32_t* vlen = reinterpret_cast<uint32_t*>(ptrs + d.tile);      // tile: validated count
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
+  const uint64_t limit = off_limit(d.off_type);
+  const uint64_t pool_end = d.pool_bytes;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t i0 = t * d.tile;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, d.n - i0);
+    const uint64_t prefix = load_off(d.offsets, d.off_type, i0);
+    for (uint32_t o = tid; o <= cnt; o += nt) {
+      uint64_t v;
+      if (o == 0) v = prefix;
+      else if (o == cnt) v = load_off(d.offsets, d.off_type, i0 + cnt);  // next tile's prefix or total
+      else {
+        v = load_off(d.offsets, d.off_type, i0 + o) + prefix;
+        store_off(d.offsets, d.off_type, i0 + o, v);
+      }
+      offs[o] = v & limit;
+    }
+    __syncthreads();
+    if (d.n_members == 0) continue;  // uniform: offsets only
+    for (uint32_t o = tid; o < cnt; o += nt) {
+      const uint8_t* rec = d.records + (i0 + o) * d.rec_stride;
+      const uint64_t p = *reinterpret_cast<const uint64_t*>(rec + d.ptr_off);
+      const uint64_t len = *reinterpret_cast<const uint32_t*>(rec + d.len_off);
+      const bool good = (p & (uint64_t)(d.malign - 1)) == 0 && p <= pool_end &&
+                        len <= (pool_end - p) / d.mstride;
+      ptrs[o] = p;
+      vlen[o] = good ? (uint32_t)len : 0u;   // members readable for this object
+      if (!good) flag(d.status, ST_FLAG_BOUNDS);
+    }
+    __syncthreads();
+    const uint64_t m_lo = offs[0];
+    uint64_t m_hi = offs[cnt];
+    if (m_hi > d.capacity) m_hi = d.capacity;
+    for (uint64_t mm = m_lo + tid; mm < m_hi; mm += nt) {
+      // owner: the last object whose first member index is <= mm
+      uint32_t lo = 0, hi = cnt;  // offs[lo] <= mm < offs[hi] when well formed
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (offs[mid] <= mm) lo = mid; else hi = mid;
+      }
+      // j indexes the object's member block; reads stay inside the block the
+      // record validated against the pool, whatever the offsets hold
+      const uint64_t j = mm - offs[lo];
+      if (mm < offs[lo] || j >= vlen[lo]) continue;
+      const uint8_t* src = d.pool + ptrs[lo] + j * d.mstride;
+      for (uint32_t k = 0; k < d.n_members; ++k) {
+        const uint8_t* s = src + d.moff[k];
+        uint8_t* dst = d.mcol[k] + mm * d.msize[k];
+        switch (d.msize[k]) {
+          case 1: *dst = *s; break;
+          case 2: *reinterpret_cast<uint16_t*>(dst) = *reinterpret_cast<const uint16_t*>(s); break;
+          case 4: *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(s); break;
+          default: *reinterpret_cast<uint64_t*>(dst) = *reinterpret_cast<const uint64_t*>(s); break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Offsets column -> offsets column, rebased to start at 0, with the checks
+// of a well-formed source (non-decreasing, inside the source capacity) and
+// of the destination capacity.
+__global__ void rebase_kernel(const RebaseDesc d) {
+  const uint64_t first = load_off(d.src, d.off_type, 0);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= d.n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t a = load_off(d.src, d.off_type, i);
+    if (d.dst) store_off(d.dst, d.off_type, i, a - first);
+    if (i < d.n) {
+      const uint64_t b = load_off(d.src, d.off_type, i + 1);
+      if (b < a) flag(d.status, ST_FLAG_OVERFLOW);
+      else if (a > d.src_capacity || b - a > d.src_capacity - a) flag(d.status, ST_FLAG_BOUNDS);
+    } else if (a >= first && a - first > d.dst_capacity) {
+      flag(d.status, ST_FLAG_CAPACITY);
+    }
+  }
+}
+
+__global__ void clear_status_kernel(uint32_t* status) { *status = 0; }
+
+// ------------------------------------------------------------------ launchers
+
+uint32_t dense_lds_bytes(const DenseDesc& d) {
+  return round16(d.src.image_bytes) + round16(d.dst.image_bytes) + round16(17 * sizeof(uint64_t));
+}
+
+uint64_t dense_tiles(const DenseDesc& d) { return (d.n + d.tile - 1) / d.tile; }
+
+hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid, hipStream_t s) {
+  const uint32_t lds = dense_lds_bytes(d);
+  hipLaunchKernelGGL(dense_kernel, dim3(grid), dim3(threads), lds, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_totals(const ScanTotalsDesc& d, hipStream_t s) {
+  hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(1024), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherDesc& d, uint32_t threads, hipStream_t s) {
+  const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
+  const uint32_t grid = (uint32_t)(ntiles < 65535ull * 8 ? ntiles : 65535ull * 8);
+  const uint32_t lds = (2 * d.tile + 1) * 8 + d.tile * 4;
+  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(threads), lds, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s) {
+  const uint64_t work = d.n + 1;
+  const uint32_t grid = (uint32_t)((work + 255) / 256 < 4096 ? (work + 255) / 256 : 4096);
+  hipLaunchKernelGGL(rebase_kernel, dim3(grid), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_status(uint32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, s, status);
+  return hipGetLastError();
+}
+
+}  // namespace rl

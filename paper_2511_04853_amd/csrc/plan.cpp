@@ -1,0 +1,356 @@
+// Planning of conversions: descriptors of the dense, scan, gather and
+// rebase kernels for one collection.
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "plan.h"
+
+namespace rl {
+
+static constexpr uint32_t kLdsBudget = 64 * 1024;
+static constexpr uint32_t kDefaultTile = 256;
+static constexpr uint32_t kMaxTile = 4096;
+
+SideSpec object_side(const rl_layout* L, void* const* bufs, uint64_t index0) {
+  SideSpec s;
+  s.kind = (uint32_t)L->kind;
+  s.types = L->storage;
+  if (L->kind == RL_AOS) {
+    s.base = (uint8_t*)bufs[0] + index0 * L->stride;
+    s.stride = (uint32_t)L->stride;
+    s.off = L->leaf_offset;
+  } else if (L->kind == RL_SOA) {
+    for (size_t c = 0; c < L->storage.size(); ++c)
+      s.cols.push_back((uint8_t*)bufs[c] + index0 * type_size(L->storage[c]));
+  } else {
+    s.base = (uint8_t*)bufs[0] + index0 * (uint64_t)L->obj_bytes;  // index0 is a multiple of W
+    s.width = L->width;
+  }
+  return s;
+}
+
+SideSpec member_side(const rl_layout* L, void* const* bufs, uint32_t g) {
+  SideSpec s;
+  const rl_schema* sc = L->schema;
+  const uint32_t gb = group_buffer(L, g);
+  for (const auto& m : sc->members[g]) s.types.push_back(m.type);
+  if (L->kind == RL_AOS) {
+    s.kind = KIND_AOS;
+    s.base = (uint8_t*)bufs[gb];
+    s.stride = L->mstride[g];
+    s.off = L->moff[g];
+  } else {
+    s.kind = KIND_SOA;
+    for (size_t m = 0; m < sc->members[g].size(); ++m) s.cols.push_back((uint8_t*)bufs[gb + 1 + m]);
+  }
+  return s;
+}
+
+static uint32_t side_obj_bytes(const SideSpec& s) {
+  uint32_t b = 0;
+  for (auto t : s.types) b += type_size(t);
+  return b;
+}
+
+static uint64_t image_bytes(const SideSpec& s, uint32_t tile) {
+  if (s.kind == KIND_AOS) return (uint64_t)tile * s.stride;
+  return (uint64_t)tile * side_obj_bytes(s);
+}
+
+static uint32_t lcm32(uint32_t a, uint32_t b) { return a / std::gcd(a, b) * b; }
+
+uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target) {
+  uint32_t unit = 16;
+  if (s.kind == KIND_AOSOA) unit = lcm32(unit, s.width);
+  if (d.kind == KIND_AOSOA) unit = lcm32(unit, d.width);
+  if (unit > kMaxTile) return 0;
+  if (!target) target = kDefaultTile;
+  uint32_t t = std::max(unit, target / unit * unit);
+  while (t >= unit) {
+    const uint64_t lds = ((image_bytes(s, t) + 15) & ~15ull) + ((image_bytes(d, t) + 15) & ~15ull) + 144;
+    if (lds <= kLdsBudget) return t;
+    t -= unit;
+  }
+  return 0;
+}
+
+static bool side_aligned(const SideSpec& s, uint32_t c, uint32_t size, uint32_t prefix, uint32_t obj_bytes) {
+  if (s.kind == KIND_AOS) return s.stride % size == 0 && s.off[c] % size == 0;
+  if (s.kind == KIND_SOA) return true;
+  return ((uint64_t)s.width * obj_bytes) % size == 0 && ((uint64_t)s.width * prefix) % size == 0;
+}
+
+static bool cols_aligned16(const SideSpec& s) {
+  for (auto* p : s.cols)
+    if ((uintptr_t)p & 15) return false;
+  return true;
+}
+
+// ceil(2^32 / w): umulhi(i, magic) == i / w for i < 2^17 and 2 <= w <= 4096
+// (the rounding error i * (magic - 2^32 / w) / 2^32 stays below 1 / w).
+// Width 1 is handled without the multiplier.
+static uint32_t width_magic(uint32_t w) {
+  if (w <= 1) return 0;
+  return (uint32_t)(((1ull << 32) + w - 1) / w);
+}
+
+rl_status build_dense(const SideSpec& s, const SideSpec& d, uint64_t n, uint32_t tile, DenseDesc* out) {
+  DenseDesc& k = *out;
+  memset(&k, 0, sizeof k);
+  const uint32_t nl = (uint32_t)s.types.size();
+  if (nl != d.types.size()) return fail(RL_EINVAL, "internal: leaf count mismatch");
+  if (nl > (uint32_t)kMaxLeaves) return fail(RL_EUNSUPPORTED, "too many leaves");
+  const uint32_t sb = side_obj_bytes(s), db = side_obj_bytes(d);
+  auto fill_side = [&](const SideSpec& x, uint32_t obj_bytes, SideDesc& o) {
+    o.base = x.base;
+    o.kind = x.kind;
+    o.stride = x.stride;
+    o.width = x.kind == KIND_AOSOA ? x.width : 1;
+    o.obj_bytes = obj_bytes;
+    o.width_magic = width_magic(o.width);
+    o.image_bytes = (uint32_t)image_bytes(x, tile);
+  };
+  fill_side(s, sb, k.src);
+  fill_side(d, db, k.dst);
+  k.n = n;
+  k.tile = tile;
+  k.n_leaves = nl;
+  uint32_t sp = 0, dp = 0;
+  for (uint32_t c = 0; c < nl; ++c) {
+    LeafDesc& L = k.leaf[c];
+    const uint32_t ss = type_size(s.types[c]), dsz = type_size(d.types[c]);
+    L.src_size = (uint8_t)ss;
+    L.dst_size = (uint8_t)dsz;
+    if (s.types[c] == d.types[c]) L.op = OP_COPY;
+    else if (s.types[c] == RL_F64 && d.types[c] == RL_F32) L.op = OP_NARROW;
+    else if (s.types[c] == RL_F32 && d.types[c] == RL_F64) L.op = OP_WIDEN;
+    else return fail(RL_EUNSUPPORTED, "leaf %u: storage types %d -> %d", c, (int)s.types[c], (int)d.types[c]);
+    auto image_off = [&](const SideSpec& x, uint32_t prefix) -> uint32_t {
+      if (x.kind == KIND_AOS) return x.off[c];
+      if (x.kind == KIND_SOA) return tile * prefix;
+      return x.width * prefix;
+    };
+    L.src_off = image_off(s, sp);
+    L.dst_off = image_off(d, dp);
+    L.byte_wise = !(side_aligned(s, c, ss, sp, sb) && side_aligned(d, c, dsz, dp, db));
+    L.src_col = s.kind == KIND_SOA ? s.cols[c] : nullptr;
+    L.dst_col = d.kind == KIND_SOA ? d.cols[c] : nullptr;
+    sp += ss;
+    dp += dsz;
+  }
+  if (s.kind == KIND_SOA && sb <= (uint32_t)kMaxUnits && sb > 0 && cols_aligned16(s)) {
+    k.units_src = 1;
+    uint32_t u = 0;
+    for (uint32_t c = 0; c < nl; ++c)
+      for (uint32_t b = 0; b < k.leaf[c].src_size; ++b) k.unit_src[u++] = (uint8_t)c;
+  }
+  if (d.kind == KIND_SOA && db <= (uint32_t)kMaxUnits && db > 0 && cols_aligned16(d)) {
+    k.units_dst = 1;
+    uint32_t u = 0;
+    for (uint32_t c = 0; c < nl; ++c)
+      for (uint32_t b = 0; b < k.leaf[c].dst_size; ++b) k.unit_dst[u++] = (uint8_t)c;
+  }
+  return RL_OK;
+}
+
+static uint32_t default_grid(uint64_t tiles, const PlanShape& shape) {
+  if (shape.grid) return (uint32_t)std::min<uint64_t>(tiles ? tiles : 1, shape.grid);
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 256ull * 16));
+}
+
+static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& shape) {
+  Step st;
+  st.kind = Step::DENSE;
+  st.dense = d;
+  st.threads = shape.threads ? shape.threads : 256;
+  st.grid = default_grid(dense_tiles(d), shape);
+  plan->steps.push_back(st);
+  return RL_OK;
+}
+
+// Scan + gather steps for group g of an AoS record source into an offsets
+// destination.  `fused` says the first pass already ran inside the objects'
+// dense step.
+static rl_status push_scan_gather(Plan* plan, const rl_view& src, const rl_view& dst, uint32_t g,
+                                  uint64_t n, uint32_t tile, bool fused, bool gather,
+                                  const PlanShape& shape, uint32_t* status) {
+  const rl_layout* SL = src.layout;
+  const rl_layout* DL = dst.layout;
+  const rl_schema* sc = SL->schema;
+  const rl_type ot = sc->offset_types[g];
+  uint8_t* offs = (uint8_t*)dst.buffers[group_buffer(DL, g)];
+  if (!fused) {
+    // counts-only pass: a dense step with no leaves that scans group g
+    SideSpec s = object_side(SL, src.buffers, 0);
+    s.types.clear();
+    s.off.clear();
+    SideSpec d;
+    d.kind = KIND_SOA;
+    DenseDesc dd;
+    rl_status st = build_dense(s, d, n, tile, &dd);
+    if (st) return st;
+    dd.scan_offsets = offs;
+    dd.scan_len_off = SL->len_off[g];
+    dd.scan_off_type = ot;
+    dd.status = status;
+    push_dense(plan, dd, shape);
+  }
+  Step t;
+  t.kind = Step::SCAN_TOTALS;
+  t.totals = ScanTotalsDesc{offs, n, tile, (uint32_t)ot, gather ? dst.member_capacity[g] : ~0ull, status};
+  plan->steps.push_back(t);
+  Step ga;
+  ga.kind = Step::GATHER;
+  GatherDesc& G = ga.gather;
+  memset(&G, 0, sizeof G);
+  G.offsets = offs;
+  G.n = n;
+  G.tile = tile;
+  G.off_type = ot;
+  G.capacity = gather ? dst.member_capacity[g] : 0;
+  G.records = (const uint8_t*)src.buffers[0];
+  G.rec_stride = (uint32_t)SL->stride;
+  G.ptr_off = SL->ptr_off[g];
+  G.len_off = SL->len_off[g];
+  G.mstride = SL->mstride[g];
+  G.malign = SL->malign[g];
+  G.pool = (const uint8_t*)src.buffers[group_buffer(SL, g)];
+  G.pool_bytes = src.member_capacity[g] * SL->mstride[g];
+  G.status = status;
+  if (gather) {
+    const uint32_t mb = group_buffer(DL, g) + 1;
+    G.n_members = (uint32_t)sc->members[g].size();
+    for (uint32_t m = 0; m < G.n_members; ++m) {
+      G.moff[m] = SL->moff[g][m];
+      G.msize[m] = sc->members[g][m].size;
+      G.mcol[m] = (uint8_t*)dst.buffers[mb + m];
+    }
+  }
+  ga.threads = shape.threads ? shape.threads : 256;
+  plan->steps.push_back(ga);
+  return RL_OK;
+}
+
+rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const PlanShape& shape,
+                    Plan* plan) {
+  const rl_layout* SL = src.layout;
+  const rl_layout* DL = dst.layout;
+  const rl_schema* sc = SL->schema;
+  const uint32_t ng = (uint32_t)sc->members.size();
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  uint32_t* status = device_status(dev);
+  if (!status) return fail(RL_ENOMEM, "device status word");
+  if (ng && SL->kind == RL_AOS && DL->kind == RL_AOS)
+    return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
+
+  SideSpec s = object_side(SL, src.buffers, 0);
+  SideSpec d = object_side(DL, dst.buffers, 0);
+  const uint32_t tile = choose_tile(s, d, shape.tile);
+  if (!tile) return fail(RL_EUNSUPPORTED, "no tile shape fits these layouts (block widths or record size)");
+  DenseDesc dd;
+  rl_status st = build_dense(s, d, n, tile, &dd);
+  if (st) return st;
+  dd.status = status;
+  dd.zero_dst = DL->kind == RL_AOS && DL->has_gaps;
+  // destination records of a jagged schema get (ptr, len) from the source offsets
+  if (ng && DL->kind == RL_AOS) {
+    for (uint32_t g = 0; g < ng; ++g) {
+      const rl_type ot = sc->offset_types[g];
+      const uint8_t* so = (const uint8_t*)src.buffers[group_buffer(SL, g)];
+      for (int which = 0; which < 2; ++which) {
+        if (dd.n_leaves >= (uint32_t)kMaxLeaves) return fail(RL_EUNSUPPORTED, "too many leaves");
+        LeafDesc& L = dd.leaf[dd.n_leaves++];
+        memset(&L, 0, sizeof L);
+        L.op = which == 0 ? OP_PTR : OP_LEN;
+        L.dst_off = which == 0 ? DL->ptr_off[g] : DL->len_off[g];
+        L.dst_size = which == 0 ? 8 : 4;
+        L.src_size = 0;
+        L.byte_wise = (DL->stride % L.dst_size) != 0;
+        L.aux = (which == 0 ? DL->mstride[g] : 0) | ((uint32_t)ot << 24);
+        L.src_col = so;
+      }
+    }
+  }
+  const bool scan_src = ng && SL->kind == RL_AOS;
+  if (scan_src) {
+    dd.scan_offsets = (uint8_t*)dst.buffers[group_buffer(DL, 0)];
+    dd.scan_len_off = SL->len_off[0];
+    dd.scan_off_type = sc->offset_types[0];
+  }
+  push_dense(plan, dd, shape);
+
+  for (uint32_t g = 0; g < ng; ++g) {
+    const rl_type ot = sc->offset_types[g];
+    if (SL->kind == RL_AOS) {
+      if ((st = push_scan_gather(plan, src, dst, g, n, tile, g == 0, true, shape, status))) return st;
+      continue;
+    }
+    // offsets-column source: check (and, for an offsets destination, copy
+    // rebased), then move the member values
+    Step r;
+    r.kind = Step::REBASE;
+    r.rebase = RebaseDesc{(const uint8_t*)src.buffers[group_buffer(SL, g)],
+                          DL->kind == RL_AOS ? nullptr : (uint8_t*)dst.buffers[group_buffer(DL, g)],
+                          n, (uint32_t)ot, src.member_capacity[g], dst.member_capacity[g], status};
+    plan->steps.push_back(r);
+    SideSpec ms = member_side(SL, src.buffers, g);
+    SideSpec md = member_side(DL, dst.buffers, g);
+    const uint32_t mt = choose_tile(ms, md, shape.tile);
+    if (!mt) return fail(RL_EUNSUPPORTED, "no tile shape fits the member records");
+    DenseDesc m;
+    if ((st = build_dense(ms, md, dst.member_capacity[g], mt, &m))) return st;
+    m.status = status;
+    m.count_offsets = (const uint8_t*)src.buffers[group_buffer(SL, g)];
+    m.count_index = n;
+    m.count_off_type = (uint32_t)ot;
+    m.src_capacity = src.member_capacity[g];
+    m.zero_dst = md.kind == KIND_AOS && (side_obj_bytes(md) < md.stride);
+    push_dense(plan, m, shape);
+  }
+  return RL_OK;
+}
+
+rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t g, uint64_t n,
+                            const PlanShape& shape, Plan* plan) {
+  const rl_layout* SL = src.layout;
+  const rl_schema* sc = SL->schema;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  uint32_t* status = device_status(dev);
+  if (!status) return fail(RL_ENOMEM, "device status word");
+  if (SL->kind == RL_AOS) {
+    SideSpec s = object_side(SL, src.buffers, 0);
+    s.types.clear();
+    SideSpec d;
+    d.kind = KIND_SOA;
+    const uint32_t tile = choose_tile(s, d, shape.tile ? shape.tile : 1024);
+    if (!tile) return fail(RL_EUNSUPPORTED, "record too large for a tile");
+    return push_scan_gather(plan, src, dst, g, n, tile, false, false, shape, status);
+  }
+  Step r;
+  r.kind = Step::REBASE;
+  r.rebase = RebaseDesc{(const uint8_t*)src.buffers[group_buffer(SL, g)],
+                        (uint8_t*)dst.buffers[group_buffer(dst.layout, g)], n,
+                        (uint32_t)sc->offset_types[g], src.member_capacity[g], ~0ull, status};
+  plan->steps.push_back(r);
+  return RL_OK;
+}
+
+rl_status enqueue_plan(const Plan& plan, hipStream_t stream) {
+  for (const Step& s : plan.steps) {
+    hipError_t e = hipSuccess;
+    switch (s.kind) {
+      case Step::DENSE: e = launch_dense(s.dense, s.threads, s.grid, stream); break;
+      case Step::SCAN_TOTALS: e = launch_scan_totals(s.totals, stream); break;
+      case Step::GATHER: e = launch_gather(s.gather, s.threads, stream); break;
+      case Step::REBASE: e = launch_rebase(s.rebase, stream); break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return RL_OK;
+}
+
+}  // namespace rl

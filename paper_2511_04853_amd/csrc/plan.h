@@ -1,0 +1,71 @@
+// Conversion plans: the kernel steps that convert one collection.
+#pragma once
+
+#include <vector>
+
+#include "rl_internal.h"
+
+namespace rl {
+
+struct PlanShape {
+  uint32_t tile = 0;      // objects per tile (0: default)
+  uint32_t threads = 256; // threads per work-group
+  uint32_t grid = 0;      // work-groups of dense steps (0: one per tile, capped)
+};
+
+struct Step {
+  enum Kind { DENSE, SCAN_TOTALS, GATHER, REBASE } kind;
+  uint32_t threads = 256;
+  uint32_t grid = 0;
+  DenseDesc dense;
+  ScanTotalsDesc totals;
+  GatherDesc gather;
+  RebaseDesc rebase;
+};
+
+struct Plan {
+  std::vector<Step> steps;
+};
+
+// One side of a dense conversion, independent of where its leaves come
+// from (the per-object leaves of a layout, or a jagged group's members).
+struct SideSpec {
+  uint32_t kind = KIND_SOA;
+  uint8_t* base = nullptr;           // AoS records / AoSoA blocks
+  uint32_t stride = 0;               // AoS
+  uint32_t width = 0;                // AoSoA
+  std::vector<uint32_t> off;         // AoS: per leaf offset in the record
+  std::vector<uint8_t*> cols;        // SoA: per leaf column
+  std::vector<rl_type> types;        // storage type per leaf
+};
+
+struct Range {
+  uintptr_t lo, hi;
+};
+rl_status validate_view(const rl_view* v, uint64_t n, const char* which, std::vector<Range>* ranges,
+                        bool want_device);
+rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>& dst);
+
+uint32_t type_size(rl_type t);
+uint32_t layout_n_buffers(const rl_layout* L);
+void layout_buffer_bytes(const rl_layout* L, uint64_t n, const uint64_t* members, uint64_t* bytes);
+uint32_t group_buffer(const rl_layout* L, uint32_t g);
+
+SideSpec object_side(const rl_layout* L, void* const* bufs, uint64_t index0);
+SideSpec member_side(const rl_layout* L, void* const* bufs, uint32_t g);
+
+// Tile size for two sides given a target (multiple of 16 and of the block
+// widths, images within the LDS budget); 0 if none fits.
+uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target);
+rl_status build_dense(const SideSpec& s, const SideSpec& d, uint64_t n, uint32_t tile,
+                      DenseDesc* out);
+
+// Full conversion of objects 0..n-1 (views already validated).
+rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const PlanShape& shape,
+                    Plan* plan);
+rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t group, uint64_t n,
+                            const PlanShape& shape, Plan* plan);
+rl_status enqueue_plan(const Plan& plan, hipStream_t stream);
+PlanShape shape_from_env();
+
+}  // namespace rl

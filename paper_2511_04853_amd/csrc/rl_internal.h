@@ -1,0 +1,197 @@
+// Internal declarations shared by the host sources and the HIP kernels of
+// librelayout.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/relayout.h"
+
+namespace rl {
+
+constexpr int kMaxLeaves = 64;        // per-object leaves of a schema
+constexpr int kMaxMembers = 8;        // member leaves of one jagged group
+constexpr int kMaxGroups = 4;
+constexpr int kMaxObjBytes = 512;     // sum of leaf sizes on one side
+constexpr int kMaxUnits = 256;        // SoA images up to this many bytes per object use the unit table
+constexpr int kMaxExtent = 64;
+
+// Kinds of one side of a dense conversion (match rl_kind).
+enum SideKind : uint32_t { KIND_AOS = 0, KIND_SOA = 1, KIND_AOSOA = 2 };
+
+// Value operations of one leaf.
+enum LeafOp : uint8_t {
+  OP_COPY = 0,    // same type: size bytes
+  OP_NARROW = 1,  // f64 -> f32, round to nearest even
+  OP_WIDEN = 2,   // f32 -> f64
+  OP_PTR = 3,     // destination record pointer: (off[i] - off[0]) * mstride (u64)
+  OP_LEN = 4      // destination record count: off[i+1] - off[i] (u32)
+};
+
+// Device status flags (ORed by kernels, read by rl_sync).
+enum StatusFlag : uint32_t {
+  ST_FLAG_OVERFLOW = 1u,
+  ST_FLAG_CAPACITY = 2u,
+  ST_FLAG_BOUNDS = 4u
+};
+
+// One leaf of a dense (per-object) conversion.  "Image offset" is the term
+// of the leaf's byte address inside the LDS image of a tile that does not
+// depend on the object: AoS: offset in the record; SoA: tile * prefix;
+// AoSoA: width * prefix.
+struct LeafDesc {
+  uint32_t src_off;
+  uint32_t dst_off;
+  uint8_t src_size;
+  uint8_t dst_size;
+  uint8_t op;
+  uint8_t byte_wise;       // 1: an access in an image is not naturally aligned
+  uint32_t aux;            // OP_PTR: member record stride; OP_PTR/OP_LEN: offset type in bits 24..31
+  const uint8_t* src_col;  // SoA source column, or the offsets for OP_PTR/OP_LEN
+  uint8_t* dst_col;        // SoA destination column
+};
+static_assert(sizeof(LeafDesc) == 32, "LeafDesc layout");
+
+struct SideDesc {
+  uint8_t* base;           // AoS records / AoSoA blocks
+  uint32_t kind;
+  uint32_t stride;         // AoS record stride
+  uint32_t width;          // AoSoA block width W
+  uint32_t obj_bytes;      // sum of the leaf sizes on this side
+  uint32_t width_magic;    // ceil(2^32 / W): q = umulhi(i, magic) for i < 2^16
+  uint32_t image_bytes;    // bytes of this side's LDS image of one full tile
+};
+
+// Dense conversion of `n` objects (or of a count read on the device).
+struct DenseDesc {
+  SideDesc src, dst;
+  uint64_t n;              // objects; with count_offsets: the capacity bound
+  // Optional device-side count and index base (member columns of a group):
+  // count = off[count_index] - off[0], base = off[0], both read on the device.
+  const uint8_t* count_offsets;
+  uint64_t count_index;
+  uint32_t count_off_type; // rl_type of count_offsets
+  uint32_t tile;           // objects per tile (multiple of 16 and of W)
+  uint32_t n_leaves;
+  uint32_t zero_dst;       // zero the destination image before filling it
+  // Optional fused local scan of jagged counts (AoS record source):
+  uint8_t* scan_offsets;   // destination offsets column (null: no scan)
+  uint32_t scan_len_off;   // byte offset of the u32 count in a record
+  uint32_t scan_off_type;  // rl_type of scan_offsets
+  uint32_t* status;        // device status word
+  uint32_t units_src;      // 1: SoA source, full tiles walk the image by unit_src
+  uint32_t units_dst;      // 1: SoA destination, full tiles walk the image by unit_dst
+  uint64_t src_capacity;   // with count_offsets: source member capacity (count <= it - base)
+  LeafDesc leaf[kMaxLeaves];
+  uint8_t unit_src[kMaxUnits];   // SoA image: byte unit of object size -> leaf
+  uint8_t unit_dst[kMaxUnits];
+};
+
+// Second pass of the offsets scan: exclusive scan of per-tile totals.
+struct ScanTotalsDesc {
+  uint8_t* offsets;        // n + 1 entries
+  uint64_t n;
+  uint32_t tile;
+  uint32_t off_type;
+  uint64_t capacity;       // destination member capacity
+  uint32_t* status;
+};
+
+// Third pass: add tile prefixes to the local offsets and gather the members
+// of each tile's objects from a pool of member records.
+struct GatherDesc {
+  uint8_t* offsets;        // final offsets after this pass
+  uint64_t n;
+  uint32_t tile;
+  uint32_t off_type;
+  uint64_t capacity;       // destination member capacity
+  const uint8_t* records;  // source records
+  uint32_t rec_stride;
+  uint32_t ptr_off;        // u64 byte offset into the pool
+  uint32_t len_off;        // u32 member count
+  uint32_t mstride;        // member record bytes
+  uint32_t malign;         // member record alignment
+  uint32_t n_members;      // member leaves (0: offsets only)
+  const uint8_t* pool;
+  uint64_t pool_bytes;
+  uint32_t* status;
+  uint32_t moff[kMaxMembers];
+  uint32_t msize[kMaxMembers];
+  uint8_t* mcol[kMaxMembers];
+};
+
+// Offsets column to offsets column: rebased copy with checks.
+struct RebaseDesc {
+  const uint8_t* src;
+  uint8_t* dst;
+  uint64_t n;
+  uint32_t off_type;
+  uint64_t src_capacity;
+  uint64_t dst_capacity;
+  uint32_t* status;
+};
+
+// ---- kernel launchers (kernels.hip) ----
+hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid,
+                        hipStream_t s);
+hipError_t launch_scan_totals(const ScanTotalsDesc& d, hipStream_t s);
+hipError_t launch_gather(const GatherDesc& d, uint32_t threads, hipStream_t s);
+hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s);
+hipError_t launch_clear_status(uint32_t* status, hipStream_t s);
+uint32_t dense_lds_bytes(const DenseDesc& d);
+uint64_t dense_tiles(const DenseDesc& d);
+
+// ---- errors ----
+void set_error(const char* fmt, ...);
+rl_status fail(rl_status st, const char* fmt, ...);
+rl_status hip_fail(hipError_t e, const char* what);
+
+// ---- device state ----
+uint32_t* device_status(int device);  // lazily allocated per device
+
+}  // namespace rl
+
+// ---- opaque handle types ----
+struct rl_schema {
+  struct Leaf {
+    rl_type type;
+    uint32_t size;
+    int32_t field;
+    uint32_t element;
+    int32_t subgroup;
+  };
+  // Record slots in order: per-object leaves and, per jagged group, the
+  // (ptr, len) pair.  kind 0: leaf index; 1: ptr of group; 2: len of group.
+  struct Slot {
+    int kind;
+    int index;
+    int32_t subgroup;
+  };
+  std::vector<rl_field> fields;
+  std::vector<std::string> names;
+  std::vector<Leaf> leaves;
+  std::vector<std::vector<Leaf>> members;   // per group
+  std::vector<rl_type> offset_types;        // per group
+  std::vector<Slot> slots;
+};
+
+struct rl_layout {
+  const rl_schema* schema;
+  rl_kind kind;
+  rl_space space;
+  uint32_t width;
+  uint64_t stride;
+  std::vector<uint64_t> slot_offsets;       // AoS
+  std::vector<rl_type> storage;             // per per-object leaf
+  std::vector<uint32_t> leaf_offset;        // AoS: offset of each leaf in the record
+  std::vector<uint32_t> prefix;             // prefix sums of storage sizes
+  uint32_t obj_bytes;                       // sum of storage sizes
+  uint32_t record_align;                    // AoS: largest slot alignment
+  std::vector<uint32_t> ptr_off, len_off;   // AoS: per group
+  std::vector<uint32_t> mstride, malign;    // AoS: per group member record
+  std::vector<std::vector<uint32_t>> moff;  // AoS: per group member offsets
+  bool has_gaps;                            // AoS: bytes not covered by a written slot
+};

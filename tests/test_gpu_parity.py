@@ -1,0 +1,346 @@
+"""GPU parity: every conversion through the C ABI must give, byte for byte,
+what the oracle gives on the same input (padding and unused block slots
+included: the destination is pre-filled with a sentinel)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_04853_amd as P
+from paper_2511_04853_amd import workloads as W
+from tests import rlhelp as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.lib()
+    yield
+
+
+def _kinds():
+    return [("aos", 0), ("soa", 0), ("aosoa", 1), ("aosoa", 3), ("aosoa", 32), ("aosoa", 128)]
+
+
+def _check(decl, src_kind, dst_kind, n, seed=0, narrow=False, shuffle=True, mean_len=3.0):
+    sp = H.SchemaPair(decl)
+    if decl is W.CELL:
+        v = W.cell_values(n, seed=seed)
+    elif decl is W.CLUSTER:
+        v = W.cluster_values(n, seed=seed, mean_len=mean_len, shuffle_pool=shuffle)
+    else:
+        v = W.generic_values(decl, n, seed=seed, mean_len=mean_len, shuffle_pool=shuffle)
+    dst_storage = H.narrowed_storage(decl) if narrow else None
+    src = sp.layout(*src_kind)
+    dst = sp.layout(*dst_kind, storage=dst_storage)
+    tot = H.totals(v)
+    sbytes = oracle.pack(sp.orc, v, src.orc, pool_order=shuffle)
+    if src.kind == "aos":
+        src_members = [len(sbytes[1 + g]) // src.orc.member_stride[g] for g in range(sp.orc.n_groups)]
+    else:
+        src_members = tot
+    st, want, wt = H.oracle_convert(src, sbytes, dst, n, src_members, tot)
+    assert st == 0 and wt == tot
+    rc, rs, got = H.run_lib_convert(src, sbytes, dst, n, src_members, tot)
+    assert rc == P.RL_OK, P.rl_last_error()
+    assert rs == P.RL_OK, P.rl_last_error()
+    H.assert_same_bytes(got, want, f"{decl.name} {src_kind}->{dst_kind} n={n}")
+    return got
+
+
+@pytest.mark.parametrize("decl", [W.PLAIN8, W.CELL, W.SENSOR], ids=lambda d: d.name)
+@pytest.mark.parametrize("src_kind", _kinds(), ids=str)
+@pytest.mark.parametrize("dst_kind", _kinds(), ids=str)
+def test_dense_pairs(decl, src_kind, dst_kind):
+    if src_kind == dst_kind:
+        pytest.skip("same layout")
+    _check(decl, src_kind, dst_kind, 1037, seed=1)
+
+
+@pytest.mark.parametrize("decl", [W.CLUSTER, W.PARTICLE], ids=lambda d: d.name)
+@pytest.mark.parametrize("pair", [(("aos", 0), ("soa", 0)), (("aos", 0), ("aosoa", 32)),
+                                  (("soa", 0), ("aos", 0)), (("aosoa", 64), ("aos", 0)),
+                                  (("soa", 0), ("aosoa", 3)), (("aosoa", 128), ("soa", 0))], ids=str)
+def test_jagged_pairs(decl, pair):
+    _check(decl, pair[0], pair[1], 2333, seed=2)
+
+
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 255, 256, 257])
+def test_small_and_ragged_sizes(n):
+    _check(W.PLAIN8, ("aos", 0), ("soa", 0), n, seed=n)
+    _check(W.CELL, ("aos", 0), ("aosoa", 128), n, seed=n, narrow=True)
+    _check(W.CLUSTER, ("aos", 0), ("soa", 0), n, seed=n)
+
+
+def test_zero_objects_is_a_no_op():
+    sp = H.SchemaPair(W.PLAIN8)
+    a, s = sp.layout("aos"), sp.layout("soa")
+    src = H.alloc_device([64])
+    dst = H.alloc_device([64] * 8)
+    sv = P.View(a.lib, 2, src)
+    dv = P.View(s.lib, 2, dst)
+    assert P.lib().rl_convert(sv.ref(), dv.ref(), 0, P.stream_ptr()) == P.RL_OK
+    assert P.sync() == P.RL_OK
+    assert all(int(t.min()) == H.SENTINEL for t in dst)
+
+
+def test_plain_round_trip_full_size():
+    """Plain method, small case: 10,000 objects of 8 mixed scalars,
+    AoS -> SoA -> AoS on the device."""
+    v = W.plain_values()
+    sp = H.SchemaPair(W.PLAIN8)
+    aos, soa = sp.layout("aos"), sp.layout("soa")
+    src = oracle.pack(sp.orc, v, aos.orc)
+    st, want, _ = H.oracle_convert(aos, src, soa, v.n, [], [])
+    rc, rs, got = H.run_lib_convert(aos, src, soa, v.n, [], [])
+    assert rc == 0 and rs == 0
+    H.assert_same_bytes(got, want, "aos->soa")
+    rc, rs, back = H.run_lib_convert(soa, got, aos, v.n, [], [])
+    assert rc == 0 and rs == 0
+    H.assert_same_bytes(back, src, "soa->aos round trip")
+
+
+@pytest.mark.parametrize("dst", [("soa", 0), ("aosoa", 32), ("aosoa", 64), ("aosoa", 128)], ids=str)
+def test_cell_collection_full_size(dst):
+    """Cell-like collection, 190,000 objects, energy_d narrowed to f32."""
+    got = _check(W.CELL, ("aos", 0), dst, 190_000, seed=1001, narrow=True)
+    if dst[0] == "soa":
+        assert np.array_equal(got[4].view(np.uint32), np.arange(190_000, dtype=np.uint32))
+        assert np.array_equal(got[6], got[0])
+
+
+@pytest.mark.parametrize("shuffle", [True, False])
+def test_cluster_collection_full_size(shuffle):
+    """Jagged collection, 50,000 objects, Poisson(40) members: AoS-ptr ->
+    SoA + offsets -> AoS-ptr (canonical pool)."""
+    sp = H.SchemaPair(W.CLUSTER)
+    v = W.cluster_values(shuffle_pool=shuffle)
+    aos, soa = sp.layout("aos"), sp.layout("soa")
+    src = oracle.pack(sp.orc, v, aos.orc, pool_order=shuffle)
+    tot = H.totals(v)
+    st, want, _ = H.oracle_convert(aos, src, soa, v.n, tot, tot)
+    rc, rs, got = H.run_lib_convert(aos, src, soa, v.n, tot, tot)
+    assert rc == 0 and rs == 0, P.rl_last_error()
+    H.assert_same_bytes(got, want, "aos-ptr -> soa")
+    st, want2, _ = H.oracle_convert(soa, want, aos, v.n, tot, tot)
+    rc, rs, back = H.run_lib_convert(soa, got, aos, v.n, tot, tot)
+    assert rc == 0 and rs == 0, P.rl_last_error()
+    H.assert_same_bytes(back, want2, "soa -> aos-ptr")
+    canon = oracle.pack(sp.orc, v, aos.orc, pool_order=False)
+    H.assert_same_bytes(back, canon, "canonical pool")
+
+
+def test_narrowing_edge_vector_on_gpu():
+    from tests.test_oracle_pins import narrowing_edge_vector
+    cases = narrowing_edge_vector()
+    d = np.array([c[0] for c in cases])
+    want = np.array([c[1] for c in cases], dtype=np.float32).view(np.uint32)
+    decl = W.SchemaDecl("n1", (W.Field("x", "f64"),))
+    sp = H.SchemaPair(decl)
+    for kinds in [(("soa", 0), ("soa", 0)), (("aos", 0), ("aosoa", 16)), (("soa", 0), ("aos", 0))]:
+        src = sp.layout(*kinds[0])
+        dst = sp.layout(*kinds[1], storage=["f32"])
+        sbytes = oracle.pack(sp.orc, W.Values(decl, len(d), fields={"x": d}), src.orc)
+        rc, rs, got = H.run_lib_convert(src, sbytes, dst, len(d), [], [])
+        assert rc == 0 and rs == 0
+        if dst.kind == "soa":
+            vals = got[0].view(np.uint32)
+        elif dst.kind == "aos":
+            vals = got[0].view(np.uint32)
+        else:
+            vals = got[0].view(np.uint32)[:len(d)]
+        assert np.array_equal(vals, want), (kinds, vals, want)
+
+
+def test_narrowing_random_doubles_on_gpu():
+    rng = np.random.default_rng(5)
+    span = np.ldexp(rng.uniform(1, 2, 200_000), rng.integers(-160, 130, 200_000))
+    span *= np.where(rng.random(200_000) < 0.5, -1.0, 1.0)
+    decl = W.SchemaDecl("n1", (W.Field("x", "f64"),))
+    sp = H.SchemaPair(decl)
+    src, dst = sp.layout("soa"), sp.layout("soa", storage=["f32"])
+    sbytes = [span.view(np.uint8)]
+    rc, rs, got = H.run_lib_convert(src, sbytes, dst, span.size, [], [])
+    assert rc == 0 and rs == 0
+    st, want, _ = H.oracle_convert(src, sbytes, dst, span.size, [], [])
+    H.assert_same_bytes(got, want, "narrowing")
+
+
+@pytest.mark.parametrize("tile,threads", [(16, 64), (48, 128), (128, 256), (256, 256), (1024, 1024),
+                                          (4096, 512)])
+def test_tile_shape_independence(tile, threads, monkeypatch):
+    monkeypatch.setenv("RL_TILE_OBJECTS", str(tile))
+    monkeypatch.setenv("RL_BLOCK_THREADS", str(threads))
+    _check(W.CELL, ("aos", 0), ("soa", 0), 20_011, seed=7, narrow=True)
+    _check(W.CELL, ("soa", 0), ("aosoa", 16), 20_011, seed=7)
+    _check(W.CLUSTER, ("aos", 0), ("aosoa", 16), 3_001, seed=7, mean_len=10)
+    monkeypatch.setenv("RL_GRID_BLOCKS", "3")   # persistent-style grid-stride
+    _check(W.PLAIN8, ("aosoa", 16), ("aos", 0), 20_011, seed=7)
+
+
+def test_packed_source_records():
+    """A pre-existing packed struct (no padding, fields at odd offsets)."""
+    sp = H.SchemaPair(W.CELL)
+    offs = [0, 4, 8, 9, 11, 15, 19]
+    src = H.Pair.__new__(H.Pair)
+    src.sp, src.kind, src.width, src.storage = sp, "aos", 0, None
+    src.lib = P.Layout(sp.lib, "aos", slot_offsets=offs, stride=27)
+    src.orc = oracle.make_layout(sp.orc, "aos", slot_offsets=offs, stride=27)
+    dst = sp.layout("soa", storage=H.narrowed_storage(W.CELL))
+    v = W.cell_values(5_000, seed=3)
+    sbytes = oracle.pack(sp.orc, v, src.orc)
+    st, want, _ = H.oracle_convert(src, sbytes, dst, v.n, [], [])
+    rc, rs, got = H.run_lib_convert(src, sbytes, dst, v.n, [], [])
+    assert rc == 0 and rs == 0
+    H.assert_same_bytes(got, want, "packed records")
+    rc, rs, back = H.run_lib_convert(dst, got, src, v.n, [], [])
+    st, want2, _ = H.oracle_convert(dst, want, src, v.n, [], [])
+    H.assert_same_bytes(back, want2, "back to packed records")
+
+
+# ------------------------------------------------------------------ device-side errors
+
+def _cluster_src(n=300, seed=9):
+    sp = H.SchemaPair(W.CLUSTER)
+    v = W.cluster_values(n, seed=seed, mean_len=5)
+    aos, soa = sp.layout("aos"), sp.layout("soa")
+    src = oracle.pack(sp.orc, v, aos.orc, pool_order=True)
+    return sp, v, aos, soa, src
+
+
+def test_capacity_exceeded_is_reported():
+    sp, v, aos, soa, src = _cluster_src()
+    tot = v.total(0)
+    st, _, _ = oracle.convert(aos.orc, src, soa.orc, v.n, [tot], [tot - 1])
+    assert st == oracle.ST_CAPACITY
+    rc, rs, got = H.run_lib_convert(aos, src, soa, v.n, [tot], [tot - 1])
+    assert rc == 0 and rs == P.RL_ECAPACITY
+    # nothing written past the destination member columns
+    assert got[7].size == 4 * (tot - 1)
+
+
+def test_pool_bounds_are_reported():
+    from tests import npref
+    sp, v, aos, soa, src = _cluster_src()
+    tot = v.total(0)
+    bad = [b.copy() for b in src]
+    rec = bad[0].view(npref.record_dtype(W.CLUSTER))
+    i = int(np.nonzero(rec["len0"])[0][0])
+    rec["ptr0"][i] = len(bad[1]) - 8      # last member record: its list runs past the pool
+    st, _, _ = oracle.convert(aos.orc, bad, soa.orc, v.n, [tot], [tot])
+    rc, rs, _ = H.run_lib_convert(aos, bad, soa, v.n, [tot], [tot])
+    assert st == oracle.ST_BOUNDS and rs == P.RL_EBOUNDS
+    bad = [b.copy() for b in src]
+    rec = bad[0].view(npref.record_dtype(W.CLUSTER))
+    rec["ptr0"][i] += 2                    # misaligned member block
+    rc, rs, _ = H.run_lib_convert(aos, bad, soa, v.n, [tot], [tot])
+    assert rs == P.RL_EBOUNDS
+
+
+def test_offset_overflow_is_reported():
+    from tests import npref
+    sp, v, aos, soa, src = _cluster_src()
+    tot = v.total(0)
+    bad = [b.copy() for b in src]
+    rec = bad[0].view(npref.record_dtype(W.CLUSTER))
+    rec["len0"][:3] = 2**31
+    st, _, _ = oracle.convert(aos.orc, bad, soa.orc, v.n, [tot], [tot], dst_capacity=[tot])
+    rc, rs, _ = H.run_lib_convert(aos, bad, soa, v.n, [tot], [tot])
+    assert st == oracle.ST_OVERFLOW and rs == P.RL_EOVERFLOW
+    # the status word is cleared by rl_sync
+    assert P.sync() == P.RL_OK
+
+
+# ------------------------------------------------------------------ offsets alone
+
+@pytest.mark.parametrize("n", [1, 1023, 1024, 1025, 50_000, 300_001])
+def test_offsets_scan(n):
+    sp = H.SchemaPair(W.CLUSTER)
+    v = W.cluster_values(n, seed=n, mean_len=3)
+    aos, soa = sp.layout("aos"), sp.layout("soa")
+    src = oracle.pack(sp.orc, v, aos.orc, pool_order=True)
+    tot = v.total(0)
+    dsrc = H.to_device(src)
+    ddst = H.alloc_device(soa.lib.buffer_bytes(n, [tot]))
+    sv = P.View(aos.lib, n, dsrc, [tot])
+    dv = P.View(soa.lib, n, ddst, [tot])
+    import ctypes
+    total = ctypes.c_uint64()
+    assert P.lib().rl_offsets(sv.ref(), dv.ref(), 0, n, ctypes.byref(total), P.stream_ptr()) == 0, P.rl_last_error()
+    assert P.sync() == 0
+    assert total.value == tot
+    st, want, _ = oracle.exclusive_scan(v.lengths[0], "u32")
+    assert np.array_equal(ddst[6].cpu().numpy().view(np.uint32), want)
+
+
+# ------------------------------------------------------------------ transfers
+
+def _pinned_from(bufs):
+    out = H.alloc_pinned([len(b) for b in bufs])
+    for t, b in zip(out, bufs):
+        if t is not None:
+            t.numpy()[:] = b
+    return out
+
+
+@pytest.mark.parametrize("mode", ["staged", "zero_copy"])
+@pytest.mark.parametrize("dst", [("soa", 0), ("aosoa", 64)], ids=str)
+@pytest.mark.parametrize("chunk", [0, 65536])
+def test_h2d_transfer_cell(mode, dst, chunk):
+    sp = H.SchemaPair(W.CELL)
+    v = W.cell_values(190_000, seed=1001)
+    aos = sp.layout("aos", space="pinned")
+    dl = sp.layout(*dst, storage=H.narrowed_storage(W.CELL))
+    sbytes = oracle.pack(sp.orc, v, aos.orc)
+    st, want, _ = H.oracle_convert(aos, sbytes, dl, v.n, [], [])
+    hsrc = _pinned_from(sbytes)
+    ddst = H.alloc_device(dl.lib.buffer_bytes(v.n))
+    sv = P.View(aos.lib, v.n, hsrc)
+    dv = P.View(dl.lib, v.n, ddst)
+    P.transfer(sv, dv, v.n, mode=mode, chunk_bytes=chunk)
+    assert P.sync() == 0, P.rl_last_error()
+    H.assert_same_bytes(H.to_numpy(ddst), want, f"h2d {mode}")
+
+
+@pytest.mark.parametrize("mode", ["staged", "zero_copy"])
+def test_d2h_transfer_cell(mode):
+    sp = H.SchemaPair(W.CELL)
+    st_types = H.narrowed_storage(W.CELL)
+    v = W.cell_values(100_003, seed=4)
+    soa = sp.layout("soa", storage=st_types)
+    aos = sp.layout("aos", space="pinned")
+    sbytes = oracle.pack(sp.orc, v, soa.orc)
+    st, want, _ = H.oracle_convert(soa, sbytes, aos, v.n, [], [])
+    dsrc = H.to_device(sbytes)
+    hdst = H.alloc_pinned(aos.lib.buffer_bytes(v.n))
+    P.transfer(P.View(soa.lib, v.n, dsrc), P.View(aos.lib, v.n, hdst), v.n, mode=mode, chunk_bytes=1 << 20)
+    assert P.sync() == 0, P.rl_last_error()
+    H.assert_same_bytes(H.to_numpy(hdst), want, f"d2h {mode}")
+
+
+@pytest.mark.parametrize("mode", ["staged", "zero_copy"])
+def test_jagged_transfers(mode):
+    sp = H.SchemaPair(W.CLUSTER)
+    v = W.cluster_values(20_000, seed=11)
+    aos_h = sp.layout("aos", space="pinned")
+    soa = sp.layout("soa")
+    tot = H.totals(v)
+    sbytes = oracle.pack(sp.orc, v, aos_h.orc, pool_order=True)
+    st, want, _ = H.oracle_convert(aos_h, sbytes, soa, v.n, tot, tot)
+    hsrc = _pinned_from(sbytes)
+    ddst = H.alloc_device(soa.lib.buffer_bytes(v.n, tot))
+    P.transfer(P.View(aos_h.lib, v.n, hsrc, tot), P.View(soa.lib, v.n, ddst, tot), v.n, mode=mode)
+    assert P.sync() == 0, P.rl_last_error()
+    got = H.to_numpy(ddst)
+    H.assert_same_bytes(got, want, f"jagged h2d {mode}")
+    hback = H.alloc_pinned(aos_h.lib.buffer_bytes(v.n, tot))
+    P.transfer(P.View(soa.lib, v.n, ddst, tot), P.View(aos_h.lib, v.n, hback, tot), v.n, mode=mode)
+    assert P.sync() == 0, P.rl_last_error()
+    canon = oracle.pack(sp.orc, v, aos_h.orc, pool_order=False)
+    H.assert_same_bytes(H.to_numpy(hback), canon, f"jagged d2h {mode}")
