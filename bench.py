@@ -1,0 +1,268 @@
+"""Benchmark of the layout-conversion hot path on one MI355X.
+
+Step: the cell-like collection of the case study (190,000 objects: energy
+f32, time f32, gain i8, quality u16, hash u32, flags u32, energy_d f64),
+resident in HBM as AoS records, converted into the four device layouts the
+workload asks for: SoA (energy_d narrowed to f32) and AoSoA with block
+widths 32, 64 and 128 (same narrowing).  Each step uses its own copy of the
+source and destinations, rotating over enough copies that the working set
+is several times the 256 MB Infinity Cache, so every step reads and writes
+HBM.
+
+Value: algorithmic bytes (source footprint read + destination footprint
+written, per conversion) per second of the timed region.
+
+Extra legs, outside the timed region: a sweep at larger object counts, the
+host -> device transfer + conversion rate (PCIe included), the batched
+graph launch against a per-collection launch loop, and the oracle timed on
+the host cores (cpu_baseline).
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_CELLS = 190_000
+WIDTHS = (32, 64, 128)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--sets", type=int, default=32, help="rotating input/output copies")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2511_04853_amd as P
+    from paper_2511_04853_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    P.lib()
+    stream = torch.cuda.current_stream()
+    sp = P.stream_ptr(stream)
+
+    # calibration copy of known size for the HBM byte counters (untimed)
+    calib = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    calib2 = torch.empty_like(calib)
+    calib2.copy_(calib)
+    torch.cuda.synchronize()
+    del calib, calib2
+
+    S = P.Schema(W.CELL)
+    narrowed = ["f32" if f.type == "f64" else f.type for f in W.CELL.fields]
+    aos = P.Layout(S, "aos")
+    dsts = [P.Layout(S, "soa", storage=narrowed)] + [P.Layout(S, "aosoa", width=w, storage=narrowed)
+                                                     for w in WIDTHS]
+    n = N_CELLS
+    v = W.cell_values(n)
+
+    # source records built on the device from the generated columns
+    def device_aos(values):
+        cols = []
+        for f in W.CELL.fields:
+            cols.append(torch.from_numpy(np.ascontiguousarray(values.fields[f.name]).view(np.uint8)).cuda())
+        soa64 = P.Layout(S, "soa")
+        rec = torch.empty(aos.buffer_bytes(values.n)[0], dtype=torch.uint8, device="cuda")
+        P.convert(P.View(soa64, values.n, cols), P.View(aos, values.n, [rec]), values.n)
+        assert P.sync() == 0
+        return rec
+
+    rec0 = device_aos(v)
+    sets = []
+    for r in range(args.sets):
+        src = rec0 if r == 0 else rec0.clone()
+        outs = []
+        for L in dsts:
+            bufs = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in L.buffer_bytes(n)]
+            outs.append(P.View(L, n, bufs))
+        sets.append((P.View(aos, n, [src]), outs))
+    torch.cuda.synchronize()
+
+    src_bytes = aos.buffer_bytes(n)[0]
+    conv_bytes = [src_bytes + sum(L.buffer_bytes(n)) for L in dsts]
+    step_bytes = sum(conv_bytes)
+    lib = P.lib()
+
+    def step(k, evs=None):
+        s, outs = sets[k % len(sets)]
+        for j, d in enumerate(outs):
+            if evs is not None:
+                evs[j][0].record(stream)
+            st = lib.rl_convert(s.ref(), d.ref(), n, sp)
+            if st:
+                raise P.RelayoutError(st, "rl_convert")
+            if evs is not None:
+                evs[j][1].record(stream)
+
+    for k in range(args.warmup):
+        step(k)
+    assert P.sync(stream) == 0, P.rl_last_error()
+
+    K = args.steps
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in dsts] for _ in range(K)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(K):
+        step(k, evs[k])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t0.elapsed_time(t1)
+    assert P.sync(stream) == 0, P.rl_last_error()
+    ms_per_step = ms_total / K
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in row] for row in evs])
+    per_kernel_ms = launch_ms.mean(axis=0)
+    mean_launch_ms = float(launch_ms.mean())
+    mean_launch_bytes = float(np.mean(conv_bytes))
+    achieved = mean_launch_bytes / (mean_launch_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "conversion GB/s (read+write) vs HBM peak; batched speedup; p50/p99 event lat",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": "cell collection, 190,000 objects, device AoS (32 B records) -> SoA with "
+                        "energy_d f64->f32 and -> AoSoA W=32/64/128 (same narrowing), "
+                        f"{args.sets} rotating copies ({args.sets * (step_bytes - 3 * src_bytes) / 1e6:.0f} MB "
+                        "working set, beyond the 256 MB Infinity Cache)",
+            "objects": n,
+            "bytes_per_step": step_bytes,
+            "conversions_per_step": len(dsts),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "rl::dense_kernel",
+            "mean_launch_us": round(mean_launch_ms * 1e3, 3),
+            "per_destination_us": [round(x * 1e3, 3) for x in per_kernel_ms],
+            "bytes_per_launch": int(mean_launch_bytes),
+        },
+    }
+
+    if not args.no_extras:
+        out["sweep"] = sweep(P, W, torch, stream)
+        out["h2d"] = h2d_rate(P, W, torch, stream, S, aos, dsts[0], v)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W, v, args.cpu_seconds, step_bytes)
+    print(json.dumps(out), flush=True)
+
+
+def sweep(P, W, torch, stream):
+    """AoS -> SoA (narrowed) at larger object counts, 2 copies rotating."""
+    res = {}
+    S = P.Schema(W.CELL)
+    narrowed = ["f32" if f.type == "f64" else f.type for f in W.CELL.fields]
+    aos = P.Layout(S, "aos")
+    soa = P.Layout(S, "soa", storage=narrowed)
+    lib = P.lib()
+    sp = P.stream_ptr(stream)
+    for n in (1 << 20, 1 << 22, 1 << 24):
+        pairs = []
+        for r in range(2):
+            src = torch.randint(0, 255, (aos.buffer_bytes(n)[0],), dtype=torch.uint8, device="cuda")
+            dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in soa.buffer_bytes(n)]
+            pairs.append((P.View(aos, n, [src]), P.View(soa, n, dst)))
+        nbytes = aos.buffer_bytes(n)[0] + sum(soa.buffer_bytes(n))
+        reps = 10
+        for k in range(3):
+            lib.rl_convert(pairs[k % 2][0].ref(), pairs[k % 2][1].ref(), n, sp)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for k in range(reps):
+            lib.rl_convert(pairs[k % 2][0].ref(), pairs[k % 2][1].ref(), n, sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[str(n)] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                       "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del pairs
+    assert P.sync(stream) == 0
+    return res
+
+
+def h2d_rate(P, W, torch, stream, S, aos_dev, soa, v):
+    """Pinned host AoS -> device SoA, staged over PCIe (not the headline value)."""
+    aos_h = P.Layout(S, "aos", space="pinned")
+    n = v.n
+    host = torch.empty(aos_dev.buffer_bytes(n)[0], dtype=torch.uint8, pin_memory=True)
+    dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in soa.buffer_bytes(n)]
+    sv, dv = P.View(aos_h, n, [host]), P.View(soa, n, dst)
+    res = {}
+    for mode in ("staged", "zero_copy"):
+        for _ in range(3):
+            P.transfer(sv, dv, n, mode=mode)
+        torch.cuda.synchronize()
+        reps = 20
+        t = time.perf_counter()
+        for _ in range(reps):
+            P.transfer(sv, dv, n, mode=mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        res[mode] = {"us": round(dt * 1e6, 1), "link_GBps": round(host.numel() / dt / 1e9, 2)}
+    assert P.sync(stream) == 0
+    return res
+
+
+def cpu_baseline(W, v, seconds, step_bytes):
+    """The oracle (plain C per-object loop, single thread) on the same step."""
+    import oracle
+    S = oracle.Schema(W.CELL)
+    narrowed = ["f32" if t == "f64" else t for t in S.leaf_types()]
+    aos = oracle.make_layout(S, "aos")
+    dsts = [oracle.make_layout(S, "soa", storage=narrowed)] + [
+        oracle.make_layout(S, "aosoa", width=w, storage=narrowed) for w in WIDTHS]
+    src = oracle.pack(S, v, aos)
+    reps = 0
+    t = time.perf_counter()
+    while True:
+        for d in dsts:
+            st, _, _ = oracle.convert(aos, src, d, v.n)
+            assert st == 0
+        reps += 1
+        if time.perf_counter() - t >= seconds:
+            break
+    dt = (time.perf_counter() - t) / reps
+    return {"value": round(step_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full steps (190,000 objects x 4 conversions), single thread, "
+                      f"{dt * 1e3:.1f} ms per step"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,21 +1,438 @@
-// Batched conversion (placeholder entry points until the batch engine lands).
+// Batched conversion: many collections through one launch of a captured
+// HIP graph.  Every item is planned as for rl_convert; the steps of all
+// items are gathered into device-resident tables by kernel kind, and three
+// persistent kernels (dense tiles, tile-total scans and rebases, member
+// gathers) walk those tables taking tickets.  The graph holds the three
+// launches; a per-collection loop over rl_convert plans is kept for
+// comparison.  An autotuner times candidate tile shapes (and block widths
+// of "auto" AoSoA destinations) on the batch itself and keeps the fastest,
+// remembering the choice in a JSON cache.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+
 #include "plan.h"
 #include "rl_internal.h"
 
 using namespace rl;
 
-struct rl_batch {
-  int unused;
+namespace {
+
+constexpr uint32_t kAutoWidths[] = {32, 64, 128};
+
+struct Item {
+  const rl_layout* src_layout;
+  const rl_layout* dst_layout;        // as given (width 0 = auto)
+  std::unique_ptr<rl_layout> resolved;  // auto width resolved
+  uint64_t src_cap, dst_cap, n;
+  std::vector<void*> src_bufs, dst_bufs;
+  std::vector<uint64_t> src_mcap, dst_mcap;
+  rl_view src_view() const {
+    return rl_view{src_layout, src_cap, src_mcap.empty() ? nullptr : src_mcap.data(),
+                   const_cast<void* const*>(src_bufs.data())};
+  }
+  rl_view dst_view() const {
+    return rl_view{resolved ? resolved.get() : dst_layout, dst_cap,
+                   dst_mcap.empty() ? nullptr : dst_mcap.data(), const_cast<void* const*>(dst_bufs.data())};
+  }
+  bool auto_width() const { return dst_layout->kind == RL_AOSOA && dst_layout->width == 0; }
 };
 
-extern "C" rl_status rl_batch_create(const rl_batch_opts*, rl_batch** out) {
-  if (out) *out = nullptr;
-  return fail(RL_EUNSUPPORTED, "batches are not available yet");
+struct Config {
+  uint32_t tile = 256, threads = 256, grid = 2048, width = 64;
+};
+
+struct DeviceTables {
+  uint8_t* mem = nullptr;
+  BatchTables t{};
+  uint32_t dense_lds = 0, gather_lds = 0;
+  void release() {
+    if (mem) (void)hipFree(mem);
+    mem = nullptr;
+  }
+};
+
+}  // namespace
+
+struct rl_batch {
+  int autotune = 0;
+  std::string cache;
+  std::vector<Item> items;
+  bool finalized = false;
+  Config cfg;
+  std::vector<Plan> plans;   // per item (for the launch loop)
+  DeviceTables dev;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double tuned_us = 0;
+  ~rl_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    dev.release();
+  }
+};
+
+namespace {
+
+rl_status resolve_widths(rl_batch* b, uint32_t width) {
+  for (auto& it : b->items) {
+    if (!it.auto_width()) continue;
+    it.resolved.reset(new rl_layout(*it.dst_layout));
+    it.resolved->width = width;
+  }
+  return RL_OK;
 }
-extern "C" rl_status rl_batch_add(rl_batch*, const rl_view*, const rl_view*, uint64_t) { return fail(RL_EUNSUPPORTED, "batches"); }
-extern "C" rl_status rl_batch_finalize(rl_batch*, void*) { return fail(RL_EUNSUPPORTED, "batches"); }
-extern "C" rl_status rl_batch_launch(rl_batch*, void*) { return fail(RL_EUNSUPPORTED, "batches"); }
-extern "C" rl_status rl_batch_launch_loop(rl_batch*, void*) { return fail(RL_EUNSUPPORTED, "batches"); }
-extern "C" rl_status rl_batch_item_width(const rl_batch*, uint32_t, uint32_t*) { return fail(RL_EUNSUPPORTED, "batches"); }
-extern "C" rl_status rl_batch_shape(const rl_batch*, uint32_t*, uint32_t*, uint32_t*) { return fail(RL_EUNSUPPORTED, "batches"); }
-extern "C" void rl_batch_destroy(rl_batch*) {}
+
+rl_status plan_all(rl_batch* b, const Config& c) {
+  b->plans.clear();
+  PlanShape shape;
+  shape.tile = c.tile;
+  shape.threads = c.threads;
+  for (auto& it : b->items) {
+    Plan p;
+    if (it.n) {
+      rl_view s = it.src_view(), d = it.dst_view();
+      rl_status st = make_plan(s, d, it.n, shape, &p);
+      if (st) return st;
+    }
+    b->plans.push_back(std::move(p));
+  }
+  return RL_OK;
+}
+
+rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
+  std::vector<DenseDesc> dense;
+  std::vector<GatherDesc> gather;
+  std::vector<ScanTotalsDesc> totals;
+  std::vector<RebaseDesc> rebase;
+  std::vector<uint64_t> dprefix{0}, gprefix{0};
+  uint32_t dense_lds = 0, gather_lds = 0;
+  for (const Plan& p : b->plans)
+    for (const Step& s : p.steps) {
+      switch (s.kind) {
+        case Step::DENSE:
+          dense.push_back(s.dense);
+          dprefix.push_back(dprefix.back() + dense_tiles(s.dense));
+          dense_lds = std::max(dense_lds, dense_lds_bytes(s.dense));
+          break;
+        case Step::GATHER:
+          gather.push_back(s.gather);
+          gprefix.push_back(gprefix.back() + (s.gather.n + s.gather.tile - 1) / s.gather.tile);
+          gather_lds = std::max(gather_lds, (2 * s.gather.tile + 1) * 8 + s.gather.tile * 4);
+          break;
+        case Step::SCAN_TOTALS: totals.push_back(s.totals); break;
+        case Step::REBASE: rebase.push_back(s.rebase); break;
+      }
+    }
+  if (dprefix.back() >= (1ull << 32) || gprefix.back() >= (1ull << 32))
+    return fail(RL_EUNSUPPORTED, "batch has more than 2^32 tiles");
+  // one allocation: tables + prefix arrays + counters
+  size_t sz = 0;
+  auto reserve = [&](size_t bytes) { size_t at = sz; sz += (bytes + 255) & ~size_t(255); return at; };
+  const size_t o_dense = reserve(dense.size() * sizeof(DenseDesc));
+  const size_t o_dp = reserve(dprefix.size() * 8);
+  const size_t o_gather = reserve(gather.size() * sizeof(GatherDesc));
+  const size_t o_gp = reserve(gprefix.size() * 8);
+  const size_t o_tot = reserve(totals.size() * sizeof(ScanTotalsDesc));
+  const size_t o_reb = reserve(rebase.size() * sizeof(RebaseDesc));
+  const size_t o_ctr = reserve(16);
+  std::vector<uint8_t> host(sz, 0);
+  memcpy(host.data() + o_dense, dense.data(), dense.size() * sizeof(DenseDesc));
+  memcpy(host.data() + o_dp, dprefix.data(), dprefix.size() * 8);
+  memcpy(host.data() + o_gather, gather.data(), gather.size() * sizeof(GatherDesc));
+  memcpy(host.data() + o_gp, gprefix.data(), gprefix.size() * 8);
+  memcpy(host.data() + o_tot, totals.data(), totals.size() * sizeof(ScanTotalsDesc));
+  memcpy(host.data() + o_reb, rebase.data(), rebase.size() * sizeof(RebaseDesc));
+  out->release();
+  hipError_t e = hipMalloc(&out->mem, sz);
+  if (e != hipSuccess) return fail(RL_ENOMEM, "batch tables (%zu bytes): %s", sz, hipGetErrorString(e));
+  if ((e = hipMemcpy(out->mem, host.data(), sz, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(batch tables)");
+  BatchTables& t = out->t;
+  t.dense = (const DenseDesc*)(out->mem + o_dense);
+  t.dense_prefix = (const uint64_t*)(out->mem + o_dp);
+  t.n_dense = (uint32_t)dense.size();
+  t.dense_tiles = (uint32_t)dprefix.back();
+  t.gather = (const GatherDesc*)(out->mem + o_gather);
+  t.gather_prefix = (const uint64_t*)(out->mem + o_gp);
+  t.n_gather = (uint32_t)gather.size();
+  t.gather_tiles = (uint32_t)gprefix.back();
+  t.totals = (const ScanTotalsDesc*)(out->mem + o_tot);
+  t.n_totals = (uint32_t)totals.size();
+  t.rebase = (const RebaseDesc*)(out->mem + o_reb);
+  t.n_rebase = (uint32_t)rebase.size();
+  t.counters = (uint32_t*)(out->mem + o_ctr);
+  out->dense_lds = dense_lds;
+  out->gather_lds = gather_lds;
+  (void)c;
+  return RL_OK;
+}
+
+rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s) {
+  hipError_t e = launch_batch(d.t, c.threads, c.grid, d.dense_lds, d.gather_lds, s);
+  return e == hipSuccess ? RL_OK : hip_fail(e, "batch launch");
+}
+
+// Signature of a batch for the tuning cache: item shapes with object counts
+// bucketed by powers of two, and the device.
+std::string signature(const rl_batch* b) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+  for (const auto& it : b->items) {
+    for (const rl_layout* L : {it.src_layout, it.dst_layout}) {
+      mix((uint64_t)L->kind);
+      mix(L->width);
+      mix(L->stride);
+      for (auto t : L->storage) mix((uint64_t)t);
+      mix(L->schema->members.size());
+    }
+    uint64_t bucket = 0;
+    while ((1ull << bucket) < it.n) ++bucket;
+    mix(bucket);
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    for (const char* p = prop.gcnArchName; *p; ++p) mix((uint64_t)*p);
+    mix((uint64_t)prop.multiProcessorCount);
+  }
+  char buf[32];
+  snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return buf;
+}
+
+// The cache is a JSON object {"<signature>": {"tile": .., "threads": ..,
+// "grid": .., "width": .., "us": ..}, ...}, one entry per line.
+bool cache_lookup(const std::string& path, const std::string& sig, Config* c) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  const std::string key = "\"" + sig + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(key) == std::string::npos) continue;
+    auto num = [&](const char* name, uint32_t* v) {
+      const std::string k = std::string("\"") + name + "\":";
+      size_t p = line.find(k);
+      if (p == std::string::npos) return false;
+      *v = (uint32_t)strtoul(line.c_str() + p + k.size(), nullptr, 10);
+      return true;
+    };
+    Config t;
+    if (num("tile", &t.tile) && num("threads", &t.threads) && num("grid", &t.grid) && num("width", &t.width)) {
+      *c = t;
+      return true;
+    }
+  }
+  return false;
+}
+
+void cache_store(const std::string& path, const std::string& sig, const Config& c, double us) {
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+      if (line.size() < 4 || line[0] == '{' || line[0] == '}') continue;
+      if (line.find("\"" + sig + "\"") != std::string::npos) continue;
+      if (!line.empty() && line.back() == ',') line.pop_back();
+      keep.push_back(line);
+    }
+  }
+  char buf[256];
+  snprintf(buf, sizeof buf, "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"us\":%.2f}",
+           sig.c_str(), c.tile, c.threads, c.grid, c.width, us);
+  keep.push_back(buf);
+  std::ofstream o(path + ".tmp");
+  o << "{\n";
+  for (size_t k = 0; k < keep.size(); ++k) o << keep[k] << (k + 1 < keep.size() ? ",\n" : "\n");
+  o << "}\n";
+  o.close();
+  rename((path + ".tmp").c_str(), path.c_str());
+}
+
+// Time one configuration (direct launches of the batch kernels).
+rl_status time_config(rl_batch* b, const Config& c, hipStream_t s, double* us) {
+  rl_status st = resolve_widths(b, c.width);
+  if (!st) st = plan_all(b, c);
+  DeviceTables d;
+  if (!st) st = build_tables(b, c, &d);
+  if (st) { d.release(); return st; }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  for (int k = 0; k < 2 && !st; ++k) st = launch_tables(d, c, s);
+  const int reps = 5;
+  (void)hipEventRecord(e0, s);
+  for (int k = 0; k < reps && !st; ++k) st = launch_tables(d, c, s);
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (!st && e != hipSuccess) st = hip_fail(e, "tuning run");
+  if (!st) (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  d.release();
+  *us = ms * 1000.0 / reps;
+  return st;
+}
+
+rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
+  const bool any_auto = std::any_of(b->items.begin(), b->items.end(), [](const Item& i) { return i.auto_width(); });
+  double best_us = 1e30;
+  Config bc;
+  for (uint32_t tile : {128u, 256u, 512u, 1024u})
+    for (uint32_t threads : {256u, 512u})
+      for (uint32_t grid : {1024u, 2048u, 4096u}) {
+        Config c{tile, threads, grid, 64};
+        double us;
+        rl_status st = time_config(b, c, s, &us);
+        if (st) return st;
+        if (us < best_us) { best_us = us; bc = c; }
+      }
+  if (any_auto)
+    for (uint32_t w : kAutoWidths) {
+      Config c = bc;
+      c.width = w;
+      double us;
+      rl_status st = time_config(b, c, s, &us);
+      if (st) return st;
+      if (us < best_us * 0.98) { best_us = us; bc = c; }
+    }
+  *best = bc;
+  b->tuned_us = best_us;
+  return RL_OK;
+}
+
+}  // namespace
+
+extern "C" rl_status rl_batch_create(const rl_batch_opts* opts, rl_batch** out) {
+  if (!out) return fail(RL_EINVAL, "rl_batch_create: out is NULL");
+  auto* b = new rl_batch();
+  if (opts) {
+    b->autotune = opts->autotune;
+    if (opts->tune_cache) b->cache = opts->tune_cache;
+  }
+  if (b->cache.empty())
+    if (const char* p = getenv("RL_TUNE_CACHE")) b->cache = p;
+  *out = b;
+  return RL_OK;
+}
+
+extern "C" rl_status rl_batch_add(rl_batch* b, const rl_view* src, const rl_view* dst, uint64_t n) {
+  if (!b) return fail(RL_EINVAL, "batch is NULL");
+  if (b->finalized) return fail(RL_EBUSY, "batch already finalized");
+  std::vector<Range> rs, rd;
+  rl_status st = validate_view(src, n, "src", &rs, true);
+  if (st) return st;
+  if ((st = validate_view(dst, n, "dst", &rd, true))) return st;
+  if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
+  if ((st = check_overlap(rs, rd))) return st;
+  if (src->layout->kind == RL_AOSOA && src->layout->width == 0)
+    return fail(RL_EINVAL, "a source block width cannot be auto");
+  if (!src->layout->schema->members.empty() && src->layout->kind == RL_AOS && dst->layout->kind == RL_AOS)
+    return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
+  Item it;
+  it.src_layout = src->layout;
+  it.dst_layout = dst->layout;
+  it.src_cap = src->capacity;
+  it.dst_cap = dst->capacity;
+  it.n = n;
+  it.src_bufs.assign(src->buffers, src->buffers + layout_n_buffers(src->layout));
+  it.dst_bufs.assign(dst->buffers, dst->buffers + layout_n_buffers(dst->layout));
+  const size_t ng = src->layout->schema->members.size();
+  if (ng) {
+    it.src_mcap.assign(src->member_capacity, src->member_capacity + ng);
+    it.dst_mcap.assign(dst->member_capacity, dst->member_capacity + ng);
+  }
+  b->items.push_back(std::move(it));
+  return RL_OK;
+}
+
+extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
+  if (!b) return fail(RL_EINVAL, "batch is NULL");
+  if (b->finalized) return fail(RL_EBUSY, "batch already finalized");
+  hipStream_t s = (hipStream_t)stream;
+  Config c;
+  const std::string sig = signature(b);
+  bool have = false;
+  if (b->autotune) {
+    rl_status st = autotune(b, s, &c);
+    if (st) return st;
+    have = true;
+    if (!b->cache.empty()) cache_store(b->cache, sig, c, b->tuned_us);
+  } else if (!b->cache.empty()) {
+    have = cache_lookup(b->cache, sig, &c);
+  }
+  (void)have;
+  if (const char* v = getenv("RL_BATCH_TILE")) c.tile = (uint32_t)strtoul(v, nullptr, 10);
+  if (const char* v = getenv("RL_BATCH_GRID")) c.grid = (uint32_t)strtoul(v, nullptr, 10);
+  if (c.threads < 64 || c.threads > 1024 || c.threads % 64) c.threads = 256;
+  if (c.grid < 1) c.grid = 2048;
+  b->cfg = c;
+  rl_status st = resolve_widths(b, c.width);
+  if (!st) st = plan_all(b, c);
+  if (!st) st = build_tables(b, c, &b->dev);
+  if (st) return st;
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+  if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(e, "hipStreamBeginCapture");
+  st = launch_tables(b->dev, c, b->cap);
+  e = hipStreamEndCapture(b->cap, &b->graph);
+  if (st) return st;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return hip_fail(e, "hipGraphInstantiate");
+  b->finalized = true;
+  return RL_OK;
+}
+
+extern "C" rl_status rl_batch_launch(rl_batch* b, void* stream) {
+  if (!b || !b->finalized) return fail(RL_EINVAL, "batch not finalized");
+  if (!b->dev.t.dense_tiles && !b->dev.t.gather_tiles && !b->dev.t.n_totals && !b->dev.t.n_rebase) return RL_OK;
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+extern "C" rl_status rl_batch_launch_loop(rl_batch* b, void* stream) {
+  if (!b || !b->finalized) return fail(RL_EINVAL, "batch not finalized");
+  for (const Plan& p : b->plans) {
+    rl_status st = enqueue_plan(p, (hipStream_t)stream);
+    if (st) return st;
+  }
+  return RL_OK;
+}
+
+extern "C" rl_status rl_batch_item_width(const rl_batch* b, uint32_t item, uint32_t* w) {
+  if (!b || !w) return fail(RL_EINVAL, "NULL argument");
+  if (!b->finalized) return fail(RL_EINVAL, "batch not finalized");
+  if (item >= b->items.size()) return fail(RL_EINVAL, "no item %u", item);
+  const rl_layout* L = b->items[item].resolved ? b->items[item].resolved.get() : b->items[item].dst_layout;
+  *w = L->kind == RL_AOSOA ? L->width : 0;
+  return RL_OK;
+}
+
+extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t* threads, uint32_t* grid) {
+  if (!b) return fail(RL_EINVAL, "batch is NULL");
+  if (tile) *tile = b->cfg.tile;
+  if (threads) *threads = b->cfg.threads;
+  if (grid) *grid = b->cfg.grid;
+  return RL_OK;
+}
+
+extern "C" void rl_batch_destroy(rl_batch* b) {
+  if (!b) return;
+  if (b->finalized) (void)hipDeviceSynchronize();
+  delete b;
+}

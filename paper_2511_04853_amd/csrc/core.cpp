@@ -241,7 +241,8 @@ extern "C" rl_status rl_layout_create(const rl_schema* schema, const rl_layout_d
   L->obj_bytes = acc;
   if (acc > (uint32_t)kMaxObjBytes) { delete L; return fail(RL_EINVAL, "more than %d bytes per object", kMaxObjBytes); }
   if (L->kind == RL_AOSOA) {
-    if (L->width < 1 || L->width >= 65536) { delete L; return fail(RL_EINVAL, "AoSoA block width must be 1..65535"); }
+    // width 0: chosen by a batch ("auto"); buffers are sized for the widest candidate
+    if (L->width >= 65536) { delete L; return fail(RL_EINVAL, "AoSoA block width must be 0..65535"); }
   }
   if (L->kind == RL_AOS) {
     std::vector<uint64_t> nat;
@@ -326,7 +327,8 @@ void layout_buffer_bytes(const rl_layout* L, uint64_t n, const uint64_t* members
   if (L->kind == RL_SOA) {
     for (size_t c = 0; c < s->leaves.size(); ++c) bytes[k++] = n * type_size(L->storage[c]);
   } else {
-    bytes[k++] = (n + L->width - 1) / L->width * L->width * (uint64_t)L->obj_bytes;
+    const uint64_t w = L->width ? L->width : kAutoWidthMax;
+    bytes[k++] = (n + w - 1) / w * w * (uint64_t)L->obj_bytes;
   }
   for (size_t g = 0; g < s->members.size(); ++g) {
     bytes[k++] = (n + 1) * type_size(s->offset_types[g]);
@@ -446,12 +448,19 @@ PlanShape shape_from_env() {
 }
 }  // namespace rl
 
+namespace rl {
+bool auto_width(const rl_view* v) {
+  return v && v->layout && v->layout->kind == RL_AOSOA && v->layout->width == 0;
+}
+}  // namespace rl
+
 extern "C" rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t n, void* stream) {
   std::vector<Range> rs, rd;
   rl_status st = validate_view(src, n, "src", &rs, true);
   if (st) return st;
   st = validate_view(dst, n, "dst", &rd, true);
   if (st) return st;
+  if (auto_width(src) || auto_width(dst)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
   if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
   if ((st = check_overlap(rs, rd))) return st;
   if (!src->layout->schema->members.empty() && src->layout->kind == RL_AOS && dst->layout->kind == RL_AOS)
@@ -471,6 +480,7 @@ extern "C" rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t
   if (st) return st;
   if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
   if (group >= src->layout->schema->members.size()) return fail(RL_EINVAL, "no jagged group %u", group);
+  if (auto_width(src) || auto_width(dst)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
   if (dst->layout->kind == RL_AOS) return fail(RL_EUNSUPPORTED, "rl_offsets writes an offsets column (SoA/AoSoA dst)");
   // only the offsets column of dst is written
   const uint32_t ob = group_buffer(dst->layout, group);

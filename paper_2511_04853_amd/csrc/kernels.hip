@@ -362,8 +362,7 @@ __global__ void __launch_bounds__(1024) dense_kernel(const DenseDesc d) {
 // Exclusive scan of the per-tile totals left by the dense kernel's fused
 // scan (stored at entry tile * T), writing each tile's prefix there and the
 // grand total at entry n.  One work-group.
-__global__ void __launch_bounds__(1024) scan_totals_kernel(const ScanTotalsDesc d) {
-  __shared__ uint64_t wsum[17];
+__device__ void scan_totals_body(const ScanTotalsDesc& d, uint64_t* wsum) {
   const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
   uint64_t carry = 0;
   for (uint64_t c0 = 0; c0 < ntiles; c0 += blockDim.x) {
@@ -381,18 +380,21 @@ __global__ void __launch_bounds__(1024) scan_totals_kernel(const ScanTotalsDesc 
   }
 }
 
+__global__ void __launch_bounds__(1024) scan_totals_kernel(const ScanTotalsDesc d) {
+  __shared__ uint64_t wsum[17];
+  scan_totals_body(d, wsum);
+}
+
 // Add tile prefixes, then copy the members of the tile's objects from the
 // pool into the member columns.  One work-group per tile (grid-stride).
-__global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
-  extern __shared__ uint4 smem_raw[];
-  uint64_t* offs = reinterpret_cast<uint64_t*>(smem_raw);          // tile + 1
+__device__ void gather_tile(const GatherDesc& d, uint64_t t, uint8_t* smem) {
+  uint64_t* offs = reinterpret_cast<uint64_t*>(smem);               // tile + 1
   uint64_t* ptrs = offs + (d.tile + 1);                             // tile
   uint32_t* vlen = reinterpret_cast<uint32_t*>(ptrs + d.tile);      // tile: validated count
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
   const uint64_t limit = off_limit(d.off_type);
   const uint64_t pool_end = d.pool_bytes;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  {
     const uint64_t i0 = t * d.tile;
     const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, d.n - i0);
     const uint64_t prefix = load_off(d.offsets, d.off_type, i0);
@@ -407,7 +409,7 @@ __global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
       offs[o] = v & limit;
     }
     __syncthreads();
-    if (d.n_members == 0) continue;  // uniform: offsets only
+    if (d.n_members == 0) return;  // uniform: offsets only
     for (uint32_t o = tid; o < cnt; o += nt) {
       const uint8_t* rec = d.records + (i0 + o) * d.rec_stride;
       const uint64_t p = *reinterpret_cast<const uint64_t*>(rec + d.ptr_off);
@@ -449,13 +451,21 @@ __global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
   }
 }
 
+__global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
+  extern __shared__ uint4 smem_raw[];
+  const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    gather_tile(d, t, reinterpret_cast<uint8_t*>(smem_raw));
+    __syncthreads();
+  }
+}
+
 // Offsets column -> offsets column, rebased to start at 0, with the checks
 // of a well-formed source (non-decreasing, inside the source capacity) and
 // of the destination capacity.
-__global__ void rebase_kernel(const RebaseDesc d) {
+__device__ void rebase_range(const RebaseDesc& d, uint64_t begin, uint64_t step) {
   const uint64_t first = load_off(d.src, d.off_type, 0);
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= d.n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
+  for (uint64_t i = begin; i <= d.n; i += step) {
     const uint64_t a = load_off(d.src, d.off_type, i);
     if (d.dst) store_off(d.dst, d.off_type, i, a - first);
     if (i < d.n) {
@@ -468,7 +478,90 @@ __global__ void rebase_kernel(const RebaseDesc d) {
   }
 }
 
+__global__ void rebase_kernel(const RebaseDesc d) {
+  rebase_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
+}
+
 __global__ void clear_status_kernel(uint32_t* status) { *status = 0; }
+
+// ------------------------------------------------------------------ batches
+
+// Item of a flat tile space: binary search of the tile prefix (n + 1
+// entries, prefix[0] = 0) for the last item whose first tile is <= t.
+__device__ __forceinline__ uint32_t find_item(const uint64_t* prefix, uint32_t n, uint64_t t) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Next ticket of a persistent grid (one atomic per work-group, broadcast
+// through LDS).  Tickets are handed out in increasing order, so every
+// work-group runs until the tile space is exhausted.
+__device__ __forceinline__ uint32_t take_ticket(uint32_t* counter, uint32_t* slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1u);
+  __syncthreads();
+  const uint32_t t = *slot;
+  __syncthreads();
+  return t;
+}
+
+// The last work-group out resets the counters for the next launch (kernel
+// boundaries order the reset before the next launch's first ticket).
+__device__ __forceinline__ void retire(uint32_t* counter, uint32_t* done) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(done, 1u);
+    if (prev == gridDim.x - 1) {
+      atomicExch(counter, 0u);
+      atomicExch(done, 0u);
+    }
+  }
+}
+
+// Every dense step of every item: the tiles of all items form one space,
+// walked by a persistent grid taking tickets.
+__global__ void __launch_bounds__(1024) batch_dense_kernel(const BatchTables b) {
+  extern __shared__ uint4 smem_raw[];
+  __shared__ uint32_t ticket;
+  uint8_t* smem = reinterpret_cast<uint8_t*>(smem_raw);
+  while (true) {
+    const uint32_t t = take_ticket(b.counters + 0, &ticket);
+    if (t >= b.dense_tiles) break;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(find_item(b.dense_prefix, b.n_dense, t));
+    const DenseDesc& d = b.dense[item];
+    const uint64_t local = t - b.dense_prefix[item];
+    uint64_t count, base;
+    dense_count(d, &count, &base);
+    if (local * d.tile >= count) continue;   // device-side count below the planned bound
+    dense_tile(d, carve(smem, d), local, count, base);
+  }
+  retire(b.counters + 0, b.counters + 1);
+}
+
+// Tile-total scans (one work-group each) and offsets rebases.
+__global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
+  __shared__ uint64_t wsum[17];
+  const uint32_t j = blockIdx.x;
+  if (j < b.n_totals) scan_totals_body(b.totals[j], wsum);
+  else if (j - b.n_totals < b.n_rebase) rebase_range(b.rebase[j - b.n_totals], threadIdx.x, blockDim.x);
+}
+
+// Every gather tile of every jagged item, persistent like the dense kernel.
+__global__ void __launch_bounds__(1024) batch_gather_kernel(const BatchTables b) {
+  extern __shared__ uint4 smem_raw[];
+  __shared__ uint32_t ticket;
+  while (true) {
+    const uint32_t t = take_ticket(b.counters + 2, &ticket);
+    if (t >= b.gather_tiles) break;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(find_item(b.gather_prefix, b.n_gather, t));
+    gather_tile(b.gather[item], t - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw));
+    __syncthreads();
+  }
+  retire(b.counters + 2, b.counters + 3);
+}
 
 // ------------------------------------------------------------------ launchers
 
@@ -502,6 +595,26 @@ hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s) {
   const uint32_t grid = (uint32_t)((work + 255) / 256 < 4096 ? (work + 255) / 256 : 4096);
   hipLaunchKernelGGL(rebase_kernel, dim3(grid), dim3(256), 0, s, d);
   return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchTables& b, uint32_t threads, uint32_t grid, uint32_t dense_lds,
+                        uint32_t gather_lds, hipStream_t s) {
+  if (b.dense_tiles) {
+    hipLaunchKernelGGL(batch_dense_kernel, dim3(grid), dim3(threads), dense_lds, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.n_totals + b.n_rebase) {
+    hipLaunchKernelGGL(batch_misc_kernel, dim3(b.n_totals + b.n_rebase), dim3(1024), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.gather_tiles) {
+    hipLaunchKernelGGL(batch_gather_kernel, dim3(grid), dim3(threads), gather_lds, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_clear_status(uint32_t* status, hipStream_t s) {

@@ -67,5 +67,6 @@ rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t gro
                             const PlanShape& shape, Plan* plan);
 rl_status enqueue_plan(const Plan& plan, hipStream_t stream);
 PlanShape shape_from_env();
+bool auto_width(const rl_view* v);
 
 }  // namespace rl

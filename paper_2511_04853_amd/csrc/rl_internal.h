@@ -18,6 +18,7 @@ constexpr int kMaxGroups = 4;
 constexpr int kMaxObjBytes = 512;     // sum of leaf sizes on one side
 constexpr int kMaxUnits = 256;        // SoA images up to this many bytes per object use the unit table
 constexpr int kMaxExtent = 64;
+constexpr uint32_t kAutoWidthMax = 128; // "auto" AoSoA widths are 32, 64 or 128
 
 // Kinds of one side of a dense conversion (match rl_kind).
 enum SideKind : uint32_t { KIND_AOS = 0, KIND_SOA = 1, KIND_AOSOA = 2 };
@@ -134,6 +135,24 @@ struct RebaseDesc {
   uint32_t* status;
 };
 
+// Device-resident tables of a batch: every step of every item, grouped by
+// the kernel that runs it.  Prefix arrays have one entry per item plus one.
+struct BatchTables {
+  const DenseDesc* dense;
+  const uint64_t* dense_prefix;     // first tile of each dense step
+  uint32_t n_dense;
+  uint32_t dense_tiles;
+  const GatherDesc* gather;
+  const uint64_t* gather_prefix;
+  uint32_t n_gather;
+  uint32_t gather_tiles;
+  const ScanTotalsDesc* totals;
+  uint32_t n_totals;
+  uint32_t n_rebase;
+  const RebaseDesc* rebase;
+  uint32_t* counters;               // tickets and retire counts (4 words, zero between launches)
+};
+
 // ---- kernel launchers (kernels.hip) ----
 hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid,
                         hipStream_t s);
@@ -141,6 +160,8 @@ hipError_t launch_scan_totals(const ScanTotalsDesc& d, hipStream_t s);
 hipError_t launch_gather(const GatherDesc& d, uint32_t threads, hipStream_t s);
 hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s);
 hipError_t launch_clear_status(uint32_t* status, hipStream_t s);
+hipError_t launch_batch(const BatchTables& b, uint32_t threads, uint32_t grid, uint32_t dense_lds,
+                        uint32_t gather_lds, hipStream_t s);
 uint32_t dense_lds_bytes(const DenseDesc& d);
 uint64_t dense_tiles(const DenseDesc& d);
 

@@ -270,6 +270,7 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
   const rl_layout* SL = src->layout;
   const rl_layout* DL = dst->layout;
   if (SL->schema != DL->schema) return fail(RL_EINVAL, "src and dst use different schemas");
+  if (auto_width(src) || auto_width(dst)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
   const bool sh = is_host(SL->space), dh = is_host(DL->space);
   if (sh == dh) return fail(RL_EUNSUPPORTED, "rl_transfer needs one host and one device view (use rl_convert on device)");
   if (n == 0) return RL_OK;

@@ -16,7 +16,9 @@ class Pair:
         self.sp = schema_pair
         self.kind, self.width, self.storage = kind, width, storage
         self.lib = P.Layout(schema_pair.lib, kind, space=space, width=width, storage=storage)
-        self.orc = oracle.make_layout(schema_pair.orc, kind, width=width, storage=storage)
+        # an AoSoA width of 0 ("auto", chosen by a batch) has no oracle layout until resolved
+        self.orc = (None if kind == "aosoa" and width == 0
+                    else oracle.make_layout(schema_pair.orc, kind, width=width, storage=storage))
 
 
 class SchemaPair:

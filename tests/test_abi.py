@@ -94,7 +94,7 @@ def test_schema_validation():
 def test_layout_validation():
     sp = SchemaPair(W.CELL)
     with pytest.raises(P.RelayoutError) as e:
-        P.Layout(sp.lib, "aosoa", width=0)
+        P.Layout(sp.lib, "aosoa", width=70_000)
     assert e.value.status == P.RL_EINVAL
     with pytest.raises(P.RelayoutError):
         P.Layout(sp.lib, "soa", storage=["f32", "f32", "i8", "u16", "u32", "u32", "u64"])
@@ -159,3 +159,31 @@ def test_jagged_aos_to_aos_is_unsupported():
     a = _fake_view(sp.layout("aos"), 10, 1 << 40, [100])
     b = _fake_view(sp.layout("aos"), 10, 1 << 42, [100])
     assert P.lib().rl_convert(a.ref(), b.ref(), 0, ctypes.c_void_p(0)) == P.RL_EUNSUPPORTED
+
+
+def test_batch_validation_on_the_host():
+    sp = SchemaPair(W.CELL)
+    h = ctypes.c_void_p()
+    assert P.lib().rl_batch_create(None, ctypes.byref(h)) == P.RL_OK
+    a = _fake_view(sp.layout("aos"), 100, 1 << 40)
+    s = _fake_view(sp.layout("soa"), 100, 1 << 42)
+    auto = _fake_view(sp.layout("aosoa", width=0), 100, 1 << 43)
+    assert P.lib().rl_batch_add(h, a.ref(), s.ref(), 101) == P.RL_EINVAL        # over capacity
+    assert P.lib().rl_batch_add(h, auto.ref(), s.ref(), 10) == P.RL_EINVAL      # auto width as source
+    over = _fake_view(sp.layout("soa"), 100, (1 << 40) + 256)
+    assert P.lib().rl_batch_add(h, a.ref(), over.ref(), 10) == P.RL_EOVERLAP
+    assert P.lib().rl_batch_add(h, a.ref(), auto.ref(), 10) == P.RL_OK          # auto width as destination
+    w = ctypes.c_uint32()
+    assert P.lib().rl_batch_item_width(h, 0, ctypes.byref(w)) == P.RL_EINVAL    # not finalized
+    assert P.lib().rl_batch_launch(h, ctypes.c_void_p(0)) == P.RL_EINVAL
+    P.lib().rl_batch_destroy(h)
+
+
+def test_auto_width_layout_is_batch_only():
+    sp = SchemaPair(W.CELL)
+    auto = sp.layout("aosoa", width=0)
+    # buffers are sized for the widest candidate (128)
+    assert auto.lib.buffer_bytes(1000) == [8 * 128 * 27]
+    a = _fake_view(sp.layout("aos"), 100, 1 << 40)
+    d = _fake_view(auto, 100, 1 << 42)
+    assert P.lib().rl_convert(a.ref(), d.ref(), 10, ctypes.c_void_p(0)) == P.RL_EINVAL
