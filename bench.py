@@ -225,6 +225,17 @@ def h2d_rate(P, W, torch, stream, S, aos_dev, soa, v):
     dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in soa.buffer_bytes(n)]
     sv, dv = P.View(aos_h, n, [host]), P.View(soa, n, dst)
     res = {}
+    # the plain pinned -> device copy of the same bytes, for reference
+    raw = torch.empty(host.numel(), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        raw.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(20):
+        raw.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 20
+    res["plain_copy"] = {"us": round(dt * 1e6, 1), "link_GBps": round(host.numel() / dt / 1e9, 2)}
     for mode in ("staged", "zero_copy"):
         for _ in range(3):
             P.transfer(sv, dv, n, mode=mode)

@@ -180,6 +180,12 @@ struct DenseLds {
 
 __host__ __device__ __forceinline__ uint32_t round16(uint32_t x) { return (x + 15u) & ~15u; }
 
+// Byte unit of object size that SoA image vector v belongs to
+// (v / (tile / 16), by multiplier).
+__device__ __forceinline__ uint32_t unit_of(const DenseDesc& d, uint32_t v) {
+  return d.tile == 16 ? v : __umulhi(v, d.vt_magic);
+}
+
 // Load one side's tile into its LDS image.  `idx0` is the index of the
 // tile's first object on that side.
 __device__ void load_side(const DenseDesc& d, uint8_t* img, uint64_t idx0, uint32_t cnt,
@@ -198,8 +204,7 @@ __device__ void load_side(const DenseDesc& d, uint8_t* img, uint64_t idx0, uint3
     const uint32_t nv = vt * s.obj_bytes;
     v4u* lv = reinterpret_cast<v4u*>(img);
     for (uint32_t v = tid; v < nv; v += nt) {
-      const uint32_t u = v / vt;
-      const uint32_t c = d.unit_src[u];
+      const uint32_t c = d.unit_src[unit_of(d, v)];
       const LeafDesc& L = d.leaf[c];
       const uint32_t first_v = L.src_off >> 4;   // tile * prefix / 16
       const v4u* col = reinterpret_cast<const v4u*>(L.src_col + idx0 * L.src_size);
@@ -227,8 +232,7 @@ __device__ void store_side(const DenseDesc& d, const uint8_t* img, uint64_t idx0
     const uint32_t nv = vt * s.obj_bytes;
     const v4u* lv = reinterpret_cast<const v4u*>(img);
     for (uint32_t v = tid; v < nv; v += nt) {
-      const uint32_t u = v / vt;
-      const uint32_t c = d.unit_dst[u];
+      const uint32_t c = d.unit_dst[unit_of(d, v)];
       const LeafDesc& L = d.leaf[c];
       const uint32_t first_v = L.dst_off >> 4;
       v4u* col = reinterpret_cast<v4u*>(L.dst_col + idx0 * L.dst_size);
@@ -243,49 +247,120 @@ __device__ void store_side(const DenseDesc& d, const uint8_t* img, uint64_t idx0
   }
 }
 
-// Convert one tile.  `d` is read from kernel arguments or global memory
-// (uniform fields through the scalar cache).  `count` is the number of objects to
-// convert, `base` the source index of object 0 (device-side member bases).
-__device__ void dense_tile(const DenseDesc& d, const DenseLds& m, uint64_t tile, uint64_t count,
-                           uint64_t base) {
+__device__ __forceinline__ DenseLds carve(uint8_t* smem, const DenseDesc& d) {
+  DenseLds m;
+  m.src = smem;
+  m.dst = smem + round16(d.src.image_bytes);
+  m.wsum = reinterpret_cast<uint64_t*>(m.dst + round16(d.dst.image_bytes));
+  return m;
+}
+
+// Count and source base of a conversion: host-given, or read on the device
+// from an offsets column (member columns of a jagged group).
+__device__ __forceinline__ void dense_count(const DenseDesc& d, uint64_t* count, uint64_t* base) {
+  if (d.count_offsets) {
+    const uint64_t b = load_off(d.count_offsets, d.count_off_type, 0);
+    const uint64_t e = load_off(d.count_offsets, d.count_off_type, d.count_index);
+    uint64_t c = e >= b ? e - b : 0;
+    if (c > d.n) c = d.n;   // never beyond the destination capacity
+    if (b > d.src_capacity) c = 0;
+    else if (c > d.src_capacity - b) c = d.src_capacity - b;  // nor the source's
+    *count = c;
+    *base = b;
+  } else {
+    *count = d.n;
+    *base = 0;
+  }
+}
+
+// ------------------------------------------------------------------ tile pipeline
+//
+// A work-group converts a sequence of tiles.  While tile k is moved inside
+// LDS and written out, the 16-byte source vectors of tile k+1 are already
+// in flight into registers: global loads and stores of neighbouring tiles
+// overlap, and the in-order vector-memory counter never makes a tile's
+// loads wait behind the previous tile's stores.
+
+constexpr uint32_t kPrefetch = 4;   // 16-byte vectors per thread held in registers
+
+struct TileJob {
+  uint32_t valid;       // 0: no more work
+  uint32_t item;        // descriptor index (batches)
+  uint64_t tile, count, base;
+};
+
+// A full tile of a source whose runs are 16-byte aligned, small enough for
+// the register buffer, can be fetched ahead.
+__device__ __forceinline__ bool fetchable(const DenseDesc& d, const TileJob& j) {
+  if (!d.prefetch || j.base != 0) return false;
+  if ((j.tile + 1) * d.tile > j.count) return false;
+  return (d.src.image_bytes >> 4) <= kPrefetch * blockDim.x;
+}
+
+__device__ __forceinline__ void fetch(const DenseDesc& d, const TileJob& j, v4u* r) {
+  const uint32_t nv = d.src.image_bytes >> 4;
+  const uint64_t idx0 = j.tile * d.tile;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint64_t i0 = tile * d.tile;
-  const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, count - i0);
-  const bool full = cnt == d.tile;
-  // Source index alignment: a device-side base breaks the 16-byte runs of
-  // SoA columns; the per-column path then handles any alignment.
-  const bool aligned_src = full && (base == 0);
-
-  load_side(d, m.src, i0 + base, cnt, aligned_src);
-  if (d.zero_dst || (!full && d.dst.kind == KIND_AOSOA)) {
-    v4u* z = reinterpret_cast<v4u*>(m.dst);
-    const uint32_t nv = d.dst.image_bytes >> 4;
-    for (uint32_t v = tid; v < nv; v += nt) z[v] = v4u{0u, 0u, 0u, 0u};
-  }
-  __syncthreads();
-
-  // Fused local scan of jagged counts held in the source records.
-  if (d.scan_offsets) {
-    const uint32_t per = (d.tile + nt - 1) / nt;
-    const uint32_t o0 = tid * per;
-    uint64_t sum = 0;
-    for (uint32_t k = 0; k < per; ++k) {
-      const uint32_t o = o0 + k;
-      if (o < cnt) sum += *reinterpret_cast<const uint32_t*>(m.src + o * d.src.stride + d.scan_len_off);
+  if (d.src.kind != KIND_SOA) {
+    // AoS records / AoSoA blocks: one contiguous run
+    const uint64_t per = d.src.kind == KIND_AOS ? d.src.stride : d.src.obj_bytes;
+    const v4u* run = reinterpret_cast<const v4u*>(d.src.base + idx0 * per);
+#pragma unroll
+    for (uint32_t k = 0; k < kPrefetch; ++k) {
+      const uint32_t v = tid + k * nt;
+      if (v < nv) r[k] = run[v];
     }
-    uint64_t total;
-    uint64_t run = block_exclusive_scan(sum, m.wsum, &total);
-    for (uint32_t k = 0; k < per; ++k) {
-      const uint32_t o = o0 + k;
-      if (o < cnt) {
-        // entry i0 of a tile holds the tile total until the totals pass
-        store_off(d.scan_offsets, d.scan_off_type, i0 + o, o == 0 ? total : run);
-        run += *reinterpret_cast<const uint32_t*>(m.src + o * d.src.stride + d.scan_len_off);
-      }
-    }
-    if (tid == 0 && total > off_limit(d.scan_off_type)) flag(d.status, ST_FLAG_OVERFLOW);
+    return;
   }
+  // SoA image: column c's run starts at vector tile * prefix(c) / 16
+#pragma unroll
+  for (uint32_t k = 0; k < kPrefetch; ++k) {
+    const uint32_t v = tid + k * nt;
+    if (v < nv) {
+      const LeafDesc& L = d.leaf[d.unit_src[unit_of(d, v)]];
+      r[k] = reinterpret_cast<const v4u*>(L.src_col + idx0 * L.src_size)[v - (L.src_off >> 4)];
+    }
+  }
+}
 
+__device__ __forceinline__ void commit(const DenseDesc& d, const v4u* r, uint8_t* img) {
+  const uint32_t nv = d.src.image_bytes >> 4;
+  v4u* lv = reinterpret_cast<v4u*>(img);
+#pragma unroll
+  for (uint32_t k = 0; k < kPrefetch; ++k) {
+    const uint32_t v = threadIdx.x + k * blockDim.x;
+    if (v < nv) lv[v] = r[k];
+  }
+}
+
+// Fused local scan of jagged counts held in the source records: writes the
+// tile's exclusive offsets (entry i0 holds the tile total until the totals
+// pass replaces it with the tile's prefix).
+__device__ void scan_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t per = (d.tile + nt - 1) / nt;
+  const uint32_t o0 = tid * per;
+  uint64_t sum = 0;
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t o = o0 + k;
+    if (o < cnt) sum += *reinterpret_cast<const uint32_t*>(m.src + o * d.src.stride + d.scan_len_off);
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(sum, m.wsum, &total);
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t o = o0 + k;
+    if (o < cnt) {
+      store_off(d.scan_offsets, d.scan_off_type, i0 + o, o == 0 ? total : run);
+      run += *reinterpret_cast<const uint32_t*>(m.src + o * d.src.stride + d.scan_len_off);
+    }
+  }
+  if (tid == 0 && total > off_limit(d.scan_off_type)) flag(d.status, ST_FLAG_OVERFLOW);
+}
+
+// Move every leaf value of the tile from the source image to the
+// destination image.
+__device__ void transform_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
     const LeafDesc& L = d.leaf[c];
     if (L.op == OP_PTR || L.op == OP_LEN) {
@@ -313,48 +388,76 @@ __device__ void dense_tile(const DenseDesc& d, const DenseLds& m, uint64_t tile,
       move_value(dp, sp, L);
     }
   }
-  __syncthreads();
-  store_side(d, m.dst, i0, cnt, full);
-  __syncthreads();
 }
 
-__device__ __forceinline__ DenseLds carve(uint8_t* smem, const DenseDesc& d) {
-  DenseLds m;
-  uint32_t off = 0;
-  m.src = smem + off;
-  off += round16(d.src.image_bytes);
-  m.dst = smem + off;
-  off += round16(d.dst.image_bytes);
-  m.wsum = reinterpret_cast<uint64_t*>(smem + off);
-  return m;
-}
-
-// Count and source base of a conversion: host-given, or read on the device
-// from an offsets column (member columns of a jagged group).
-__device__ __forceinline__ void dense_count(const DenseDesc& d, uint64_t* count, uint64_t* base) {
-  if (d.count_offsets) {
-    const uint64_t b = load_off(d.count_offsets, d.count_off_type, 0);
-    const uint64_t e = load_off(d.count_offsets, d.count_off_type, d.count_index);
-    uint64_t c = e >= b ? e - b : 0;
-    if (c > d.n) c = d.n;   // never beyond the destination capacity
-    if (b > d.src_capacity) c = 0;
-    else if (c > d.src_capacity - b) c = d.src_capacity - b;  // nor the source's
-    *count = c;
-    *base = b;
-  } else {
-    *count = d.n;
-    *base = 0;
+// Convert the tiles handed out by `next` (a functor returning TileJob);
+// `desc(item)` gives a job's descriptor.  (Jobs carry an index, not a
+// pointer: the address of a kernel-argument descriptor must not escape
+// into a loop-carried value, or the compiler copies it to scratch.)
+template <class Next, class Desc>
+__device__ void dense_pipeline(uint8_t* smem, Next next, Desc desc) {
+  v4u regs[kPrefetch];
+  TileJob cur = next();
+  bool in_regs = false;
+  if (cur.valid && fetchable(desc(cur.item), cur)) {
+    fetch(desc(cur.item), cur, regs);
+    in_regs = true;
+  }
+  while (cur.valid) {
+    const DenseDesc& d = desc(cur.item);
+    const DenseLds m = carve(smem, d);
+    const uint64_t i0 = cur.tile * d.tile;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, cur.count - i0);
+    const bool full = cnt == d.tile;
+    // 1. source image
+    if (in_regs) commit(d, regs, m.src);
+    else load_side(d, m.src, i0 + cur.base, cnt, full && cur.base == 0);
+    __syncthreads();
+    // 2. start fetching the next tile
+    const TileJob nxt = next();
+    in_regs = false;
+    if (nxt.valid && fetchable(desc(nxt.item), nxt)) {
+      fetch(desc(nxt.item), nxt, regs);
+      in_regs = true;
+    }
+    // 3. zero-filled destination where padding or unused block slots exist
+    if (d.zero_dst || (!full && d.dst.kind == KIND_AOSOA)) {
+      v4u* z = reinterpret_cast<v4u*>(m.dst);
+      const uint32_t nv = d.dst.image_bytes >> 4;
+      for (uint32_t v = threadIdx.x; v < nv; v += blockDim.x) z[v] = v4u{0u, 0u, 0u, 0u};
+      __syncthreads();
+    }
+    // 4. counts scan and value moves inside LDS
+    if (d.scan_offsets) scan_tile(d, m, i0, cnt);
+    transform_tile(d, m, i0, cnt);
+    __syncthreads();
+    // 5. destination image out
+    store_side(d, m.dst, i0, cnt, full);
+    cur = nxt;
   }
 }
 
+// Tiles blockIdx.x, blockIdx.x + gridDim.x, ... of one conversion.
+struct StridedTiles {
+  uint64_t t, ntiles, count, base;
+  __device__ TileJob operator()() {
+    TileJob j{0, 0, 0, count, base};
+    if (t < ntiles) {
+      j.valid = 1;
+      j.tile = t;
+      t += gridDim.x;
+    }
+    return j;
+  }
+};
+
 __global__ void __launch_bounds__(1024) dense_kernel(const DenseDesc d) {
   extern __shared__ uint4 smem_raw[];
-  uint8_t* smem = reinterpret_cast<uint8_t*>(smem_raw);
-  const DenseLds m = carve(smem, d);
   uint64_t count, base;
   dense_count(d, &count, &base);
-  const uint64_t ntiles = (count + d.tile - 1) / d.tile;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) dense_tile(d, m, t, count, base);
+  dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw),
+                 StridedTiles{blockIdx.x, (count + d.tile - 1) / d.tile, count, base},
+                 [&](uint32_t) -> const DenseDesc& { return d; });
 }
 
 // ------------------------------------------------------------------ offsets
@@ -526,18 +629,20 @@ __device__ __forceinline__ void retire(uint32_t* counter, uint32_t* done) {
 __global__ void __launch_bounds__(1024) batch_dense_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
   __shared__ uint32_t ticket;
-  uint8_t* smem = reinterpret_cast<uint8_t*>(smem_raw);
-  while (true) {
-    const uint32_t t = take_ticket(b.counters + 0, &ticket);
-    if (t >= b.dense_tiles) break;
-    const uint32_t item = __builtin_amdgcn_readfirstlane(find_item(b.dense_prefix, b.n_dense, t));
-    const DenseDesc& d = b.dense[item];
-    const uint64_t local = t - b.dense_prefix[item];
-    uint64_t count, base;
-    dense_count(d, &count, &base);
-    if (local * d.tile >= count) continue;   // device-side count below the planned bound
-    dense_tile(d, carve(smem, d), local, count, base);
-  }
+  dense_pipeline(
+      reinterpret_cast<uint8_t*>(smem_raw),
+      [&]() {
+        while (true) {
+          const uint32_t t = take_ticket(b.counters + 0, &ticket);
+          if (t >= b.dense_tiles) return TileJob{0, 0, 0, 0, 0};
+          const uint32_t item = __builtin_amdgcn_readfirstlane(find_item(b.dense_prefix, b.n_dense, t));
+          const DenseDesc& d = b.dense[item];
+          TileJob j{1, item, t - b.dense_prefix[item], 0, 0};
+          dense_count(d, &j.count, &j.base);
+          if (j.tile * d.tile < j.count) return j;   // else: beyond a device-side count
+        }
+      },
+      [&](uint32_t item) -> const DenseDesc& { return b.dense[item]; });
   retire(b.counters + 0, b.counters + 1);
 }
 

@@ -116,6 +116,9 @@ rl_status build_dense(const SideSpec& s, const SideSpec& d, uint64_t n, uint32_t
   fill_side(d, db, k.dst);
   k.n = n;
   k.tile = tile;
+  // umulhi(v, magic) == v / (tile / 16) for v < 2^17, 2 <= tile / 16 <= 256
+  // (tile == 16 is handled without it)
+  k.vt_magic = tile <= 16 ? 0 : (uint32_t)(((1ull << 32) + tile / 16 - 1) / (tile / 16));
   k.n_leaves = nl;
   uint32_t sp = 0, dp = 0;
   for (uint32_t c = 0; c < nl; ++c) {
@@ -146,6 +149,10 @@ rl_status build_dense(const SideSpec& s, const SideSpec& d, uint64_t n, uint32_t
     for (uint32_t c = 0; c < nl; ++c)
       for (uint32_t b = 0; b < k.leaf[c].src_size; ++b) k.unit_src[u++] = (uint8_t)c;
   }
+  // full source tiles can be fetched ahead as 16-byte vectors when every
+  // run starts 16-byte aligned (tiles hold a multiple of 16 objects)
+  if (s.kind == KIND_SOA) k.prefetch = k.units_src;
+  else k.prefetch = ((uintptr_t)s.base & 15) == 0 && sb + (s.kind == KIND_AOS ? s.stride : 0) > 0;
   if (d.kind == KIND_SOA && db <= (uint32_t)kMaxUnits && db > 0 && cols_aligned16(d)) {
     k.units_dst = 1;
     uint32_t u = 0;

@@ -85,6 +85,8 @@ struct DenseDesc {
   uint32_t* status;        // device status word
   uint32_t units_src;      // 1: SoA source, full tiles walk the image by unit_src
   uint32_t units_dst;      // 1: SoA destination, full tiles walk the image by unit_dst
+  uint32_t prefetch;       // 1: full source tiles are 16-byte aligned runs (fetched ahead)
+  uint32_t vt_magic;       // ceil(2^32 / (tile / 16)): SoA image vector -> byte unit
   uint64_t src_capacity;   // with count_offsets: source member capacity (count <= it - base)
   LeafDesc leaf[kMaxLeaves];
   uint8_t unit_src[kMaxUnits];   // SoA image: byte unit of object size -> leaf
