@@ -433,6 +433,10 @@ __device__ void dense_pipeline(uint8_t* smem, Next next, Desc desc) {
     __syncthreads();
     // 5. destination image out
     store_side(d, m.dst, i0, cnt, full);
+    // A next tile of another descriptor carves LDS differently: its source
+    // image may cover this tile's destination image, which other threads
+    // may still be reading.
+    if (nxt.valid && nxt.item != cur.item) __syncthreads();
     cur = nxt;
   }
 }
