@@ -88,16 +88,6 @@ __device__ __forceinline__ void l2g(uint8_t* g, const uint8_t* lds, uint32_t byt
   }
 }
 
-// Byte address of leaf value `obj` inside a side's LDS image.
-__device__ __forceinline__ uint32_t image_addr(const SideDesc& s, uint32_t obj, uint32_t off,
-                                               uint32_t size) {
-  if (s.kind == KIND_AOS) return obj * s.stride + off;
-  if (s.kind == KIND_SOA) return off + obj * size;
-  const uint32_t blk = s.width == 1 ? obj : __umulhi(obj, s.width_magic);
-  const uint32_t lane = obj - blk * s.width;
-  return blk * s.width * s.obj_bytes + off + lane * size;
-}
-
 // Bytes of a side's image that hold `cnt` objects (runs are contiguous for
 // AoS and AoSoA; for SoA this is only used for zeroing).
 __device__ __forceinline__ uint32_t image_used(const SideDesc& s, uint32_t cnt) {
@@ -188,7 +178,7 @@ __device__ __forceinline__ uint32_t unit_of(const DenseDesc& d, uint32_t v) {
 
 // Load one side's tile into its LDS image.  `idx0` is the index of the
 // tile's first object on that side.
-__device__ void load_side(const DenseDesc& d, uint8_t* img, uint64_t idx0, uint32_t cnt,
+__device__ __forceinline__ void load_side(const DenseDesc& d, uint8_t* img, uint64_t idx0, uint32_t cnt,
                           bool full) {
   const SideDesc& s = d.src;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
@@ -219,7 +209,7 @@ __device__ void load_side(const DenseDesc& d, uint8_t* img, uint64_t idx0, uint3
   }
 }
 
-__device__ void store_side(const DenseDesc& d, const uint8_t* img, uint64_t idx0, uint32_t cnt,
+__device__ __forceinline__ void store_side(const DenseDesc& d, const uint8_t* img, uint64_t idx0, uint32_t cnt,
                            bool full) {
   const SideDesc& s = d.dst;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
@@ -336,7 +326,7 @@ __device__ __forceinline__ void commit(const DenseDesc& d, const v4u* r, uint8_t
 // Fused local scan of jagged counts held in the source records: writes the
 // tile's exclusive offsets (entry i0 holds the tile total until the totals
 // pass replaces it with the tile's prefix).
-__device__ void scan_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+__device__ __forceinline__ void scan_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t per = (d.tile + nt - 1) / nt;
   const uint32_t o0 = tid * per;
@@ -357,36 +347,135 @@ __device__ void scan_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, ui
   if (tid == 0 && total > off_limit(d.scan_off_type)) flag(d.status, ST_FLAG_OVERFLOW);
 }
 
-// Move every leaf value of the tile from the source image to the
-// destination image.
-__device__ void transform_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+// ------------------------------------------------------------------ transform
+//
+// Every leaf value of the tile moves from the source image to the
+// destination image.  The transform is specialised on the two layout
+// kinds, and each thread takes kObjPerThread objects per pass: the
+// object-dependent part of every image address is computed once per
+// object, and the per-leaf work (descriptor load, one switch) is shared by
+// all of a thread's objects.  Full passes carry no per-object guards.
+
+constexpr uint32_t kObjPerThread = 4;
+
+// Object-dependent address terms of one side: addr = a + off + b * size.
+template <uint32_t K>
+__device__ __forceinline__ void obj_terms(const SideDesc& s, uint32_t o, uint32_t& a, uint32_t& b) {
+  if (K == KIND_AOS) {
+    a = o * s.stride;
+    b = 0;
+  } else if (K == KIND_SOA) {
+    a = 0;
+    b = o;
+  } else {
+    const uint32_t blk = s.width == 1 ? o : __umulhi(o, s.width_magic);
+    a = blk * s.width * s.obj_bytes;
+    b = o - blk * s.width;
+  }
+}
+
+template <uint32_t K, uint32_t SIZE>
+__device__ __forceinline__ uint32_t at(uint32_t a, uint32_t off, uint32_t b) {
+  return K == KIND_AOS ? a + off : a + off + b * SIZE;
+}
+
+template <uint32_t SK, uint32_t DK, bool FULL>
+__device__ __forceinline__ void transform_pass(const DenseDesc& d, const DenseLds& m, uint64_t i0,
+                                               uint32_t o0, uint32_t cnt) {
+  constexpr uint32_t P = kObjPerThread;
+  const uint32_t nt = blockDim.x;
+  uint32_t sa[P], sb[P], da[P], db[P];
+  bool ok[P];
+#pragma unroll
+  for (uint32_t k = 0; k < P; ++k) {
+    const uint32_t o = o0 + threadIdx.x + k * nt;
+    ok[k] = FULL || o < cnt;
+    obj_terms<SK>(d.src, o, sa[k], sb[k]);
+    obj_terms<DK>(d.dst, o, da[k], db[k]);
+  }
+  const uint8_t* S = m.src;
+  uint8_t* D = m.dst;
+#define RL_MOVE(ST, DT, SS, DS, EXPR)                                                  \
+  _Pragma("unroll") for (uint32_t k = 0; k < P; ++k) {                                 \
+    if (FULL || ok[k]) {                                                               \
+      const ST x = *reinterpret_cast<const ST*>(S + at<SK, SS>(sa[k], so, sb[k]));     \
+      *reinterpret_cast<DT*>(D + at<DK, DS>(da[k], dof, db[k])) = (EXPR);              \
+    }                                                                                  \
+  }
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
     const LeafDesc& L = d.leaf[c];
-    if (L.op == OP_PTR || L.op == OP_LEN) {
-      const uint32_t ot = L.aux >> 24;
-      const uint64_t first = load_off(L.src_col, ot, 0);
-      for (uint32_t o = tid; o < cnt; o += nt) {
-        const uint64_t i = i0 + o;
-        const uint64_t a = load_off(L.src_col, ot, i);
-        uint8_t* dp = m.dst + image_addr(d.dst, o, L.dst_off, L.dst_size);
-        if (L.op == OP_PTR) {
-          const uint64_t v = (a - first) * (uint64_t)(L.aux & 0xffffffu);
-          if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 8);
-          else *reinterpret_cast<uint64_t*>(dp) = v;
-        } else {
-          const uint32_t v = (uint32_t)(load_off(L.src_col, ot, i + 1) - a);
-          if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 4);
-          else *reinterpret_cast<uint32_t*>(dp) = v;
-        }
+    const uint32_t so = L.src_off, dof = L.dst_off;
+    switch (L.code) {
+      case CODE_COPY1: RL_MOVE(uint8_t, uint8_t, 1, 1, x); break;
+      case CODE_COPY2: RL_MOVE(uint16_t, uint16_t, 2, 2, x); break;
+      case CODE_COPY4: RL_MOVE(uint32_t, uint32_t, 4, 4, x); break;
+      case CODE_COPY8: RL_MOVE(uint64_t, uint64_t, 8, 8, x); break;
+      case CODE_NARROW: RL_MOVE(double, float, 8, 4, (float)x); break;  // v_cvt_f32_f64: round to nearest even
+      case CODE_WIDEN: RL_MOVE(float, double, 4, 8, (double)x); break;
+      default: break;   // slow leaves: transform_slow
+    }
+  }
+#undef RL_MOVE
+}
+
+// Leaves at misaligned image addresses and destination record (pointer,
+// count) pairs: one object per thread, generic address arithmetic.
+__device__ __forceinline__ void transform_slow(const DenseDesc& d, uint8_t* src_img, uint8_t* dst_img,
+                                            uint64_t i0, uint32_t cnt) {
+  for (uint32_t c = 0; c < d.n_leaves; ++c) {
+    const LeafDesc& L = d.leaf[c];
+    if (L.code < CODE_BYTES) continue;
+    for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) {
+      uint32_t sa, sb, da, db;
+      if (d.src.kind == KIND_AOS) obj_terms<KIND_AOS>(d.src, o, sa, sb);
+      else if (d.src.kind == KIND_SOA) obj_terms<KIND_SOA>(d.src, o, sa, sb);
+      else obj_terms<KIND_AOSOA>(d.src, o, sa, sb);
+      if (d.dst.kind == KIND_AOS) obj_terms<KIND_AOS>(d.dst, o, da, db);
+      else if (d.dst.kind == KIND_SOA) obj_terms<KIND_SOA>(d.dst, o, da, db);
+      else obj_terms<KIND_AOSOA>(d.dst, o, da, db);
+      uint8_t* dp = dst_img + da + L.dst_off + db * L.dst_size;
+      if (L.code == CODE_BYTES) {
+        move_value(dp, src_img + sa + L.src_off + sb * L.src_size, L);
+        continue;
       }
-      continue;
+      // destination record (pointer, count) from the source offsets
+      const uint64_t i = i0 + o;
+      const uint64_t first = load_off(L.src_col, L.off_type, 0);
+      const uint64_t a = load_off(L.src_col, L.off_type, i);
+      if (L.code == CODE_PTR) {
+        const uint64_t v = (a - first) * (uint64_t)L.mstride;
+        if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 8);
+        else *reinterpret_cast<uint64_t*>(dp) = v;
+      } else {
+        const uint32_t v = (uint32_t)(load_off(L.src_col, L.off_type, i + 1) - a);
+        if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 4);
+        else *reinterpret_cast<uint32_t*>(dp) = v;
+      }
     }
-    for (uint32_t o = tid; o < cnt; o += nt) {
-      const uint8_t* sp = m.src + image_addr(d.src, o, L.src_off, L.src_size);
-      uint8_t* dp = m.dst + image_addr(d.dst, o, L.dst_off, L.dst_size);
-      move_value(dp, sp, L);
-    }
+  }
+}
+
+template <uint32_t SK, uint32_t DK>
+__device__ __forceinline__ void transform_kinds(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+  const uint32_t per_pass = kObjPerThread * blockDim.x;
+  for (uint32_t o0 = 0; o0 < cnt; o0 += per_pass) {
+    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true>(d, m, i0, o0, cnt);
+    else transform_pass<SK, DK, false>(d, m, i0, o0, cnt);
+  }
+}
+
+__device__ __forceinline__ void transform_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+  if (d.slow_leaves) transform_slow(d, m.src, m.dst, i0, cnt);
+  switch (d.src.kind * 3 + d.dst.kind) {
+    case KIND_AOS * 3 + KIND_AOS: transform_kinds<KIND_AOS, KIND_AOS>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA>(d, m, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS>(d, m, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA>(d, m, i0, cnt); break;
+    default: transform_kinds<KIND_AOSOA, KIND_AOSOA>(d, m, i0, cnt); break;
   }
 }
 
@@ -395,7 +484,7 @@ __device__ void transform_tile(const DenseDesc& d, const DenseLds& m, uint64_t i
 // pointer: the address of a kernel-argument descriptor must not escape
 // into a loop-carried value, or the compiler copies it to scratch.)
 template <class Next, class Desc>
-__device__ void dense_pipeline(uint8_t* smem, Next next, Desc desc) {
+__device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc desc) {
   v4u regs[kPrefetch];
   TileJob cur = next();
   bool in_regs = false;
@@ -455,7 +544,7 @@ struct StridedTiles {
   }
 };
 
-__global__ void __launch_bounds__(1024) dense_kernel(const DenseDesc d) {
+__global__ void __launch_bounds__(256, 4) dense_kernel(const DenseDesc d) {
   extern __shared__ uint4 smem_raw[];
   uint64_t count, base;
   dense_count(d, &count, &base);
@@ -630,7 +719,7 @@ __device__ __forceinline__ void retire(uint32_t* counter, uint32_t* done) {
 
 // Every dense step of every item: the tiles of all items form one space,
 // walked by a persistent grid taking tickets.
-__global__ void __launch_bounds__(1024) batch_dense_kernel(const BatchTables b) {
+__global__ void __launch_bounds__(256, 4) batch_dense_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
   __shared__ uint32_t ticket;
   dense_pipeline(

@@ -138,8 +138,13 @@ rl_status build_dense(const SideSpec& s, const SideSpec& d, uint64_t n, uint32_t
     L.src_off = image_off(s, sp);
     L.dst_off = image_off(d, dp);
     L.byte_wise = !(side_aligned(s, c, ss, sp, sb) && side_aligned(d, c, dsz, dp, db));
+    if (L.byte_wise) L.code = CODE_BYTES;
+    else if (L.op == OP_NARROW) L.code = CODE_NARROW;
+    else if (L.op == OP_WIDEN) L.code = CODE_WIDEN;
+    else L.code = ss == 1 ? CODE_COPY1 : ss == 2 ? CODE_COPY2 : ss == 4 ? CODE_COPY4 : CODE_COPY8;
     L.src_col = s.kind == KIND_SOA ? s.cols[c] : nullptr;
     L.dst_col = d.kind == KIND_SOA ? d.cols[c] : nullptr;
+    if (L.code >= CODE_BYTES) k.slow_leaves = 1;
     sp += ss;
     dp += dsz;
   }
@@ -167,11 +172,18 @@ static uint32_t default_grid(uint64_t tiles, const PlanShape& shape) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 256ull * 16));
 }
 
+// Threads of a dense work-group: four objects per thread per pass.
+static uint32_t dense_threads(uint32_t tile, const PlanShape& shape) {
+  if (shape.threads) return shape.threads;
+  uint32_t t = (tile / 4 + 63) / 64 * 64;
+  return std::min<uint32_t>(1024, std::max<uint32_t>(64, t));
+}
+
 static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& shape) {
   Step st;
   st.kind = Step::DENSE;
   st.dense = d;
-  st.threads = shape.threads ? shape.threads : 256;
+  st.threads = dense_threads(d.tile, shape);
   st.grid = default_grid(dense_tiles(d), shape);
   plan->steps.push_back(st);
   return RL_OK;
@@ -276,7 +288,10 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
         L.dst_size = which == 0 ? 8 : 4;
         L.src_size = 0;
         L.byte_wise = (DL->stride % L.dst_size) != 0;
-        L.aux = (which == 0 ? DL->mstride[g] : 0) | ((uint32_t)ot << 24);
+        L.mstride = (uint16_t)(which == 0 ? DL->mstride[g] : 0);
+        L.off_type = (uint8_t)ot;
+        L.code = which == 0 ? CODE_PTR : CODE_LEN;
+        dd.slow_leaves = 1;
         L.src_col = so;
       }
     }

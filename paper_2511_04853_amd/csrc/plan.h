@@ -9,7 +9,7 @@ namespace rl {
 
 struct PlanShape {
   uint32_t tile = 0;      // objects per tile (0: default)
-  uint32_t threads = 256; // threads per work-group
+  uint32_t threads = 0;   // threads per work-group (0: a quarter of the tile)
   uint32_t grid = 0;      // work-groups of dense steps (0: one per tile, capped)
 };
 

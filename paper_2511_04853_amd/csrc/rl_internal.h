@@ -32,6 +32,14 @@ enum LeafOp : uint8_t {
   OP_LEN = 4      // destination record count: off[i+1] - off[i] (u32)
 };
 
+// A leaf move as one value (host-computed from op, sizes and alignment).
+enum LeafCode : uint8_t {
+  CODE_COPY1 = 0, CODE_COPY2 = 1, CODE_COPY4 = 2, CODE_COPY8 = 3,
+  CODE_NARROW = 4, CODE_WIDEN = 5,
+  CODE_BYTES = 6,   // any copy/narrow/widen at a misaligned image address
+  CODE_PTR = 7, CODE_LEN = 8
+};
+
 // Device status flags (ORed by kernels, read by rl_sync).
 enum StatusFlag : uint32_t {
   ST_FLAG_OVERFLOW = 1u,
@@ -50,7 +58,9 @@ struct LeafDesc {
   uint8_t dst_size;
   uint8_t op;
   uint8_t byte_wise;       // 1: an access in an image is not naturally aligned
-  uint32_t aux;            // OP_PTR: member record stride; OP_PTR/OP_LEN: offset type in bits 24..31
+  uint16_t mstride;        // OP_PTR: member record stride
+  uint8_t off_type;        // OP_PTR/OP_LEN: rl_type of the source offsets
+  uint8_t code;            // LeafCode: the move as one switch value
   const uint8_t* src_col;  // SoA source column, or the offsets for OP_PTR/OP_LEN
   uint8_t* dst_col;        // SoA destination column
 };
@@ -86,6 +96,8 @@ struct DenseDesc {
   uint32_t units_src;      // 1: SoA source, full tiles walk the image by unit_src
   uint32_t units_dst;      // 1: SoA destination, full tiles walk the image by unit_dst
   uint32_t prefetch;       // 1: full source tiles are 16-byte aligned runs (fetched ahead)
+  uint32_t slow_leaves;    // 1: some leaf needs the generic (byte-wise / offsets) path
+  uint32_t pad1;
   uint32_t vt_magic;       // ceil(2^32 / (tile / 16)): SoA image vector -> byte unit
   uint64_t src_capacity;   // with count_offsets: source member capacity (count <= it - base)
   LeafDesc leaf[kMaxLeaves];
