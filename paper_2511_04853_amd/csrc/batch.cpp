@@ -46,7 +46,7 @@ struct Item {
 };
 
 struct Config {
-  uint32_t tile = 256, threads = 256, grid = 2048, width = 64;
+  uint32_t tile = 256, threads = 64, grid = 2048, width = 64;   // threads: dense work-groups
 };
 
 struct DeviceTables {
@@ -178,7 +178,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
 }
 
 rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s) {
-  hipError_t e = launch_batch(d.t, c.threads, c.grid, d.dense_lds, d.gather_lds, s);
+  const uint32_t dt = std::min<uint32_t>(c.threads, kDenseMaxThreads);
+  hipError_t e = launch_batch(d.t, dt, 256, c.grid, d.dense_lds, d.gather_lds, s);
   return e == hipSuccess ? RL_OK : hip_fail(e, "batch launch");
 }
 
@@ -292,7 +293,7 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
   double best_us = 1e30;
   Config bc;
   for (uint32_t tile : {128u, 256u, 512u, 1024u})
-    for (uint32_t threads : {256u, 512u})
+    for (uint32_t threads : {64u, 128u, 256u})
       for (uint32_t grid : {1024u, 2048u, 4096u}) {
         Config c{tile, threads, grid, 64};
         double us;
@@ -377,7 +378,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   (void)have;
   if (const char* v = getenv("RL_BATCH_TILE")) c.tile = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_GRID")) c.grid = (uint32_t)strtoul(v, nullptr, 10);
-  if (c.threads < 64 || c.threads > 1024 || c.threads % 64) c.threads = 256;
+  if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 64;
   if (c.grid < 1) c.grid = 2048;
   b->cfg = c;
   rl_status st = resolve_widths(b, c.width);

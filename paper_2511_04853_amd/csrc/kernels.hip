@@ -770,6 +770,7 @@ uint32_t dense_lds_bytes(const DenseDesc& d) {
 uint64_t dense_tiles(const DenseDesc& d) { return (d.n + d.tile - 1) / d.tile; }
 
 hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid, hipStream_t s) {
+  if (threads == 0 || threads > kDenseMaxThreads || threads % 64) return hipErrorInvalidValue;
   const uint32_t lds = dense_lds_bytes(d);
   hipLaunchKernelGGL(dense_kernel, dim3(grid), dim3(threads), lds, s, d);
   return hipGetLastError();
@@ -795,10 +796,12 @@ hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchTables& b, uint32_t threads, uint32_t grid, uint32_t dense_lds,
-                        uint32_t gather_lds, hipStream_t s) {
+hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
+                        uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s) {
+  if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
+  if (gather_threads == 0 || gather_threads > 1024 || gather_threads % 64) return hipErrorInvalidValue;
   if (b.dense_tiles) {
-    hipLaunchKernelGGL(batch_dense_kernel, dim3(grid), dim3(threads), dense_lds, s, b);
+    hipLaunchKernelGGL(batch_dense_kernel, dim3(grid), dim3(dense_threads), dense_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -808,7 +811,7 @@ hipError_t launch_batch(const BatchTables& b, uint32_t threads, uint32_t grid, u
     if (e != hipSuccess) return e;
   }
   if (b.gather_tiles) {
-    hipLaunchKernelGGL(batch_gather_kernel, dim3(grid), dim3(threads), gather_lds, s, b);
+    hipLaunchKernelGGL(batch_gather_kernel, dim3(grid), dim3(gather_threads), gather_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -174,9 +174,8 @@ static uint32_t default_grid(uint64_t tiles, const PlanShape& shape) {
 
 // Threads of a dense work-group: four objects per thread per pass.
 static uint32_t dense_threads(uint32_t tile, const PlanShape& shape) {
-  if (shape.threads) return shape.threads;
-  uint32_t t = (tile / 4 + 63) / 64 * 64;
-  return std::min<uint32_t>(1024, std::max<uint32_t>(64, t));
+  uint32_t t = shape.threads ? shape.threads : (tile / 4 + 63) / 64 * 64;
+  return std::min<uint32_t>(kDenseMaxThreads, std::max<uint32_t>(64, t));
 }
 
 static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& shape) {

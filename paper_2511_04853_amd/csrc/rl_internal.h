@@ -19,6 +19,7 @@ constexpr int kMaxObjBytes = 512;     // sum of leaf sizes on one side
 constexpr int kMaxUnits = 256;        // SoA images up to this many bytes per object use the unit table
 constexpr int kMaxExtent = 64;
 constexpr uint32_t kAutoWidthMax = 128; // "auto" AoSoA widths are 32, 64 or 128
+constexpr uint32_t kDenseMaxThreads = 256;  // launch bound of the dense kernels
 
 // Kinds of one side of a dense conversion (match rl_kind).
 enum SideKind : uint32_t { KIND_AOS = 0, KIND_SOA = 1, KIND_AOSOA = 2 };
@@ -174,8 +175,8 @@ hipError_t launch_scan_totals(const ScanTotalsDesc& d, hipStream_t s);
 hipError_t launch_gather(const GatherDesc& d, uint32_t threads, hipStream_t s);
 hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s);
 hipError_t launch_clear_status(uint32_t* status, hipStream_t s);
-hipError_t launch_batch(const BatchTables& b, uint32_t threads, uint32_t grid, uint32_t dense_lds,
-                        uint32_t gather_lds, hipStream_t s);
+hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
+                        uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s);
 uint32_t dense_lds_bytes(const DenseDesc& d);
 uint64_t dense_tiles(const DenseDesc& d);
 
