@@ -12,10 +12,14 @@ HBM.
 Value: algorithmic bytes (source footprint read + destination footprint
 written, per conversion) per second of the timed region.
 
-Extra legs, outside the timed region: a sweep at larger object counts, the
-host -> device transfer + conversion rate (PCIe included), the batched
-graph launch against a per-collection launch loop, and the oracle timed on
-the host cores (cpu_baseline).
+The four conversions of a step run as one graph launch of the batch engine
+(persistent kernels over a device table; shape autotuned once, cached); the
+same conversions as a per-conversion launch loop are timed beside it.
+
+Extra legs, outside the timed region: 512 heterogeneous collections in one
+graph launch against the launch loop, a sweep at larger object counts, the
+host -> device transfer + conversion rate (PCIe included), and the oracle
+timed on the host cores (cpu_baseline).
 """
 import argparse
 import ctypes
@@ -89,6 +93,7 @@ def main():
         return rec
 
     rec0 = device_aos(v)
+    tune_cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"rl_tune_{os.getpid()}.json")
     sets = []
     for r in range(args.sets):
         src = rec0 if r == 0 else rec0.clone()
@@ -96,48 +101,57 @@ def main():
         for L in dsts:
             bufs = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in L.buffer_bytes(n)]
             outs.append(P.View(L, n, bufs))
-        sets.append((P.View(aos, n, [src]), outs))
+        sv = P.View(aos, n, [src])
+        # one batch per copy: the four conversions of a step in one graph launch
+        b = Batch(P, autotune=1 if r == 0 else 0, cache=tune_cache)
+        for d in outs:
+            b.add(sv, d, n)
+        b.finalize(sp)
+        sets.append((sv, outs, b))
     torch.cuda.synchronize()
+    shape = sets[0][2].shape()
 
     src_bytes = aos.buffer_bytes(n)[0]
     conv_bytes = [src_bytes + sum(L.buffer_bytes(n)) for L in dsts]
     step_bytes = sum(conv_bytes)
-    lib = P.lib()
 
-    def step(k, evs=None):
-        s, outs = sets[k % len(sets)]
-        for j, d in enumerate(outs):
-            if evs is not None:
-                evs[j][0].record(stream)
-            st = lib.rl_convert(s.ref(), d.ref(), n, sp)
-            if st:
-                raise P.RelayoutError(st, "rl_convert")
-            if evs is not None:
-                evs[j][1].record(stream)
+    def run(k, loop=False):
+        b = sets[k % len(sets)][2]
+        b.loop(sp) if loop else b.launch(sp)
 
     for k in range(args.warmup):
-        step(k)
+        run(k)
     assert P.sync(stream) == 0, P.rl_last_error()
 
     K = args.steps
-    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-            for _ in dsts] for _ in range(K)]
+    evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(K)]
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
     for k in range(K):
-        step(k, evs[k])
+        evs[k][0].record(stream)
+        run(k)
+        evs[k][1].record(stream)
     t1.record(stream)
     torch.cuda.synchronize()
     ms_total = t0.elapsed_time(t1)
     assert P.sync(stream) == 0, P.rl_last_error()
     ms_per_step = ms_total / K
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
-    launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in row] for row in evs])
-    per_kernel_ms = launch_ms.mean(axis=0)
+    launch_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     mean_launch_ms = float(launch_ms.mean())
-    mean_launch_bytes = float(np.mean(conv_bytes))
-    achieved = mean_launch_bytes / (mean_launch_ms * 1e-3) / 1e9
+    achieved = step_bytes / (mean_launch_ms * 1e-3) / 1e9
+
+    # the same conversions as a launch loop (one kernel launch per conversion)
+    for k in range(args.warmup):
+        run(k, loop=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(K):
+        run(k, loop=True)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_loop = t0.elapsed_time(t1) / K
 
     out = {
         "metric": "conversion GB/s (read+write) vs HBM peak; batched speedup; p50/p99 event lat",
@@ -160,6 +174,8 @@ def main():
             "objects": n,
             "bytes_per_step": step_bytes,
             "conversions_per_step": len(dsts),
+            "launch": "one graph launch per step (batch of the 4 conversions), "
+                      f"tile {shape[0]} objects, {shape[1]} threads, {shape[2]} persistent blocks (autotuned)",
         },
         "roofline": {
             "bound": "hbm",
@@ -168,19 +184,148 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "kernel": "rl::dense_kernel",
+            "kernel": "rl::batch_dense_kernel",
             "mean_launch_us": round(mean_launch_ms * 1e3, 3),
-            "per_destination_us": [round(x * 1e3, 3) for x in per_kernel_ms],
-            "bytes_per_launch": int(mean_launch_bytes),
+            "bytes_per_launch": int(step_bytes),
         },
+        "step_launch_loop": {"ms_per_step": round(ms_loop, 5),
+                             "GBps": round(step_bytes / (ms_loop * 1e-3) / 1e9, 2),
+                             "graph_speedup": round(ms_loop / ms_per_step, 3)},
     }
 
     if not args.no_extras:
+        out["batched"] = batched(P, W, torch, stream, tune_cache)
         out["sweep"] = sweep(P, W, torch, stream)
         out["h2d"] = h2d_rate(P, W, torch, stream, S, aos, dsts[0], v)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W, v, args.cpu_seconds, step_bytes)
     print(json.dumps(out), flush=True)
+
+
+class Batch:
+    """ctypes wrapper of an rl_batch."""
+
+    def __init__(self, P, autotune=0, cache=None):
+        self.P = P
+        self.keep = []
+        h = ctypes.c_void_p()
+        opts = P.rl_batch_opts(autotune, cache.encode() if cache else None)
+        P.check(P.lib().rl_batch_create(ctypes.byref(opts), ctypes.byref(h)), "rl_batch_create")
+        self.h = h
+
+    def add(self, sv, dv, n):
+        self.keep += [sv, dv]
+        self.P.check(self.P.lib().rl_batch_add(self.h, sv.ref(), dv.ref(), n), "rl_batch_add")
+
+    def finalize(self, sp):
+        self.P.check(self.P.lib().rl_batch_finalize(self.h, sp), "rl_batch_finalize")
+
+    def launch(self, sp):
+        self.P.check(self.P.lib().rl_batch_launch(self.h, sp), "rl_batch_launch")
+
+    def loop(self, sp):
+        self.P.check(self.P.lib().rl_batch_launch_loop(self.h, sp), "rl_batch_launch_loop")
+
+    def width(self, k):
+        w = ctypes.c_uint32()
+        self.P.check(self.P.lib().rl_batch_item_width(self.h, k, ctypes.byref(w)), "width")
+        return w.value
+
+    def shape(self):
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        self.P.check(self.P.lib().rl_batch_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "shape")
+        return a.value, b.value, c.value
+
+
+def batched(P, W, torch, stream, tune_cache):
+    """512 collections (three schemas, sizes log-uniform over 1k..200k,
+    mixed kinds, auto block widths): one graph launch vs the launch loop.
+    Sources are generated on the device (random field bits, Poisson(40)
+    member counts) and laid out by the library."""
+    sp = P.stream_ptr(stream)
+    decls = {"plain8": W.PLAIN8, "cell": W.CELL, "cluster": W.CLUSTER}
+    schemas = {k: P.Schema(d) for k, d in decls.items()}
+    kinds = {"aos": ("aos", 0), "soa": ("soa", 0), "aosoa": ("aosoa", 64)}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1003)
+    specs = W.batch_items()
+    b = Batch(P, autotune=1, cache=tune_cache)
+    keep = []
+    item_bytes = []
+    for it in specs:
+        decl, S, n = decls[it["schema"]], schemas[it["schema"]], it["n"]
+        narrow = ["f32" if f.type == "f64" else f.type for f in decl.fields if f.group < 0]
+        narrow = narrow if it["schema"] == "cell" and it["dst"] != "aos" else None
+        vals = P.Layout(S, "soa")
+        mem = []
+        bufs = []
+        for f in decl.fields:
+            if f.group < 0:
+                bufs.append(torch.randint(0, 256, (n * W.TYPE_SIZE[f.type] * f.extent,), dtype=torch.uint8,
+                                          device="cuda", generator=g))
+        if decl.offset_types:
+            lens = torch.poisson(torch.full((n,), 40.0, device="cuda"), generator=g).to(torch.int64)
+            offs = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+            offs[1:] = torch.cumsum(lens, 0)
+            tot = int(offs[-1].item())
+            mem = [tot]
+            bufs.append(offs.to(torch.int32).view(torch.uint8))
+            for f in decl.fields:
+                if f.group >= 0:
+                    bufs.append(torch.randint(0, 256, (tot * W.TYPE_SIZE[f.type],), dtype=torch.uint8,
+                                              device="cuda", generator=g))
+        vview = P.View(vals, n, bufs, mem)
+        sk = kinds[it["src"]]
+        if sk[0] == "soa":
+            sview, slay = vview, vals
+        else:
+            slay = P.Layout(S, sk[0], width=sk[1])
+            sbufs = [torch.empty(x, dtype=torch.uint8, device="cuda") for x in slay.buffer_bytes(n, mem)]
+            sview = P.View(slay, n, sbufs, mem)
+            P.convert(vview, sview, n)
+        dk = kinds[it["dst"]]
+        dlay = P.Layout(S, dk[0], width=0 if dk[0] == "aosoa" else 0, storage=narrow)
+        dbufs = [torch.empty(x, dtype=torch.uint8, device="cuda") for x in dlay.buffer_bytes(n, mem)]
+        dview = P.View(dlay, n, dbufs, mem)
+        b.add(sview, dview, n)
+        keep += [vview, sview, dview, slay, dlay]
+        item_bytes.append((slay, dlay, n, mem))
+    assert P.sync(stream) == 0, P.rl_last_error()
+    t = time.perf_counter()
+    b.finalize(sp)
+    tune_s = time.perf_counter() - t
+    # algorithmic bytes: source and destination footprints at the chosen widths
+    total = 0
+    for k, (slay, dlay, n, mem) in enumerate(item_bytes):
+        total += sum(slay.buffer_bytes(n, mem))
+        if dlay.kind == "aosoa":
+            w = b.width(k)
+            dl2 = P.Layout(dlay.schema, "aosoa", width=w, storage=None if dlay.storage is None else dlay.storage)
+            total += sum(dl2.buffer_bytes(n, mem))
+        else:
+            total += sum(dlay.buffer_bytes(n, mem))
+    res = {"items": len(specs), "objects": int(sum(s["n"] for s in specs)), "bytes": total,
+           "shape": b.shape(), "finalize_s": round(tune_s, 2)}
+    for mode in ("graph", "loop"):
+        fn = b.launch if mode == "graph" else b.loop
+        for _ in range(3):
+            fn(sp)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            fn(sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[mode] = {"ms": round(ms, 4), "GBps": round(total / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    assert P.sync(stream) == 0, P.rl_last_error()
+    res["speedup"] = round(res["loop"]["ms"] / res["graph"]["ms"], 3)
+    del keep, b
+    torch.cuda.empty_cache()
+    return res
 
 
 def sweep(P, W, torch, stream):

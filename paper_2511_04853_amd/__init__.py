@@ -199,6 +199,7 @@ class Layout:
     def __init__(self, schema: Schema, kind: str, space: str = "device", width: int = 0,
                  storage=None, slot_offsets=None, stride: int = 0):
         self.schema, self.kind, self.space, self.width = schema, kind, space, width
+        self.storage = list(storage) if storage is not None else None
         d = rl_layout_desc()
         d.kind = KINDS[kind]
         d.space = SPACES[space]

@@ -46,7 +46,7 @@ struct Item {
 };
 
 struct Config {
-  uint32_t tile = 256, threads = 64, grid = 2048, width = 64;   // threads: dense work-groups
+  uint32_t tile = 256, threads = 128, grid = 2048, width = 64;   // threads: dense work-groups
 };
 
 struct DeviceTables {
@@ -378,7 +378,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   (void)have;
   if (const char* v = getenv("RL_BATCH_TILE")) c.tile = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_GRID")) c.grid = (uint32_t)strtoul(v, nullptr, 10);
-  if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 64;
+  if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 128;
   if (c.grid < 1) c.grid = 2048;
   b->cfg = c;
   rl_status st = resolve_widths(b, c.width);

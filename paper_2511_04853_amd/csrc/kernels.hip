@@ -356,7 +356,7 @@ __device__ __forceinline__ void scan_tile(const DenseDesc& d, const DenseLds& m,
 // object, and the per-leaf work (descriptor load, one switch) is shared by
 // all of a thread's objects.  Full passes carry no per-object guards.
 
-constexpr uint32_t kObjPerThread = 4;
+constexpr uint32_t kObjPerThread = 2;
 
 // Object-dependent address terms of one side: addr = a + off + b * size.
 template <uint32_t K>

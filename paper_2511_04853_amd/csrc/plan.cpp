@@ -10,7 +10,7 @@
 namespace rl {
 
 static constexpr uint32_t kLdsBudget = 64 * 1024;
-static constexpr uint32_t kDefaultTile = 256;
+static constexpr uint32_t kDefaultTile = 512;
 static constexpr uint32_t kMaxTile = 4096;
 
 SideSpec object_side(const rl_layout* L, void* const* bufs, uint64_t index0) {
@@ -61,12 +61,17 @@ static uint64_t image_bytes(const SideSpec& s, uint32_t tile) {
 
 static uint32_t lcm32(uint32_t a, uint32_t b) { return a / std::gcd(a, b) * b; }
 
-uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target) {
+uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target, uint64_t n) {
   uint32_t unit = 16;
   if (s.kind == KIND_AOSOA) unit = lcm32(unit, s.width);
   if (d.kind == KIND_AOSOA) unit = lcm32(unit, d.width);
   if (unit > kMaxTile) return 0;
-  if (!target) target = kDefaultTile;
+  if (!target) {
+    // long column runs favour large tiles; small collections need enough
+    // tiles to spread over the 256 compute units
+    target = kDefaultTile;
+    while (target > 128 && n && (n + target - 1) / target < 1024) target /= 2;
+  }
   uint32_t t = std::max(unit, target / unit * unit);
   while (t >= unit) {
     const uint64_t lds = ((image_bytes(s, t) + 15) & ~15ull) + ((image_bytes(d, t) + 15) & ~15ull) + 144;
@@ -172,9 +177,9 @@ static uint32_t default_grid(uint64_t tiles, const PlanShape& shape) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 256ull * 16));
 }
 
-// Threads of a dense work-group: four objects per thread per pass.
+// Threads of a dense work-group: two objects per thread per pass.
 static uint32_t dense_threads(uint32_t tile, const PlanShape& shape) {
-  uint32_t t = shape.threads ? shape.threads : (tile / 4 + 63) / 64 * 64;
+  uint32_t t = shape.threads ? shape.threads : (tile / 2 + 63) / 64 * 64;
   return std::min<uint32_t>(kDenseMaxThreads, std::max<uint32_t>(64, t));
 }
 
@@ -266,7 +271,7 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
 
   SideSpec s = object_side(SL, src.buffers, 0);
   SideSpec d = object_side(DL, dst.buffers, 0);
-  const uint32_t tile = choose_tile(s, d, shape.tile);
+  const uint32_t tile = choose_tile(s, d, shape.tile, n);
   if (!tile) return fail(RL_EUNSUPPORTED, "no tile shape fits these layouts (block widths or record size)");
   DenseDesc dd;
   rl_status st = build_dense(s, d, n, tile, &dd);
@@ -319,7 +324,7 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
     plan->steps.push_back(r);
     SideSpec ms = member_side(SL, src.buffers, g);
     SideSpec md = member_side(DL, dst.buffers, g);
-    const uint32_t mt = choose_tile(ms, md, shape.tile);
+    const uint32_t mt = choose_tile(ms, md, shape.tile, dst.member_capacity[g]);
     if (!mt) return fail(RL_EUNSUPPORTED, "no tile shape fits the member records");
     DenseDesc m;
     if ((st = build_dense(ms, md, dst.member_capacity[g], mt, &m))) return st;
@@ -347,7 +352,7 @@ rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t g, 
     s.types.clear();
     SideSpec d;
     d.kind = KIND_SOA;
-    const uint32_t tile = choose_tile(s, d, shape.tile ? shape.tile : 1024);
+    const uint32_t tile = choose_tile(s, d, shape.tile ? shape.tile : 1024, n);
     if (!tile) return fail(RL_EUNSUPPORTED, "record too large for a tile");
     return push_scan_gather(plan, src, dst, g, n, tile, false, false, shape, status);
   }

@@ -56,7 +56,7 @@ SideSpec member_side(const rl_layout* L, void* const* bufs, uint32_t g);
 
 // Tile size for two sides given a target (multiple of 16 and of the block
 // widths, images within the LDS budget); 0 if none fits.
-uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target);
+uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target, uint64_t n);
 rl_status build_dense(const SideSpec& s, const SideSpec& d, uint64_t n, uint32_t tile,
                       DenseDesc* out);
 
