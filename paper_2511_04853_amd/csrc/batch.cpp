@@ -2,7 +2,7 @@
 // HIP graph.  Every item is planned as for rl_convert; the steps of all
 // items are gathered into device-resident tables by kernel kind, and three
 // persistent kernels (dense tiles, tile-total scans and rebases, member
-// gathers) walk those tables taking tickets.  The graph holds the three
+// gathers) stride over the tiles of all items.  The graph holds the three
 // launches; a per-collection loop over rl_convert plans is kept for
 // comparison.  An autotuner times candidate tile shapes (and block widths
 // of "auto" AoSoA destinations) on the batch itself and keeps the fastest,
@@ -135,7 +135,7 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
     }
   if (dprefix.back() >= (1ull << 32) || gprefix.back() >= (1ull << 32))
     return fail(RL_EUNSUPPORTED, "batch has more than 2^32 tiles");
-  // one allocation: tables + prefix arrays + counters
+  // one allocation: tables, prefix arrays and tile -> item maps
   size_t sz = 0;
   auto reserve = [&](size_t bytes) { size_t at = sz; sz += (bytes + 255) & ~size_t(255); return at; };
   const size_t o_dense = reserve(dense.size() * sizeof(DenseDesc));
@@ -144,7 +144,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   const size_t o_gp = reserve(gprefix.size() * 8);
   const size_t o_tot = reserve(totals.size() * sizeof(ScanTotalsDesc));
   const size_t o_reb = reserve(rebase.size() * sizeof(RebaseDesc));
-  const size_t o_ctr = reserve(16);
+  const size_t o_ditem = reserve(dprefix.back() * 4);
+  const size_t o_gitem = reserve(gprefix.back() * 4);
   std::vector<uint8_t> host(sz, 0);
   memcpy(host.data() + o_dense, dense.data(), dense.size() * sizeof(DenseDesc));
   memcpy(host.data() + o_dp, dprefix.data(), dprefix.size() * 8);
@@ -152,6 +153,14 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   memcpy(host.data() + o_gp, gprefix.data(), gprefix.size() * 8);
   memcpy(host.data() + o_tot, totals.data(), totals.size() * sizeof(ScanTotalsDesc));
   memcpy(host.data() + o_reb, rebase.data(), rebase.size() * sizeof(RebaseDesc));
+  {
+    uint32_t* di = (uint32_t*)(host.data() + o_ditem);
+    for (size_t k = 0; k + 1 < dprefix.size(); ++k)
+      for (uint64_t t = dprefix[k]; t < dprefix[k + 1]; ++t) di[t] = (uint32_t)k;
+    uint32_t* gi = (uint32_t*)(host.data() + o_gitem);
+    for (size_t k = 0; k + 1 < gprefix.size(); ++k)
+      for (uint64_t t = gprefix[k]; t < gprefix[k + 1]; ++t) gi[t] = (uint32_t)k;
+  }
   out->release();
   hipError_t e = hipMalloc(&out->mem, sz);
   if (e != hipSuccess) return fail(RL_ENOMEM, "batch tables (%zu bytes): %s", sz, hipGetErrorString(e));
@@ -160,6 +169,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   BatchTables& t = out->t;
   t.dense = (const DenseDesc*)(out->mem + o_dense);
   t.dense_prefix = (const uint64_t*)(out->mem + o_dp);
+  t.dense_item = (const uint32_t*)(out->mem + o_ditem);
+  t.gather_item = (const uint32_t*)(out->mem + o_gitem);
   t.n_dense = (uint32_t)dense.size();
   t.dense_tiles = (uint32_t)dprefix.back();
   t.gather = (const GatherDesc*)(out->mem + o_gather);
@@ -170,7 +181,6 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   t.n_totals = (uint32_t)totals.size();
   t.rebase = (const RebaseDesc*)(out->mem + o_reb);
   t.n_rebase = (uint32_t)rebase.size();
-  t.counters = (uint32_t*)(out->mem + o_ctr);
   out->dense_lds = dense_lds;
   out->gather_lds = gather_lds;
   (void)c;

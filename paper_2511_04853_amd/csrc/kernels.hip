@@ -682,61 +682,29 @@ __global__ void clear_status_kernel(uint32_t* status) { *status = 0; }
 
 // ------------------------------------------------------------------ batches
 
-// Item of a flat tile space: binary search of the tile prefix (n + 1
-// entries, prefix[0] = 0) for the last item whose first tile is <= t.
-__device__ __forceinline__ uint32_t find_item(const uint64_t* prefix, uint32_t n, uint64_t t) {
-  uint32_t lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (prefix[mid] <= t) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// Next ticket of a persistent grid (one atomic per work-group, broadcast
-// through LDS).  Tickets are handed out in increasing order, so every
-// work-group runs until the tile space is exhausted.
-__device__ __forceinline__ uint32_t take_ticket(uint32_t* counter, uint32_t* slot) {
-  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1u);
-  __syncthreads();
-  const uint32_t t = *slot;
-  __syncthreads();
-  return t;
-}
-
-// The last work-group out resets the counters for the next launch (kernel
-// boundaries order the reset before the next launch's first ticket).
-__device__ __forceinline__ void retire(uint32_t* counter, uint32_t* done) {
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(done, 1u);
-    if (prev == gridDim.x - 1) {
-      atomicExch(counter, 0u);
-      atomicExch(done, 0u);
+// Every dense step of every item: the tiles of all items form one space;
+// work-group w takes tiles w, w + grid, ... (no shared counters: same-address
+// atomics from thousands of work-groups serialise in L2).  The item of a
+// tile comes from a host-built map.
+struct BatchTiles {
+  const BatchTables* b;
+  uint64_t t;
+  __device__ TileJob operator()() {
+    while (t < b->dense_tiles) {
+      const uint32_t item = __builtin_amdgcn_readfirstlane(b->dense_item[t]);
+      TileJob j{1, item, t - b->dense_prefix[item], 0, 0};
+      t += gridDim.x;
+      dense_count(b->dense[item], &j.count, &j.base);
+      if (j.tile * b->dense[item].tile < j.count) return j;   // else: beyond a device-side count
     }
+    return TileJob{0, 0, 0, 0, 0};
   }
-}
+};
 
-// Every dense step of every item: the tiles of all items form one space,
-// walked by a persistent grid taking tickets.
 __global__ void __launch_bounds__(256, 4) batch_dense_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
-  __shared__ uint32_t ticket;
-  dense_pipeline(
-      reinterpret_cast<uint8_t*>(smem_raw),
-      [&]() {
-        while (true) {
-          const uint32_t t = take_ticket(b.counters + 0, &ticket);
-          if (t >= b.dense_tiles) return TileJob{0, 0, 0, 0, 0};
-          const uint32_t item = __builtin_amdgcn_readfirstlane(find_item(b.dense_prefix, b.n_dense, t));
-          const DenseDesc& d = b.dense[item];
-          TileJob j{1, item, t - b.dense_prefix[item], 0, 0};
-          dense_count(d, &j.count, &j.base);
-          if (j.tile * d.tile < j.count) return j;   // else: beyond a device-side count
-        }
-      },
-      [&](uint32_t item) -> const DenseDesc& { return b.dense[item]; });
-  retire(b.counters + 0, b.counters + 1);
+  dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw), BatchTiles{&b, blockIdx.x},
+                 [&](uint32_t item) -> const DenseDesc& { return b.dense[item]; });
 }
 
 // Tile-total scans (one work-group each) and offsets rebases.
@@ -747,18 +715,14 @@ __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   else if (j - b.n_totals < b.n_rebase) rebase_range(b.rebase[j - b.n_totals], threadIdx.x, blockDim.x);
 }
 
-// Every gather tile of every jagged item, persistent like the dense kernel.
+// Every gather tile of every jagged item, strided like the dense kernel.
 __global__ void __launch_bounds__(1024) batch_gather_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
-  __shared__ uint32_t ticket;
-  while (true) {
-    const uint32_t t = take_ticket(b.counters + 2, &ticket);
-    if (t >= b.gather_tiles) break;
-    const uint32_t item = __builtin_amdgcn_readfirstlane(find_item(b.gather_prefix, b.n_gather, t));
+  for (uint64_t t = blockIdx.x; t < b.gather_tiles; t += gridDim.x) {
+    const uint32_t item = __builtin_amdgcn_readfirstlane(b.gather_item[t]);
     gather_tile(b.gather[item], t - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw));
     __syncthreads();
   }
-  retire(b.counters + 2, b.counters + 3);
 }
 
 // ------------------------------------------------------------------ launchers

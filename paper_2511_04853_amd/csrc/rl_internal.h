@@ -155,17 +155,18 @@ struct RebaseDesc {
 struct BatchTables {
   const DenseDesc* dense;
   const uint64_t* dense_prefix;     // first tile of each dense step
+  const uint32_t* dense_item;       // tile -> dense step
   uint32_t n_dense;
   uint32_t dense_tiles;
   const GatherDesc* gather;
   const uint64_t* gather_prefix;
+  const uint32_t* gather_item;      // tile -> gather step
   uint32_t n_gather;
   uint32_t gather_tiles;
   const ScanTotalsDesc* totals;
   uint32_t n_totals;
   uint32_t n_rebase;
   const RebaseDesc* rebase;
-  uint32_t* counters;               // tickets and retire counts (4 words, zero between launches)
 };
 
 // ---- kernel launchers (kernels.hip) ----
