@@ -194,6 +194,7 @@ def main():
     }
 
     if not args.no_extras:
+        out["serving"] = serving(P, W, torch, stream)
         out["batched"] = batched(P, W, torch, stream, tune_cache)
         out["sweep"] = sweep(P, W, torch, stream)
         out["h2d"] = h2d_rate(P, W, torch, stream, S, aos, dsts[0], v)
@@ -325,6 +326,99 @@ def batched(P, W, torch, stream, tune_cache):
     res["speedup"] = round(res["loop"]["ms"] / res["graph"]["ms"], 3)
     del keep, b
     torch.cuda.empty_cache()
+    return res
+
+
+def serving(P, W, torch, stream, rates=(1000, 3000), n_events=3000, hold=512, pool_events=64):
+    """Open-loop Poisson arrivals; each event one collection per schema
+    (plain / cell / cluster, log-normal sizes with medians 10k / 100k / 20k,
+    sigma 0.5) in pinned host AoS memory; converted into device SoA under a
+    16 GB budget; results held until 512 newer events are done."""
+    import threading
+    decls = [W.PLAIN8, W.CELL, W.CLUSTER]
+    schemas = [P.Schema(d) for d in decls]
+    src_l = [P.Layout(S, "aos", space="pinned") for S in schemas]
+    dev_aos = [P.Layout(S, "aos") for S in schemas]
+    dst_l = [P.Layout(S, "soa", storage=["f32" if f.type == "f64" else f.type for f in d.fields if f.group < 0]
+                      if d is W.CELL else None) for S, d in zip(schemas, decls)]
+    sizes = W.serving_events(pool_events)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1004)
+    events = []
+    for row in sizes:
+        items = []
+        for j, (S, d) in enumerate(zip(schemas, decls)):
+            n = int(row[j])
+            vals = P.Layout(S, "soa")
+            bufs = [torch.randint(0, 256, (n * W.TYPE_SIZE[f.type],), dtype=torch.uint8, device="cuda",
+                                  generator=g) for f in d.fields if f.group < 0]
+            mem = []
+            if d.offset_types:
+                lens = torch.poisson(torch.full((n,), 40.0, device="cuda"), generator=g).to(torch.int64)
+                offs = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+                offs[1:] = torch.cumsum(lens, 0)
+                tot = int(offs[-1].item())
+                mem = [tot]
+                bufs.append(offs.to(torch.int32).view(torch.uint8))
+                bufs += [torch.randint(0, 256, (tot * W.TYPE_SIZE[f.type],), dtype=torch.uint8, device="cuda",
+                                       generator=g) for f in d.fields if f.group >= 0]
+            if d is W.CELL:   # valid doubles in the narrowed field
+                bufs[6] = (torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 1e3).view(torch.uint8)
+            daos = [torch.empty(x, dtype=torch.uint8, device="cuda") for x in dev_aos[j].buffer_bytes(n, mem)]
+            P.convert(P.View(vals, n, bufs, mem), P.View(dev_aos[j], n, daos, mem), n)
+            pinned = [torch.empty(t.numel(), dtype=torch.uint8, pin_memory=True) for t in daos]
+            for h_, t in zip(pinned, daos):
+                h_.copy_(t)
+            items.append((P.View(src_l[j], n, pinned, mem), dst_l[j], n))
+        events.append(items)
+    assert P.sync(stream) == 0
+    torch.cuda.synchronize()
+    ev_bytes = [sum(sum(v.layout.buffer_bytes(n, list(v._mcap)[:1] if v.layout.schema.n_groups else []))
+                    for v, _, n in items) for items in events]
+    res = {"event_pool": pool_events, "mean_event_h2d_MB": round(float(np.mean(ev_bytes)) / 1e6, 2),
+           "budget_GB": 16, "hold": hold}
+    for rate in rates:
+        srv = P.Server(16 << 30, max_in_flight=32, n_streams=8)
+        arrivals = W.poisson_arrivals(n_events, rate)
+        tickets = [None] * n_events
+        lock = threading.Lock()
+
+        def producer():
+            t0 = time.perf_counter()
+            for k in range(n_events):
+                while time.perf_counter() - t0 < arrivals[k]:
+                    pass
+                t = srv.submit(events[k % pool_events])
+                with lock:
+                    tickets[k] = t
+
+        th = threading.Thread(target=producer)
+        t_start = time.perf_counter()
+        th.start()
+        released = 0
+        for k in range(n_events):
+            while True:
+                with lock:
+                    t = tickets[k]
+                if t is not None:
+                    break
+                time.sleep(0.0001)
+            r = srv.wait(t)
+            assert r["status"] == 0
+            while released <= k - hold:
+                srv.release(tickets[released])
+                released += 1
+        th.join()
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        while released < n_events:
+            srv.release(tickets[released])
+            released += 1
+        srv.close()
+        res[f"{rate}/s"] = {"events": n_events, "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                            "max_ms": round(st["max_ms"], 3), "events_per_s": round(st["events_per_s"], 1),
+                            "link_GBps": round(st["h2d_bytes"] / wall / 1e9, 2),
+                            "peak_resident_GB": round(st["peak_bytes"] / 1e9, 3)}
     return res
 
 

@@ -282,3 +282,54 @@ def sync(stream=None):
 def transfer(src: View, dst: View, n: int, stream=None, mode="auto", chunk_bytes=0, n_slots=0):
     o = rl_xfer_opts(XFER_MODES[mode], chunk_bytes, n_slots)
     check(lib().rl_transfer(src.ref(), dst.ref(), n, stream_ptr(stream), ctypes.byref(o)), "rl_transfer")
+
+
+class Server:
+    """An rl_server: submit events (lists of (host View, device Layout, n)),
+    wait for them, release their resident results."""
+
+    def __init__(self, budget_bytes, max_in_flight=8, n_streams=4):
+        h = ctypes.c_void_p()
+        o = rl_server_opts(budget_bytes, max_in_flight, n_streams)
+        check(lib().rl_server_create(ctypes.byref(o), ctypes.byref(h)), "rl_server_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, items):
+        arr = (rl_event_item * max(1, len(items)))()
+        for k, (view, layout, n) in enumerate(items):
+            arr[k] = rl_event_item(view.c, layout.handle, n)
+        ev = rl_event(arr, len(items))
+        t = ctypes.c_uint64()
+        check(lib().rl_server_submit(self.h, ctypes.byref(ev), ctypes.byref(t)), "rl_server_submit")
+        self._keep[t.value] = (arr, items)
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        r = rl_event_result()
+        st = lib().rl_server_wait(self.h, ticket, timeout_ms, ctypes.byref(r))
+        if st == RL_EBUSY:
+            return None
+        check(st, "rl_server_wait")
+        out = {"latency_ns": r.latency_ns, "bytes": r.bytes, "status": r.status, "buffers": []}
+        _, items = self._keep[ticket]
+        for k, (view, layout, n) in enumerate(items):
+            out["buffers"].append([r.buffers[k][b] for b in range(layout.max_buffers)])
+        return out
+
+    def release(self, ticket):
+        check(lib().rl_server_release(self.h, ticket), "rl_server_release")
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        s = rl_server_stats()
+        check(lib().rl_server_stats_get(self.h, ctypes.byref(s)), "rl_server_stats_get")
+        return {k: getattr(s, k) for k, _ in rl_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rl_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,19 +1,333 @@
-// Serving loop (placeholder entry points until the server lands).
+// Serving loop: events (one or more collections each, in pinned host
+// memory) arrive at any time; a scheduler thread admits them in arrival
+// order while their result bytes fit a device-memory budget and an
+// in-flight slot is free, converts them with host -> device transfers on
+// the server's streams (events overlap on the device), and keeps the
+// converted collections resident in a pool carved from one device slab
+// until the client releases them.  Completion is observed by polling
+// events; latency is submit -> last conversion done.
+#include <math.h>
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
 #include "plan.h"
+#include "pool.h"
 #include "rl_internal.h"
 
 using namespace rl;
 
-struct rl_server {
-  int unused;
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class EvState { QUEUED, RUNNING, DONE, RELEASED };
+
+struct ItemCopy {
+  const rl_layout* src_layout;
+  const rl_layout* dst_layout;
+  uint64_t n, src_cap;
+  std::vector<void*> src_bufs;
+  std::vector<uint64_t> src_mcap;
+  std::vector<uint64_t> dst_mcap;      // member capacity of the result
+  std::vector<uint64_t> dst_bytes;     // bytes of each result buffer
+  std::vector<uint64_t> dst_offsets;   // pool offsets of the result buffers
+  std::vector<void*> dst_bufs;
 };
 
-extern "C" rl_status rl_server_create(const rl_server_opts*, rl_server** out) {
-  if (out) *out = nullptr;
-  return fail(RL_EUNSUPPORTED, "serving is not available yet");
+struct Event {
+  uint64_t ticket;
+  Clock::time_point submitted, done_at;
+  std::vector<ItemCopy> items;
+  uint64_t bytes = 0;
+  EvState state = EvState::QUEUED;
+  hipEvent_t done = nullptr;
+  uint32_t stream = 0;
+  rl_status status = RL_OK;
+  // result views handed to the client
+  std::vector<void* const*> buf_ptrs;
+  std::vector<uint64_t> mcaps;
+};
+
+}  // namespace
+
+struct rl_server {
+  rl_server_opts opts{};
+  int device = 0;
+  std::vector<hipStream_t> streams;
+  uint8_t* slab = nullptr;
+  SlabAllocator pool;
+  std::mutex mu;
+  std::condition_variable cv_done;   // events finished
+  std::condition_variable cv_work;   // new submissions or releases
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, std::unique_ptr<Event>> events;
+  uint64_t next_ticket = 1;
+  uint32_t running = 0;
+  uint32_t next_stream = 0;
+  bool stop = false;
+  std::thread scheduler;
+  // statistics
+  std::vector<double> lat_ms;
+  uint64_t submitted = 0, completed = 0, peak = 0, h2d_bytes = 0;
+  Clock::time_point first_submit, last_done;
+  bool any = false;
+};
+
+namespace {
+
+uint64_t event_bytes(Event& e) {
+  uint64_t total = 0;
+  for (auto& it : e.items) total += [&] {
+    uint64_t s = 0;
+    for (auto b : it.dst_bytes) s += (b + 255) / 256 * 256;
+    return s;
+  }();
+  return total;
 }
-extern "C" rl_status rl_server_submit(rl_server*, const rl_event*, uint64_t*) { return fail(RL_EUNSUPPORTED, "serving"); }
-extern "C" rl_status rl_server_wait(rl_server*, uint64_t, int64_t, rl_event_result*) { return fail(RL_EUNSUPPORTED, "serving"); }
-extern "C" rl_status rl_server_release(rl_server*, uint64_t) { return fail(RL_EUNSUPPORTED, "serving"); }
-extern "C" rl_status rl_server_stats_get(rl_server*, rl_server_stats*) { return fail(RL_EUNSUPPORTED, "serving"); }
-extern "C" void rl_server_destroy(rl_server*) {}
+
+// Admit queued events in arrival order while they fit (caller holds mu).
+void admit(rl_server* s) {
+  while (!s->queue.empty() && s->running < s->opts.max_in_flight) {
+    Event& e = *s->events[s->queue.front()];
+    std::vector<uint64_t> sizes;
+    for (auto& it : e.items)
+      for (auto b : it.dst_bytes) sizes.push_back(b);
+    if (!s->pool.fits(sizes)) break;   // head of line waits for releases
+    for (auto& it : e.items) {
+      it.dst_offsets.clear();
+      it.dst_bufs.clear();
+      for (auto b : it.dst_bytes) {
+        const uint64_t off = s->pool.alloc(b);
+        it.dst_offsets.push_back(off);
+        it.dst_bufs.push_back(b ? s->slab + off : nullptr);
+      }
+    }
+    s->peak = std::max<uint64_t>(s->peak, s->pool.in_use());
+    s->queue.pop_front();
+    e.stream = s->next_stream;
+    s->next_stream = (s->next_stream + 1) % (uint32_t)s->streams.size();
+    hipStream_t st = s->streams[e.stream];
+    for (auto& it : e.items) {
+      rl_view sv{it.src_layout, it.src_cap, it.src_mcap.empty() ? nullptr : it.src_mcap.data(),
+                 it.src_bufs.data()};
+      rl_view dv{it.dst_layout, it.n, it.dst_mcap.empty() ? nullptr : it.dst_mcap.data(), it.dst_bufs.data()};
+      rl_xfer_opts o{RL_XFER_AUTO, 0, 0};
+      const rl_status r = rl_transfer(&sv, &dv, it.n, st, &o);
+      if (r != RL_OK && e.status == RL_OK) e.status = r;
+      std::vector<uint64_t> hb(layout_n_buffers(it.src_layout));
+      layout_buffer_bytes(it.src_layout, it.n, it.src_mcap.empty() ? nullptr : it.src_mcap.data(), hb.data());
+      for (auto b : hb) s->h2d_bytes += b;
+    }
+    if (hipEventRecord(e.done, st) != hipSuccess && e.status == RL_OK) e.status = RL_EHIP;
+    e.state = EvState::RUNNING;
+    ++s->running;
+  }
+}
+
+// Mark finished events (caller holds mu); true if any finished.
+bool reap(rl_server* s) {
+  bool any = false;
+  for (auto& kv : s->events) {
+    Event& e = *kv.second;
+    if (e.state != EvState::RUNNING) continue;
+    const hipError_t q = hipEventQuery(e.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess && e.status == RL_OK) e.status = RL_EHIP;
+    e.state = EvState::DONE;
+    e.done_at = Clock::now();
+    const double ms = std::chrono::duration<double, std::milli>(e.done_at - e.submitted).count();
+    s->lat_ms.push_back(ms);
+    ++s->completed;
+    s->last_done = e.done_at;
+    --s->running;
+    any = true;
+  }
+  return any;
+}
+
+void scheduler_loop(rl_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    const bool finished = reap(s);
+    admit(s);
+    if (finished) s->cv_done.notify_all();
+    if (s->running == 0 && (s->queue.empty() || !finished))
+      s->cv_work.wait_for(lk, std::chrono::microseconds(s->running ? 20 : 2000));
+    else {
+      // poll completions at a short period while work is on the device
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(10));
+      lk.lock();
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" rl_status rl_server_create(const rl_server_opts* opts, rl_server** out) {
+  if (!opts || !out) return fail(RL_EINVAL, "rl_server_create: NULL argument");
+  *out = nullptr;
+  if (!opts->budget_bytes || !opts->max_in_flight || !opts->n_streams || opts->n_streams > 64)
+    return fail(RL_EINVAL, "budget, slots and 1..64 streams are required");
+  auto s = std::make_unique<rl_server>();
+  s->opts = *opts;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if ((e = hipMalloc(&s->slab, opts->budget_bytes)) != hipSuccess)
+    return fail(RL_ENOMEM, "serving pool of %llu bytes: %s", (unsigned long long)opts->budget_bytes,
+                hipGetErrorString(e));
+  s->pool.reset(opts->budget_bytes, 256);
+  for (uint32_t k = 0; k < opts->n_streams; ++k) {
+    hipStream_t st;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
+      for (auto x : s->streams) (void)hipStreamDestroy(x);
+      (void)hipFree(s->slab);
+      return hip_fail(e, "hipStreamCreate");
+    }
+    s->streams.push_back(st);
+  }
+  rl_server* raw = s.release();
+  raw->scheduler = std::thread(scheduler_loop, raw);
+  *out = raw;
+  return RL_OK;
+}
+
+extern "C" rl_status rl_server_submit(rl_server* s, const rl_event* ev, uint64_t* ticket) {
+  if (!s || !ev || !ticket || (ev->n_items && !ev->items)) return fail(RL_EINVAL, "rl_server_submit: NULL argument");
+  auto e = std::make_unique<Event>();
+  for (uint32_t k = 0; k < ev->n_items; ++k) {
+    const rl_event_item& it = ev->items[k];
+    std::vector<Range> rs;
+    rl_status st = validate_view(&it.src, it.n, "src", &rs, false);
+    if (st) return st;
+    if (!it.dst_layout || it.dst_layout->schema != it.src.layout->schema)
+      return fail(RL_EINVAL, "item %u: destination layout of another schema", k);
+    if (it.src.layout->space != RL_SPACE_HOST_PINNED && it.src.layout->space != RL_SPACE_HOST)
+      return fail(RL_EINVAL, "item %u: sources are host collections", k);
+    if (it.dst_layout->space != RL_SPACE_DEVICE) return fail(RL_EINVAL, "item %u: results live on the device", k);
+    if (it.dst_layout->kind == RL_AOSOA && it.dst_layout->width == 0)
+      return fail(RL_EINVAL, "item %u: auto block width is for batches", k);
+    ItemCopy c;
+    c.src_layout = it.src.layout;
+    c.dst_layout = it.dst_layout;
+    c.n = it.n;
+    c.src_cap = it.src.capacity;
+    c.src_bufs.assign(it.src.buffers, it.src.buffers + layout_n_buffers(it.src.layout));
+    const size_t ng = it.src.layout->schema->members.size();
+    if (ng) {
+      c.src_mcap.assign(it.src.member_capacity, it.src.member_capacity + ng);
+      // results hold at most the source's members
+      c.dst_mcap = c.src_mcap;
+    }
+    c.dst_bytes.resize(layout_n_buffers(it.dst_layout));
+    layout_buffer_bytes(it.dst_layout, it.n, c.dst_mcap.empty() ? nullptr : c.dst_mcap.data(), c.dst_bytes.data());
+    e->items.push_back(std::move(c));
+  }
+  e->bytes = event_bytes(*e);
+  if (e->bytes > s->pool.capacity())
+    return fail(RL_EBUDGET, "event needs %llu bytes, budget is %llu", (unsigned long long)e->bytes,
+                (unsigned long long)s->pool.capacity());
+  hipError_t he = hipEventCreateWithFlags(&e->done, hipEventDisableTiming);
+  if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+  std::lock_guard<std::mutex> lk(s->mu);
+  e->ticket = s->next_ticket++;
+  e->submitted = Clock::now();
+  if (!s->any) {
+    s->first_submit = e->submitted;
+    s->any = true;
+  }
+  *ticket = e->ticket;
+  s->queue.push_back(e->ticket);
+  s->events[e->ticket] = std::move(e);
+  ++s->submitted;
+  s->cv_work.notify_one();
+  return RL_OK;
+}
+
+extern "C" rl_status rl_server_wait(rl_server* s, uint64_t ticket, int64_t timeout_ms, rl_event_result* res) {
+  if (!s) return fail(RL_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->events.find(ticket);
+  if (it == s->events.end()) return fail(RL_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Event* e = it->second.get();
+  auto done = [&] { return e->state == EvState::DONE || e->state == EvState::RELEASED; };
+  if (timeout_ms < 0) s->cv_done.wait(lk, done);
+  else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
+    return fail(RL_EBUSY, "event %llu not done", (unsigned long long)ticket);
+  if (e->state == EvState::RELEASED) return fail(RL_EINVAL, "event %llu already released", (unsigned long long)ticket);
+  if (res) {
+    e->buf_ptrs.clear();
+    e->mcaps.clear();
+    for (auto& c : e->items) {
+      e->buf_ptrs.push_back(c.dst_bufs.data());
+      for (auto m : c.dst_mcap) e->mcaps.push_back(m);
+    }
+    res->n_items = (uint32_t)e->items.size();
+    res->latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(e->done_at - e->submitted).count();
+    res->bytes = e->bytes;
+    res->buffers = e->buf_ptrs.data();
+    res->member_capacity = e->mcaps.empty() ? nullptr : e->mcaps.data();
+    res->status = e->status;
+  }
+  return e->status;
+}
+
+extern "C" rl_status rl_server_release(rl_server* s, uint64_t ticket) {
+  if (!s) return fail(RL_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->events.find(ticket);
+  if (it == s->events.end()) return fail(RL_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Event* e = it->second.get();
+  if (e->state != EvState::DONE) return fail(RL_EBUSY, "event %llu not done", (unsigned long long)ticket);
+  for (auto& c : e->items)
+    for (size_t b = 0; b < c.dst_offsets.size(); ++b) s->pool.release(c.dst_offsets[b]);
+  (void)hipEventDestroy(e->done);
+  s->events.erase(it);
+  s->cv_work.notify_one();
+  return RL_OK;
+}
+
+extern "C" rl_status rl_server_stats_get(rl_server* s, rl_server_stats* out) {
+  if (!s || !out) return fail(RL_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  memset(out, 0, sizeof *out);
+  out->completed = s->completed;
+  out->submitted = s->submitted;
+  out->p50_ms = percentile(s->lat_ms, 50);
+  out->p99_ms = percentile(s->lat_ms, 99);
+  out->max_ms = percentile(s->lat_ms, 100);
+  if (s->completed && s->any) {
+    const double sec = std::chrono::duration<double>(s->last_done - s->first_submit).count();
+    out->events_per_s = sec > 0 ? (double)s->completed / sec : 0.0;
+  }
+  out->peak_bytes = s->peak;
+  out->h2d_bytes = s->h2d_bytes;
+  return RL_OK;
+}
+
+extern "C" void rl_server_destroy(rl_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->scheduler.joinable()) s->scheduler.join();
+  for (auto st : s->streams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (auto& kv : s->events)
+    if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+  if (s->slab) (void)hipFree(s->slab);
+  delete s;
+}

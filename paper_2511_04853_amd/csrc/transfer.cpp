@@ -284,7 +284,9 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
   if (o.n_slots > kMaxSlots) return fail(RL_EINVAL, "at most %u staging slots", kMaxSlots);
   const rl_layout* HL = h2d ? SL : DL;
   const rl_view& hv = h2d ? *src : *dst;
-  if (o.mode == RL_XFER_AUTO) o.mode = RL_XFER_STAGED;
+  // auto: dense collections in pinned memory are read (or written) in place
+  // by the conversion kernels; others go through device staging
+  if (o.mode == RL_XFER_AUTO) o.mode = (!jagged && HL->space == RL_SPACE_HOST_PINNED) ? RL_XFER_ZERO_COPY : RL_XFER_STAGED;
   if (o.mode == RL_XFER_ZERO_COPY) {
     if (HL->space != RL_SPACE_HOST_PINNED) return fail(RL_EUNSUPPORTED, "zero-copy needs pinned host memory");
     const uint32_t nb = layout_n_buffers(HL);
