@@ -221,16 +221,17 @@ rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t group,
 
 /* Options of rl_transfer. */
 typedef enum rl_xfer_mode {
-  RL_XFER_AUTO = 0,      /* choose by size and spaces */
-  RL_XFER_STAGED = 1,    /* SDMA copies into device staging slots,
-                            overlapped with conversion kernels */
-  RL_XFER_ZERO_COPY = 2  /* kernels read/write pinned host memory directly */
+  RL_XFER_AUTO = 0,      /* zero-copy for pinned collections without jagged
+                            groups, staged otherwise */
+  RL_XFER_STAGED = 1,    /* DMA copies of the host buffers into a
+                            stream-ordered device allocation, conversion
+                            from (or into) it, on the caller's stream */
+  RL_XFER_ZERO_COPY = 2  /* the conversion kernels read/write the pinned
+                            host buffers directly (one pass, no staging) */
 } rl_xfer_mode;
 
 typedef struct rl_xfer_opts {
   rl_xfer_mode mode;
-  uint64_t chunk_bytes;  /* staged: bytes of source per chunk (0 = 4 MiB) */
-  uint32_t n_slots;      /* staged: staging slots in flight (0 = 3, max 8) */
 } rl_xfer_opts;
 
 /* Convert objects 0..n-1 between a host view and a device view (Sec. VII-A:

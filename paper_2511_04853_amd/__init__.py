@@ -59,8 +59,7 @@ class rl_view(ctypes.Structure):
 
 
 class rl_xfer_opts(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int), ("chunk_bytes", ctypes.c_uint64),
-                ("n_slots", ctypes.c_uint32)]
+    _fields_ = [("mode", ctypes.c_int)]
 
 
 class rl_batch_opts(ctypes.Structure):
@@ -279,8 +278,8 @@ def sync(stream=None):
     return lib().rl_sync(stream_ptr(stream))
 
 
-def transfer(src: View, dst: View, n: int, stream=None, mode="auto", chunk_bytes=0, n_slots=0):
-    o = rl_xfer_opts(XFER_MODES[mode], chunk_bytes, n_slots)
+def transfer(src: View, dst: View, n: int, stream=None, mode="auto"):
+    o = rl_xfer_opts(XFER_MODES[mode])
     check(lib().rl_transfer(src.ref(), dst.ref(), n, stream_ptr(stream), ctypes.byref(o)), "rl_transfer")
 
 

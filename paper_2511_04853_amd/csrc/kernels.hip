@@ -583,6 +583,78 @@ __global__ void __launch_bounds__(1024) scan_totals_kernel(const ScanTotalsDesc 
 
 // Add tile prefixes, then copy the members of the tile's objects from the
 // pool into the member columns.  One work-group per tile (grid-stride).
+// Members [m_lo, m_hi) of a tile, four consecutive members per thread
+// (groups aligned to 4 member indices): one binary search per group for the
+// owner of its first member, then the owner advances member by member.
+// NW > 0: every member leaf is a 4-byte word at offset 4k of a packed
+// record of NW words, and every member column is 16-byte aligned; each
+// column then receives one 16-byte store per full group.  NW == 0: any
+// member record, value by value.  Every read stays inside the member block
+// the object's record validated against the pool (vlen).
+template <uint32_t NW>
+__device__ __forceinline__ void gather_members(const GatherDesc& d, const uint64_t* offs, const uint64_t* ptrs,
+                                               const uint32_t* vlen, uint32_t cnt, uint64_t m_lo, uint64_t m_hi) {
+  const uint64_t start = m_lo & ~3ull;
+  const uint64_t ngroups = (m_hi - start + 3) >> 2;
+  for (uint64_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+    const uint64_t base = start + 4 * g;
+    const uint64_t first = base < m_lo ? m_lo : base;
+    uint32_t lo = 0, hi = cnt;   // owner of `first`: last object with offs <= first
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (offs[mid] <= first) lo = mid; else hi = mid;
+    }
+    const uint8_t* src[4];
+    bool ok[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint64_t m = base + k;
+      ok[k] = false;
+      src[k] = nullptr;
+      if (m < m_lo || m >= m_hi) continue;
+      while (lo + 1 < cnt && offs[lo + 1] <= m) ++lo;
+      const uint64_t j = m - offs[lo];
+      if (m < offs[lo] || j >= vlen[lo]) continue;
+      ok[k] = true;
+      src[k] = d.pool + ptrs[lo] + j * d.mstride;
+    }
+    if (NW > 0) {
+      uint32_t w[4][NW > 0 ? NW : 1];
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+        for (uint32_t q = 0; q < NW; ++q) w[k][q] = ok[k] ? reinterpret_cast<const uint32_t*>(src[k])[q] : 0u;
+      const bool full = ok[0] && ok[1] && ok[2] && ok[3];
+#pragma unroll
+      for (uint32_t q = 0; q < NW; ++q) {
+        uint32_t* col = reinterpret_cast<uint32_t*>(d.mcol[q]);
+        if (full) {
+          *reinterpret_cast<v4u*>(col + base) = v4u{w[0][q], w[1][q], w[2][q], w[3][q]};
+        } else {
+#pragma unroll
+          for (uint32_t k = 0; k < 4; ++k)
+            if (ok[k]) col[base + k] = w[k][q];
+        }
+      }
+    } else {
+      for (uint32_t q = 0; q < d.n_members; ++q) {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+          if (!ok[k]) continue;
+          const uint8_t* s = src[k] + d.moff[q];
+          uint8_t* dst = d.mcol[q] + (base + k) * d.msize[q];
+          switch (d.msize[q]) {
+            case 1: *dst = *s; break;
+            case 2: *reinterpret_cast<uint16_t*>(dst) = *reinterpret_cast<const uint16_t*>(s); break;
+            case 4: *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(s); break;
+            default: *reinterpret_cast<uint64_t*>(dst) = *reinterpret_cast<const uint64_t*>(s); break;
+          }
+        }
+      }
+    }
+  }
+}
+
 __device__ void gather_tile(const GatherDesc& d, uint64_t t, uint8_t* smem) {
   uint64_t* offs = reinterpret_cast<uint64_t*>(smem);               // tile + 1
   uint64_t* ptrs = offs + (d.tile + 1);                             // tile
@@ -620,27 +692,13 @@ __device__ void gather_tile(const GatherDesc& d, uint64_t t, uint8_t* smem) {
     const uint64_t m_lo = offs[0];
     uint64_t m_hi = offs[cnt];
     if (m_hi > d.capacity) m_hi = d.capacity;
-    for (uint64_t mm = m_lo + tid; mm < m_hi; mm += nt) {
-      // owner: the last object whose first member index is <= mm
-      uint32_t lo = 0, hi = cnt;  // offs[lo] <= mm < offs[hi] when well formed
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (offs[mid] <= mm) lo = mid; else hi = mid;
-      }
-      // j indexes the object's member block; reads stay inside the block the
-      // record validated against the pool, whatever the offsets hold
-      const uint64_t j = mm - offs[lo];
-      if (mm < offs[lo] || j >= vlen[lo]) continue;
-      const uint8_t* src = d.pool + ptrs[lo] + j * d.mstride;
-      for (uint32_t k = 0; k < d.n_members; ++k) {
-        const uint8_t* s = src + d.moff[k];
-        uint8_t* dst = d.mcol[k] + mm * d.msize[k];
-        switch (d.msize[k]) {
-          case 1: *dst = *s; break;
-          case 2: *reinterpret_cast<uint16_t*>(dst) = *reinterpret_cast<const uint16_t*>(s); break;
-          case 4: *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(s); break;
-          default: *reinterpret_cast<uint64_t*>(dst) = *reinterpret_cast<const uint64_t*>(s); break;
-        }
+    if (m_hi > m_lo) {
+      switch (d.packed_words) {
+        case 1: gather_members<1>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
+        case 2: gather_members<2>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
+        case 3: gather_members<3>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
+        case 4: gather_members<4>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
+        default: gather_members<0>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
       }
     }
     __syncthreads();

@@ -250,6 +250,11 @@ static rl_status push_scan_gather(Plan* plan, const rl_view& src, const rl_view&
       G.msize[m] = sc->members[g][m].size;
       G.mcol[m] = (uint8_t*)dst.buffers[mb + m];
     }
+    // fast path: packed 4-byte member words into 16-byte aligned columns
+    bool packed = G.n_members >= 1 && G.n_members <= 4 && G.mstride == 4 * G.n_members;
+    for (uint32_t m = 0; m < G.n_members && packed; ++m)
+      packed = G.msize[m] == 4 && G.moff[m] == 4 * m && ((uintptr_t)G.mcol[m] & 15) == 0;
+    G.packed_words = packed ? G.n_members : 0;
   }
   ga.threads = shape.threads ? shape.threads : 256;
   plan->steps.push_back(ga);

@@ -131,6 +131,7 @@ struct GatherDesc {
   uint32_t mstride;        // member record bytes
   uint32_t malign;         // member record alignment
   uint32_t n_members;      // member leaves (0: offsets only)
+  uint32_t packed_words;   // 1..4: member leaves are the words of a packed record (fast path); 0: generic
   const uint8_t* pool;
   uint64_t pool_bytes;
   uint32_t* status;

@@ -119,7 +119,7 @@ void admit(rl_server* s) {
       rl_view sv{it.src_layout, it.src_cap, it.src_mcap.empty() ? nullptr : it.src_mcap.data(),
                  it.src_bufs.data()};
       rl_view dv{it.dst_layout, it.n, it.dst_mcap.empty() ? nullptr : it.dst_mcap.data(), it.dst_bufs.data()};
-      rl_xfer_opts o{RL_XFER_AUTO, 0, 0};
+      rl_xfer_opts o{RL_XFER_AUTO};
       const rl_status r = rl_transfer(&sv, &dv, it.n, st, &o);
       if (r != RL_OK && e.status == RL_OK) e.status = r;
       std::vector<uint64_t> hb(layout_n_buffers(it.src_layout));

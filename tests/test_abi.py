@@ -148,9 +148,9 @@ def test_transfer_validation_on_the_host():
     # two device views: use rl_convert
     assert P.lib().rl_transfer(dev2.ref(), dev.ref(), 10, s0, None) == P.RL_EUNSUPPORTED
     host = _fake_view(sp.layout("aos", space="host"), 100, 1 << 40)
-    o = P.rl_xfer_opts(2, 0, 0)    # zero-copy from pageable memory
+    o = P.rl_xfer_opts(2)          # zero-copy from pageable memory
     assert P.lib().rl_transfer(host.ref(), dev.ref(), 10, s0, ctypes.byref(o)) == P.RL_EUNSUPPORTED
-    o = P.rl_xfer_opts(1, 0, 99)   # too many slots
+    o = P.rl_xfer_opts(7)          # no such mode
     assert P.lib().rl_transfer(host.ref(), dev.ref(), 10, s0, ctypes.byref(o)) == P.RL_EINVAL
 
 

@@ -289,10 +289,9 @@ def _pinned_from(bufs):
     return out
 
 
-@pytest.mark.parametrize("mode", ["staged", "zero_copy"])
+@pytest.mark.parametrize("mode", ["staged", "zero_copy", "auto"])
 @pytest.mark.parametrize("dst", [("soa", 0), ("aosoa", 64)], ids=str)
-@pytest.mark.parametrize("chunk", [0, 65536])
-def test_h2d_transfer_cell(mode, dst, chunk):
+def test_h2d_transfer_cell(mode, dst):
     sp = H.SchemaPair(W.CELL)
     v = W.cell_values(190_000, seed=1001)
     aos = sp.layout("aos", space="pinned")
@@ -303,7 +302,7 @@ def test_h2d_transfer_cell(mode, dst, chunk):
     ddst = H.alloc_device(dl.lib.buffer_bytes(v.n))
     sv = P.View(aos.lib, v.n, hsrc)
     dv = P.View(dl.lib, v.n, ddst)
-    P.transfer(sv, dv, v.n, mode=mode, chunk_bytes=chunk)
+    P.transfer(sv, dv, v.n, mode=mode)
     assert P.sync() == 0, P.rl_last_error()
     H.assert_same_bytes(H.to_numpy(ddst), want, f"h2d {mode}")
 
@@ -319,7 +318,7 @@ def test_d2h_transfer_cell(mode):
     st, want, _ = H.oracle_convert(soa, sbytes, aos, v.n, [], [])
     dsrc = H.to_device(sbytes)
     hdst = H.alloc_pinned(aos.lib.buffer_bytes(v.n))
-    P.transfer(P.View(soa.lib, v.n, dsrc), P.View(aos.lib, v.n, hdst), v.n, mode=mode, chunk_bytes=1 << 20)
+    P.transfer(P.View(soa.lib, v.n, dsrc), P.View(aos.lib, v.n, hdst), v.n, mode=mode)
     assert P.sync() == 0, P.rl_last_error()
     H.assert_same_bytes(H.to_numpy(hdst), want, f"d2h {mode}")
 
