@@ -114,7 +114,7 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   std::vector<GatherDesc> gather;
   std::vector<ScanTotalsDesc> totals;
   std::vector<RebaseDesc> rebase;
-  std::vector<uint64_t> dprefix{0}, gprefix{0};
+  std::vector<uint64_t> dprefix{0}, gprefix{0}, rprefix{0};
   uint32_t dense_lds = 0, gather_lds = 0;
   for (const Plan& p : b->plans)
     for (const Step& s : p.steps) {
@@ -130,7 +130,10 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
           gather_lds = std::max(gather_lds, (2 * s.gather.tile + 1) * 8 + s.gather.tile * 4);
           break;
         case Step::SCAN_TOTALS: totals.push_back(s.totals); break;
-        case Step::REBASE: rebase.push_back(s.rebase); break;
+        case Step::REBASE:
+          rebase.push_back(s.rebase);
+          rprefix.push_back(rprefix.back() + (s.rebase.n + 1 + kRebaseTile - 1) / kRebaseTile);
+          break;
       }
     }
   if (dprefix.back() >= (1ull << 32) || gprefix.back() >= (1ull << 32))
@@ -146,6 +149,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   const size_t o_reb = reserve(rebase.size() * sizeof(RebaseDesc));
   const size_t o_ditem = reserve(dprefix.back() * 4);
   const size_t o_gitem = reserve(gprefix.back() * 4);
+  const size_t o_rp = reserve(rprefix.size() * 8);
+  const size_t o_ritem = reserve(rprefix.back() * 4);
   std::vector<uint8_t> host(sz, 0);
   memcpy(host.data() + o_dense, dense.data(), dense.size() * sizeof(DenseDesc));
   memcpy(host.data() + o_dp, dprefix.data(), dprefix.size() * 8);
@@ -160,6 +165,10 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
     uint32_t* gi = (uint32_t*)(host.data() + o_gitem);
     for (size_t k = 0; k + 1 < gprefix.size(); ++k)
       for (uint64_t t = gprefix[k]; t < gprefix[k + 1]; ++t) gi[t] = (uint32_t)k;
+    memcpy(host.data() + o_rp, rprefix.data(), rprefix.size() * 8);
+    uint32_t* ri = (uint32_t*)(host.data() + o_ritem);
+    for (size_t k = 0; k + 1 < rprefix.size(); ++k)
+      for (uint64_t t = rprefix[k]; t < rprefix[k + 1]; ++t) ri[t] = (uint32_t)k;
   }
   out->release();
   hipError_t e = hipMalloc(&out->mem, sz);
@@ -181,6 +190,9 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   t.n_totals = (uint32_t)totals.size();
   t.rebase = (const RebaseDesc*)(out->mem + o_reb);
   t.n_rebase = (uint32_t)rebase.size();
+  t.rebase_prefix = (const uint64_t*)(out->mem + o_rp);
+  t.rebase_item = (const uint32_t*)(out->mem + o_ritem);
+  t.rebase_tiles = (uint32_t)rprefix.back();
   out->dense_lds = dense_lds;
   out->gather_lds = gather_lds;
   (void)c;
@@ -411,7 +423,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
 
 extern "C" rl_status rl_batch_launch(rl_batch* b, void* stream) {
   if (!b || !b->finalized) return fail(RL_EINVAL, "batch not finalized");
-  if (!b->dev.t.dense_tiles && !b->dev.t.gather_tiles && !b->dev.t.n_totals && !b->dev.t.n_rebase) return RL_OK;
+  if (!b->dev.t.dense_tiles && !b->dev.t.gather_tiles && !b->dev.t.n_totals && !b->dev.t.rebase_tiles) return RL_OK;
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
   return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphLaunch");
 }

@@ -717,9 +717,10 @@ __global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
 // Offsets column -> offsets column, rebased to start at 0, with the checks
 // of a well-formed source (non-decreasing, inside the source capacity) and
 // of the destination capacity.
-__device__ void rebase_range(const RebaseDesc& d, uint64_t begin, uint64_t step) {
+__device__ void rebase_range(const RebaseDesc& d, uint64_t begin, uint64_t step, uint64_t last) {
   const uint64_t first = load_off(d.src, d.off_type, 0);
-  for (uint64_t i = begin; i <= d.n; i += step) {
+  if (last > d.n) last = d.n;
+  for (uint64_t i = begin; i <= last; i += step) {
     const uint64_t a = load_off(d.src, d.off_type, i);
     if (d.dst) store_off(d.dst, d.off_type, i, a - first);
     if (i < d.n) {
@@ -733,7 +734,7 @@ __device__ void rebase_range(const RebaseDesc& d, uint64_t begin, uint64_t step)
 }
 
 __global__ void rebase_kernel(const RebaseDesc d) {
-  rebase_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
+  rebase_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x, d.n);
 }
 
 __global__ void clear_status_kernel(uint32_t* status) { *status = 0; }
@@ -769,8 +770,15 @@ __global__ void __launch_bounds__(256, 4) batch_dense_kernel(const BatchTables b
 __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   __shared__ uint64_t wsum[17];
   const uint32_t j = blockIdx.x;
-  if (j < b.n_totals) scan_totals_body(b.totals[j], wsum);
-  else if (j - b.n_totals < b.n_rebase) rebase_range(b.rebase[j - b.n_totals], threadIdx.x, blockDim.x);
+  if (j < b.n_totals) {
+    scan_totals_body(b.totals[j], wsum);
+  } else if (j - b.n_totals < b.rebase_tiles) {
+    // rebases in tiles of kRebaseTile entries, spread over work-groups
+    const uint32_t t = j - b.n_totals;
+    const uint32_t item = b.rebase_item[t];
+    const uint64_t begin = (t - b.rebase_prefix[item]) * (uint64_t)kRebaseTile;
+    rebase_range(b.rebase[item], begin + threadIdx.x, blockDim.x, begin + kRebaseTile - 1);
+  }
 }
 
 // Every gather tile of every jagged item, strided like the dense kernel.
@@ -827,8 +835,8 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (b.n_totals + b.n_rebase) {
-    hipLaunchKernelGGL(batch_misc_kernel, dim3(b.n_totals + b.n_rebase), dim3(1024), 0, s, b);
+  if (b.n_totals + b.rebase_tiles) {
+    hipLaunchKernelGGL(batch_misc_kernel, dim3(b.n_totals + b.rebase_tiles), dim3(1024), 0, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -168,7 +168,11 @@ struct BatchTables {
   uint32_t n_totals;
   uint32_t n_rebase;
   const RebaseDesc* rebase;
+  const uint64_t* rebase_prefix;    // first rebase tile of each rebase step
+  const uint32_t* rebase_item;      // rebase tile -> rebase step
+  uint32_t rebase_tiles;
 };
+constexpr uint32_t kRebaseTile = 8192;   // offsets entries per rebase work-group
 
 // ---- kernel launchers (kernels.hip) ----
 hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid,

@@ -28,7 +28,7 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-enum class EvState { QUEUED, RUNNING, DONE, RELEASED };
+enum class EvState { QUEUED, ADMITTED, RUNNING, DONE, RELEASED };
 
 struct ItemCopy {
   const rl_layout* src_layout;
@@ -93,8 +93,10 @@ uint64_t event_bytes(Event& e) {
   return total;
 }
 
-// Admit queued events in arrival order while they fit (caller holds mu).
-void admit(rl_server* s) {
+// Take queued events in arrival order while their results fit the pool and
+// a slot is free, placing their result buffers (caller holds mu).
+std::vector<Event*> admit(rl_server* s) {
+  std::vector<Event*> out;
   while (!s->queue.empty() && s->running < s->opts.max_in_flight) {
     Event& e = *s->events[s->queue.front()];
     std::vector<uint64_t> sizes;
@@ -114,22 +116,30 @@ void admit(rl_server* s) {
     s->queue.pop_front();
     e.stream = s->next_stream;
     s->next_stream = (s->next_stream + 1) % (uint32_t)s->streams.size();
-    hipStream_t st = s->streams[e.stream];
-    for (auto& it : e.items) {
-      rl_view sv{it.src_layout, it.src_cap, it.src_mcap.empty() ? nullptr : it.src_mcap.data(),
-                 it.src_bufs.data()};
-      rl_view dv{it.dst_layout, it.n, it.dst_mcap.empty() ? nullptr : it.dst_mcap.data(), it.dst_bufs.data()};
-      rl_xfer_opts o{RL_XFER_AUTO};
-      const rl_status r = rl_transfer(&sv, &dv, it.n, st, &o);
-      if (r != RL_OK && e.status == RL_OK) e.status = r;
-      std::vector<uint64_t> hb(layout_n_buffers(it.src_layout));
-      layout_buffer_bytes(it.src_layout, it.n, it.src_mcap.empty() ? nullptr : it.src_mcap.data(), hb.data());
-      for (auto b : hb) s->h2d_bytes += b;
-    }
-    if (hipEventRecord(e.done, st) != hipSuccess && e.status == RL_OK) e.status = RL_EHIP;
-    e.state = EvState::RUNNING;
+    e.state = EvState::ADMITTED;
     ++s->running;
+    out.push_back(&e);
   }
+  return out;
+}
+
+// Enqueue the transfers of admitted events (without the lock: an admitted
+// event is touched only by the scheduler thread until it is RUNNING).
+uint64_t launch(rl_server* s, Event& e) {
+  uint64_t h2d = 0;
+  hipStream_t st = s->streams[e.stream];
+  for (auto& it : e.items) {
+    rl_view sv{it.src_layout, it.src_cap, it.src_mcap.empty() ? nullptr : it.src_mcap.data(), it.src_bufs.data()};
+    rl_view dv{it.dst_layout, it.n, it.dst_mcap.empty() ? nullptr : it.dst_mcap.data(), it.dst_bufs.data()};
+    rl_xfer_opts o{RL_XFER_AUTO};
+    const rl_status r = rl_transfer(&sv, &dv, it.n, st, &o);
+    if (r != RL_OK && e.status == RL_OK) e.status = r;
+    std::vector<uint64_t> hb(layout_n_buffers(it.src_layout));
+    layout_buffer_bytes(it.src_layout, it.n, it.src_mcap.empty() ? nullptr : it.src_mcap.data(), hb.data());
+    for (auto b : hb) h2d += b;
+  }
+  if (hipEventRecord(e.done, st) != hipSuccess && e.status == RL_OK) e.status = RL_EHIP;
+  return h2d;
 }
 
 // Mark finished events (caller holds mu); true if any finished.
@@ -158,8 +168,17 @@ void scheduler_loop(rl_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
     const bool finished = reap(s);
-    admit(s);
+    std::vector<Event*> admitted = admit(s);
     if (finished) s->cv_done.notify_all();
+    if (!admitted.empty()) {
+      lk.unlock();
+      uint64_t h2d = 0;
+      for (Event* e : admitted) h2d += launch(s, *e);
+      lk.lock();
+      s->h2d_bytes += h2d;
+      for (Event* e : admitted) e->state = EvState::RUNNING;
+      continue;
+    }
     if (s->running == 0 && (s->queue.empty() || !finished))
       s->cv_work.wait_for(lk, std::chrono::microseconds(s->running ? 20 : 2000));
     else {

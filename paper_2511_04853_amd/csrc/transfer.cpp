@@ -7,8 +7,9 @@
 // the layout change are one pass with no staging.
 //
 // Staged mode: the host side's buffers are copied whole by the DMA engines
-// into a stream-ordered device allocation, then converted from there (or
-// converted into it, then copied out), all on the caller's stream.  Copies
+// into a device staging buffer kept per stream (reuse is ordered by the
+// stream), then converted from there (or converted into it, then copied
+// out), all on the caller's stream.  Copies
 // and conversions of different calls on different streams overlap.  (A
 // split into chunks on a second copy stream was measured slower: every
 // cross-stream event dependency between the DMA queue and the compute queue
@@ -16,6 +17,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 #include "plan.h"
@@ -24,6 +27,13 @@
 namespace rl {
 
 namespace {
+
+struct StageBuf {
+  uint8_t* ptr = nullptr;
+  uint64_t bytes = 0;
+};
+std::mutex g_stage_mu;
+std::map<std::pair<int, hipStream_t>, StageBuf> g_stage;   // held until the process ends
 
 bool is_host(rl_space s) { return s == RL_SPACE_HOST || s == RL_SPACE_HOST_PINNED; }
 
@@ -54,9 +64,30 @@ rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t
     at[b] = total;
     total += (bytes[b] + 255) & ~255ull;
   }
+  // one staging buffer per (device, stream), reused in stream order; the
+  // lock keeps the enqueue of one call from interleaving with another's
+  std::lock_guard<std::mutex> lk(g_stage_mu);
   uint8_t* stage = nullptr;
-  hipError_t e = hipMallocAsync((void**)&stage, std::max<uint64_t>(total, 256), stream);
-  if (e != hipSuccess) return fail(RL_ENOMEM, "staging %llu bytes: %s", (unsigned long long)total, hipGetErrorString(e));
+  hipError_t e;
+  {
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    StageBuf& sbuf = g_stage[{dev, stream}];
+    if (sbuf.bytes < total) {
+      if (sbuf.ptr) {
+        // earlier work on this stream may still read the old buffer
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        (void)hipFree(sbuf.ptr);
+        sbuf.ptr = nullptr;
+        sbuf.bytes = 0;
+      }
+      const uint64_t want = std::max<uint64_t>(total + total / 4, 1 << 20);
+      if ((e = hipMalloc(&sbuf.ptr, want)) != hipSuccess)
+        return fail(RL_ENOMEM, "staging %llu bytes: %s", (unsigned long long)want, hipGetErrorString(e));
+      sbuf.bytes = want;
+    }
+    stage = sbuf.ptr;
+  }
   std::vector<void*> sb(nb);
   for (uint32_t b = 0; b < nb; ++b) sb[b] = stage + at[b];
   rl_view staged{HL, hv.capacity, hv.member_capacity, sb.data()};
@@ -76,8 +107,6 @@ rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t
       if (bytes[b] && (e = hipMemcpyAsync(hv.buffers[b], sb[b], bytes[b], hipMemcpyDeviceToHost, stream)) != hipSuccess)
         st = hip_fail(e, "hipMemcpyAsync D2H");
   }
-  e = hipFreeAsync(stage, stream);
-  if (!st && e != hipSuccess) st = hip_fail(e, "hipFreeAsync");
   return st;
 }
 
