@@ -135,7 +135,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"librelayout.so is not built ({LIB_PATH}); "
-                               "run `python -m paper_2511_04853_amd.build`")
+                               "run `python paper_2511_04853_amd/build.py`")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -147,7 +147,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   const size_t o_gp = reserve(gprefix.size() * 8);
   const size_t o_tot = reserve(totals.size() * sizeof(ScanTotalsDesc));
   const size_t o_reb = reserve(rebase.size() * sizeof(RebaseDesc));
-  const size_t o_ditem = reserve(dprefix.back() * 4);
+  const size_t o_dmap = reserve(dprefix.back() * 8);
+  const size_t o_dcnt = reserve(dense.size() * 16);
   const size_t o_gitem = reserve(gprefix.back() * 4);
   const size_t o_rp = reserve(rprefix.size() * 8);
   const size_t o_ritem = reserve(rprefix.back() * 4);
@@ -159,9 +160,9 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   memcpy(host.data() + o_tot, totals.data(), totals.size() * sizeof(ScanTotalsDesc));
   memcpy(host.data() + o_reb, rebase.data(), rebase.size() * sizeof(RebaseDesc));
   {
-    uint32_t* di = (uint32_t*)(host.data() + o_ditem);
+    uint64_t* dm = (uint64_t*)(host.data() + o_dmap);
     for (size_t k = 0; k + 1 < dprefix.size(); ++k)
-      for (uint64_t t = dprefix[k]; t < dprefix[k + 1]; ++t) di[t] = (uint32_t)k;
+      for (uint64_t t = dprefix[k]; t < dprefix[k + 1]; ++t) dm[t] = ((uint64_t)k << 32) | (t - dprefix[k]);
     uint32_t* gi = (uint32_t*)(host.data() + o_gitem);
     for (size_t k = 0; k + 1 < gprefix.size(); ++k)
       for (uint64_t t = gprefix[k]; t < gprefix[k + 1]; ++t) gi[t] = (uint32_t)k;
@@ -178,7 +179,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   BatchTables& t = out->t;
   t.dense = (const DenseDesc*)(out->mem + o_dense);
   t.dense_prefix = (const uint64_t*)(out->mem + o_dp);
-  t.dense_item = (const uint32_t*)(out->mem + o_ditem);
+  t.dense_map = (const uint64_t*)(out->mem + o_dmap);
+  t.dense_counts = (uint64_t*)(out->mem + o_dcnt);
   t.gather_item = (const uint32_t*)(out->mem + o_gitem);
   t.n_dense = (uint32_t)dense.size();
   t.dense_tiles = (uint32_t)dprefix.back();

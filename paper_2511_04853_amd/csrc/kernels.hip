@@ -741,20 +741,68 @@ __global__ void clear_status_kernel(uint32_t* status) { *status = 0; }
 
 // ------------------------------------------------------------------ batches
 
+// Per dense step: the object count and source base (device-side counts of
+// member steps are read here once, before the dense pass).
+__global__ void batch_count_kernel(const BatchTables b) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < b.n_dense; k += gridDim.x * blockDim.x) {
+    uint64_t count, base;
+    dense_count(b.dense[k], &count, &base);
+    b.dense_counts[2 * k] = count;
+    b.dense_counts[2 * k + 1] = base;
+  }
+}
+
 // Every dense step of every item: the tiles of all items form one space;
 // work-group w takes tiles w, w + grid, ... (no shared counters: same-address
-// atomics from thousands of work-groups serialise in L2).  The item of a
-// tile comes from a host-built map.
+// atomics from thousands of work-groups serialise in L2).  A tile's map
+// entry is loaded two tiles ahead and its step's counts one tile ahead, so
+// handing out a tile never waits on a dependent load.
+// A vector-memory load: uniform addresses would otherwise become scalar
+// loads, whose completion the next LDS wait (same counter) would also wait
+// for; vector loads are waited for only where their values are used.
+__device__ __forceinline__ uint64_t vload(const uint64_t* p) {
+  return *reinterpret_cast<const volatile uint64_t*>(p);
+}
+
 struct BatchTiles {
   const BatchTables* b;
-  uint64_t t;
+  uint64_t t;              // tile handed out by the next call
+  uint64_t e1, e2;         // map entries of tiles t and t + grid
+  uint64_t c1, base1;      // counts of tile t's step
+  __device__ BatchTiles(const BatchTables* tb, uint64_t first) : b(tb), t(first), e1(0), e2(0), c1(0), base1(0) {
+    const uint64_t g = gridDim.x;
+    if (t < b->dense_tiles) {
+      e1 = vload(b->dense_map + t);
+      const uint32_t item = (uint32_t)(e1 >> 32);
+      c1 = vload(b->dense_counts + 2 * item);
+      base1 = vload(b->dense_counts + 2 * item + 1);
+    }
+    if (t + g < b->dense_tiles) e2 = vload(b->dense_map + t + g);
+  }
   __device__ TileJob operator()() {
+    const uint64_t g = gridDim.x;
     while (t < b->dense_tiles) {
-      const uint32_t item = __builtin_amdgcn_readfirstlane(b->dense_item[t]);
-      TileJob j{1, item, t - b->dense_prefix[item], 0, 0};
-      t += gridDim.x;
-      dense_count(b->dense[item], &j.count, &j.base);
-      if (j.tile * b->dense[item].tile < j.count) return j;   // else: beyond a device-side count
+      const uint32_t item = __builtin_amdgcn_readfirstlane((uint32_t)(e1 >> 32));
+      const uint32_t local = __builtin_amdgcn_readfirstlane((uint32_t)e1);
+      const uint64_t count = c1, base = base1;
+      // advance the two-stage prefetch
+      t += g;
+      if (t < b->dense_tiles) {
+        const uint32_t it2 = (uint32_t)(e2 >> 32);
+        c1 = vload(b->dense_counts + 2 * it2);
+        base1 = vload(b->dense_counts + 2 * it2 + 1);
+        e1 = e2;
+        if (t + g < b->dense_tiles) e2 = vload(b->dense_map + t + g);
+      }
+      const uint32_t tile = b->dense[item].tile;
+      if ((uint64_t)local * tile < count) {
+        TileJob j{1, item, local, 0, 0};
+        j.count = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(count >> 32)) << 32) |
+                  __builtin_amdgcn_readfirstlane((uint32_t)count);
+        j.base = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                 __builtin_amdgcn_readfirstlane((uint32_t)base);
+        return j;
+      }
     }
     return TileJob{0, 0, 0, 0, 0};
   }
@@ -762,7 +810,7 @@ struct BatchTiles {
 
 __global__ void __launch_bounds__(256, 4) batch_dense_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
-  dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw), BatchTiles{&b, blockIdx.x},
+  dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw), BatchTiles(&b, blockIdx.x),
                  [&](uint32_t item) -> const DenseDesc& { return b.dense[item]; });
 }
 
@@ -831,6 +879,9 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
   if (gather_threads == 0 || gather_threads > 1024 || gather_threads % 64) return hipErrorInvalidValue;
   if (b.dense_tiles) {
+    hipLaunchKernelGGL(batch_count_kernel, dim3((b.n_dense + 255) / 256), dim3(256), 0, s, b);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
     hipLaunchKernelGGL(batch_dense_kernel, dim3(grid), dim3(dense_threads), dense_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

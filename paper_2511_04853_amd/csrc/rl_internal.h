@@ -156,7 +156,8 @@ struct RebaseDesc {
 struct BatchTables {
   const DenseDesc* dense;
   const uint64_t* dense_prefix;     // first tile of each dense step
-  const uint32_t* dense_item;       // tile -> dense step
+  const uint64_t* dense_map;        // tile -> (dense step << 32 | tile within the step)
+  uint64_t* dense_counts;           // per dense step: (count, source base), set by the count pass
   uint32_t n_dense;
   uint32_t dense_tiles;
   const GatherDesc* gather;
