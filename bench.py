@@ -194,6 +194,8 @@ def main():
     }
 
     if not args.no_extras:
+        out["plain_round_trip"] = plain_round_trip(P, W, torch, stream)
+        out["jagged"] = jagged(P, W, torch, stream)
         out["serving"] = serving(P, W, torch, stream)
         out["batched"] = batched(P, W, torch, stream, tune_cache)
         out["sweep"] = sweep(P, W, torch, stream)
@@ -327,6 +329,78 @@ def batched(P, W, torch, stream, tune_cache):
     del keep, b
     torch.cuda.empty_cache()
     return res
+
+
+def _time(fn, stream, torch, reps=50, warm=5):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(reps):
+        fn(k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def plain_round_trip(P, W, torch, stream, sets=64):
+    """10,000 objects of 8 mixed scalars: AoS -> SoA -> AoS on the device
+    (two launches), rotating copies."""
+    S = P.Schema(W.PLAIN8)
+    aos, soa = P.Layout(S, "aos"), P.Layout(S, "soa")
+    n = 10_000
+    lib, sp = P.lib(), P.stream_ptr(stream)
+    A = [P.View(aos, n, [torch.randint(0, 256, (aos.buffer_bytes(n)[0],), dtype=torch.uint8, device="cuda")])
+         for _ in range(sets)]
+    B = [P.View(soa, n, [torch.empty(b, dtype=torch.uint8, device="cuda") for b in soa.buffer_bytes(n)])
+         for _ in range(sets)]
+    C = [P.View(aos, n, [torch.empty(aos.buffer_bytes(n)[0], dtype=torch.uint8, device="cuda")]) for _ in range(sets)]
+
+    def rt(k=0):
+        lib.rl_convert(A[k % sets].ref(), B[k % sets].ref(), n, sp)
+        lib.rl_convert(B[k % sets].ref(), C[k % sets].ref(), n, sp)
+
+    ms = _time(rt, stream, torch)
+    by = 2 * (aos.buffer_bytes(n)[0] + sum(soa.buffer_bytes(n)))
+    assert P.sync(stream) == 0
+    return {"objects": n, "us_per_round_trip": round(ms * 1e3, 2), "GBps": round(by / (ms * 1e-3) / 1e9, 1)}
+
+
+def jagged(P, W, torch, stream, sets=8):
+    """50,000 clusters with Poisson(40) (index, weight) members: AoS records
+    + shuffled-free pool -> SoA + offsets (scan + gather), and back."""
+    S = P.Schema(W.CLUSTER)
+    aos, soa = P.Layout(S, "aos"), P.Layout(S, "soa")
+    n = 50_000
+    lib, sp = P.lib(), P.stream_ptr(stream)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1002)
+    vals, back = [], []
+    for r in range(sets):
+        lens = torch.poisson(torch.full((n,), 40.0, device="cuda"), generator=g).to(torch.int64)
+        offs = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+        offs[1:] = torch.cumsum(lens, 0)
+        tot = int(offs[-1].item())
+        bufs = [torch.randint(0, 256, (4 * n,), dtype=torch.uint8, device="cuda", generator=g) for _ in range(6)]
+        bufs.append(offs.to(torch.int32).view(torch.uint8))
+        bufs += [torch.randint(0, 256, (4 * tot,), dtype=torch.uint8, device="cuda", generator=g) for _ in range(2)]
+        sv = P.View(soa, n, bufs, [tot])
+        av = P.View(aos, n, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in aos.buffer_bytes(n, [tot])],
+                    [tot])
+        P.convert(sv, av, n)
+        dv = P.View(soa, n, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in soa.buffer_bytes(n, [tot])],
+                    [tot])
+        vals.append((av, dv, tot))
+    assert P.sync(stream) == 0
+    fwd = _time(lambda k=0: lib.rl_convert(vals[k % sets][0].ref(), vals[k % sets][1].ref(), n, sp), stream, torch)
+    rev = _time(lambda k=0: lib.rl_convert(vals[k % sets][1].ref(), vals[k % sets][0].ref(), n, sp), stream, torch)
+    assert P.sync(stream) == 0
+    tot = int(np.mean([v[2] for v in vals]))
+    by = sum(aos.buffer_bytes(n, [tot])) + sum(soa.buffer_bytes(n, [tot]))
+    return {"objects": n, "members": tot, "bytes_each_way": by,
+            "forward_us": round(fwd * 1e3, 2), "forward_GBps": round(by / (fwd * 1e-3) / 1e9, 1),
+            "reverse_us": round(rev * 1e3, 2), "reverse_GBps": round(by / (rev * 1e-3) / 1e9, 1)}
 
 
 def serving(P, W, torch, stream, rates=(1000, 3000), n_events=3000, hold=512, pool_events=64):
