@@ -193,6 +193,7 @@ def main():
                              "graph_speedup": round(ms_loop / ms_per_step, 3)},
     }
 
+    out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"], n)
     if not args.no_extras:
         out["plain_round_trip"] = plain_round_trip(P, W, torch, stream)
         out["jagged"] = jagged(P, W, torch, stream)
@@ -329,6 +330,28 @@ def batched(P, W, torch, stream, tune_cache):
     del keep, b
     torch.cuda.empty_cache()
     return res
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "rl_internal.h", "plan.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2511_04853_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary, scaled by the same counters on
+    a plain copy of known size; None when the kernel source changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_batch_dense_kernel_cell190k_step.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel") != kernel or t.get("source_hash") != kernel_source_hash() or t.get("objects") != n:
+        return None
+    return int(t["hbm_bytes_per_launch"])
 
 
 def _time(fn, stream, torch, reps=50, warm=5):
