@@ -284,10 +284,13 @@ rl_status rl_batch_launch(rl_batch* batch, void* stream);
 rl_status rl_batch_launch_loop(rl_batch* batch, void* stream);
 rl_status rl_batch_item_width(const rl_batch* batch, uint32_t item,
                               uint32_t* block_width);
-/* Tile shape chosen for the batch: objects per tile, threads per block,
-   persistent blocks. */
+/* Shape chosen for the batch: objects per tile, threads per block,
+   persistent blocks, and whether rl_batch_launch replays the captured graph
+   (1) or launches the same kernels directly (0; the autotuner keeps
+   whichever it measured faster).  Any out pointer may be NULL. */
 rl_status rl_batch_shape(const rl_batch* batch, uint32_t* tile_objects,
-                         uint32_t* block_threads, uint32_t* grid_blocks);
+                         uint32_t* block_threads, uint32_t* grid_blocks,
+                         uint32_t* graph_replay);
 void rl_batch_destroy(rl_batch* batch);
 
 /* ------------------------------------------------------------------ serving */

@@ -116,7 +116,8 @@ SIGNATURES = {
     "rl_batch_launch": (ctypes.c_int, [_VP, _VP]),
     "rl_batch_launch_loop": (ctypes.c_int, [_VP, _VP]),
     "rl_batch_item_width": (ctypes.c_int, [_VP, ctypes.c_uint32, _P(ctypes.c_uint32)]),
-    "rl_batch_shape": (ctypes.c_int, [_VP, _P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
+    "rl_batch_shape": (ctypes.c_int, [_VP, _P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32),
+                                      _P(ctypes.c_uint32)]),
     "rl_batch_destroy": (None, [_VP]),
     "rl_server_create": (ctypes.c_int, [_P(rl_server_opts), _P(_VP)]),
     "rl_server_submit": (ctypes.c_int, [_VP, _P(rl_event), _P(ctypes.c_uint64)]),

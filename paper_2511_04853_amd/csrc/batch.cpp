@@ -47,6 +47,7 @@ struct Item {
 
 struct Config {
   uint32_t tile = 256, threads = 128, grid = 2048, width = 64;   // threads: dense work-groups
+  uint32_t direct = 0;   // 1: launch the batch kernels directly instead of replaying the graph
 };
 
 struct DeviceTables {
@@ -160,6 +161,12 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   memcpy(host.data() + o_tot, totals.data(), totals.size() * sizeof(ScanTotalsDesc));
   memcpy(host.data() + o_reb, rebase.data(), rebase.size() * sizeof(RebaseDesc));
   {
+    // host-known counts are written here; device-side ones by the count pass
+    uint64_t* dc = (uint64_t*)(host.data() + o_dcnt);
+    for (size_t k = 0; k < dense.size(); ++k) {
+      dc[2 * k] = dense[k].n;
+      dc[2 * k + 1] = 0;
+    }
     uint64_t* dm = (uint64_t*)(host.data() + o_dmap);
     for (size_t k = 0; k + 1 < dprefix.size(); ++k)
       for (uint64_t t = dprefix[k]; t < dprefix[k + 1]; ++t) dm[t] = ((uint64_t)k << 32) | (t - dprefix[k]);
@@ -181,6 +188,7 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   t.dense_prefix = (const uint64_t*)(out->mem + o_dp);
   t.dense_map = (const uint64_t*)(out->mem + o_dmap);
   t.dense_counts = (uint64_t*)(out->mem + o_dcnt);
+  t.device_counts = std::any_of(dense.begin(), dense.end(), [](const DenseDesc& d) { return d.count_offsets != nullptr; });
   t.gather_item = (const uint32_t*)(out->mem + o_gitem);
   t.n_dense = (uint32_t)dense.size();
   t.dense_tiles = (uint32_t)dprefix.back();
@@ -254,6 +262,7 @@ bool cache_lookup(const std::string& path, const std::string& sig, Config* c) {
     };
     Config t;
     if (num("tile", &t.tile) && num("threads", &t.threads) && num("grid", &t.grid) && num("width", &t.width)) {
+      num("direct", &t.direct);
       *c = t;
       return true;
     }
@@ -274,8 +283,9 @@ void cache_store(const std::string& path, const std::string& sig, const Config& 
     }
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"us\":%.2f}",
-           sig.c_str(), c.tile, c.threads, c.grid, c.width, us);
+  snprintf(buf, sizeof buf,
+           "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"direct\":%u, \"us\":%.2f}",
+           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, us);
   keep.push_back(buf);
   std::ofstream o(path + ".tmp");
   o << "{\n";
@@ -316,9 +326,10 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
   const bool any_auto = std::any_of(b->items.begin(), b->items.end(), [](const Item& i) { return i.auto_width(); });
   double best_us = 1e30;
   Config bc;
-  for (uint32_t tile : {128u, 256u, 512u, 1024u})
+  for (uint32_t tile : {64u, 128u, 256u, 512u, 1024u})
     for (uint32_t threads : {64u, 128u, 256u})
-      for (uint32_t grid : {1024u, 2048u, 4096u}) {
+      for (uint32_t grid : {1024u, 2048u, 4096u, 8192u}) {
+        if (threads > 2 * tile) continue;   // at least half the threads hold an object
         Config c{tile, threads, grid, 64};
         double us;
         rl_status st = time_config(b, c, s, &us);
@@ -336,6 +347,29 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
     }
   *best = bc;
   b->tuned_us = best_us;
+  return RL_OK;
+}
+
+// Time graph replay against direct launches of the chosen configuration.
+rl_status choose_launch(rl_batch* b, hipStream_t s) {
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float ms[2] = {0, 0};
+  const int reps = 10;
+  for (int mode = 0; mode < 2; ++mode) {
+    for (int k = 0; k < reps + 2; ++k) {
+      if (k == 2) (void)hipEventRecord(e0, s);
+      hipError_t e = mode == 0 ? hipGraphLaunch(b->exec, s) : launch_batch(b->dev.t, std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads), 256, b->cfg.grid, b->dev.dense_lds, b->dev.gather_lds, s);
+      if (e != hipSuccess) return hip_fail(e, "tuning launch");
+    }
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(&ms[mode], e0, e1);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->cfg.direct = ms[1] < ms[0] * 0.97 ? 1 : 0;
   return RL_OK;
 }
 
@@ -395,7 +429,6 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
     rl_status st = autotune(b, s, &c);
     if (st) return st;
     have = true;
-    if (!b->cache.empty()) cache_store(b->cache, sig, c, b->tuned_us);
   } else if (!b->cache.empty()) {
     have = cache_lookup(b->cache, sig, &c);
   }
@@ -419,6 +452,10 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
     return hip_fail(e, "hipGraphInstantiate");
+  if (b->autotune) {
+    if ((st = choose_launch(b, s))) return st;
+    if (!b->cache.empty()) cache_store(b->cache, sig, b->cfg, b->tuned_us);
+  }
   b->finalized = true;
   return RL_OK;
 }
@@ -426,6 +463,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
 extern "C" rl_status rl_batch_launch(rl_batch* b, void* stream) {
   if (!b || !b->finalized) return fail(RL_EINVAL, "batch not finalized");
   if (!b->dev.t.dense_tiles && !b->dev.t.gather_tiles && !b->dev.t.n_totals && !b->dev.t.rebase_tiles) return RL_OK;
+  if (b->cfg.direct) return launch_tables(b->dev, b->cfg, (hipStream_t)stream);
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
   return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphLaunch");
 }
@@ -448,11 +486,13 @@ extern "C" rl_status rl_batch_item_width(const rl_batch* b, uint32_t item, uint3
   return RL_OK;
 }
 
-extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t* threads, uint32_t* grid) {
+extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t* threads, uint32_t* grid,
+                                    uint32_t* graph_replay) {
   if (!b) return fail(RL_EINVAL, "batch is NULL");
   if (tile) *tile = b->cfg.tile;
   if (threads) *threads = b->cfg.threads;
   if (grid) *grid = b->cfg.grid;
+  if (graph_replay) *graph_replay = b->cfg.direct ? 0 : 1;
   return RL_OK;
 }
 

@@ -879,9 +879,11 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
   if (gather_threads == 0 || gather_threads > 1024 || gather_threads % 64) return hipErrorInvalidValue;
   if (b.dense_tiles) {
-    hipLaunchKernelGGL(batch_count_kernel, dim3((b.n_dense + 255) / 256), dim3(256), 0, s, b);
-    hipError_t e0 = hipGetLastError();
-    if (e0 != hipSuccess) return e0;
+    if (b.device_counts) {
+      hipLaunchKernelGGL(batch_count_kernel, dim3((b.n_dense + 255) / 256), dim3(256), 0, s, b);
+      hipError_t e0 = hipGetLastError();
+      if (e0 != hipSuccess) return e0;
+    }
     hipLaunchKernelGGL(batch_dense_kernel, dim3(grid), dim3(dense_threads), dense_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

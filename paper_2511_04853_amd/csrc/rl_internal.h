@@ -157,7 +157,8 @@ struct BatchTables {
   const DenseDesc* dense;
   const uint64_t* dense_prefix;     // first tile of each dense step
   const uint64_t* dense_map;        // tile -> (dense step << 32 | tile within the step)
-  uint64_t* dense_counts;           // per dense step: (count, source base), set by the count pass
+  uint64_t* dense_counts;           // per dense step: (count, source base)
+  uint32_t device_counts;           // 1: some dense step's count is read on the device (count pass needed)
   uint32_t n_dense;
   uint32_t dense_tiles;
   const GatherDesc* gather;

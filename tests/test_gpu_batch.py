@@ -55,7 +55,7 @@ class Batch:
 
     def shape(self):
         a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
-        P.check(P.lib().rl_batch_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "shape")
+        P.check(P.lib().rl_batch_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), None), "shape")
         return a.value, b.value, c.value
 
     def __del__(self):
