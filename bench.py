@@ -336,7 +336,7 @@ def batched(P, W, torch, stream, tune_cache):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "rl_internal.h", "plan.cpp"):
+    for f in ("kernels.hip", "rl_internal.h", "plan.cpp", "batch.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2511_04853_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
