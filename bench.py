@@ -569,9 +569,23 @@ def sweep(P, W, torch, stream):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        res[str(n)] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
-                       "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del pairs
+        # a plain device copy moving the same bytes (half read, half written)
+        a = [torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda") for _ in range(2)]
+        b = [torch.empty_like(a[0]) for _ in range(2)]
+        for k in range(3):
+            b[k % 2].copy_(a[k % 2])
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for k in range(reps):
+            b[k % 2].copy_(a[k % 2])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_copy = e0.elapsed_time(e1) / reps
+        del a, b
+        res[str(n)] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                       "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "plain_copy_GBps": round(nbytes / (ms_copy * 1e-3) / 1e9, 1)}
     assert P.sync(stream) == 0
     return res
 

@@ -98,6 +98,7 @@ rl_status plan_all(rl_batch* b, const Config& c) {
   PlanShape shape;
   shape.tile = c.tile;
   shape.threads = c.threads;
+  shape.direct = shape_from_env().direct;
   for (auto& it : b->items) {
     Plan p;
     if (it.n) {
@@ -435,6 +436,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   (void)have;
   if (const char* v = getenv("RL_BATCH_TILE")) c.tile = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_GRID")) c.grid = (uint32_t)strtoul(v, nullptr, 10);
+  if (const char* v = getenv("RL_BATCH_THREADS")) c.threads = (uint32_t)strtoul(v, nullptr, 10);
   if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 128;
   if (c.grid < 1) c.grid = 2048;
   b->cfg = c;

@@ -444,6 +444,7 @@ PlanShape shape_from_env() {
     if (t >= 64 && t <= 1024 && t % 64 == 0) s.threads = t;
   }
   if (const char* v = getenv("RL_GRID_BLOCKS")) s.grid = (uint32_t)strtoul(v, nullptr, 10);
+  if (const char* v = getenv("RL_DST_DIRECT")) s.direct = atoi(v) ? -1 : 0;
   return s;
 }
 }  // namespace rl

@@ -25,16 +25,25 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ helpers
 
+// Global memory.  Pointers that kernels read out of descriptors held in
+// memory (batches) are generic to the compiler, which would then use flat
+// instructions; those also count on the LDS counter, so every later LDS
+// wait would wait for them too.  Kernels reach global memory (device or
+// pinned host) through address space 1.
+#define RL_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ RL_G T* gp(T* p) { return (RL_G T*)p; }
+
 __device__ __forceinline__ uint64_t load_off(const uint8_t* p, uint32_t type, uint64_t i) {
-  if (type == RL_U64) return reinterpret_cast<const uint64_t*>(p)[i];
-  if (type == RL_I32) return (uint64_t)(int64_t)reinterpret_cast<const int32_t*>(p)[i];
-  return reinterpret_cast<const uint32_t*>(p)[i];
+  if (type == RL_U64) return gp(reinterpret_cast<const uint64_t*>(p))[i];
+  if (type == RL_I32) return (uint64_t)(int64_t)gp(reinterpret_cast<const int32_t*>(p))[i];
+  return gp(reinterpret_cast<const uint32_t*>(p))[i];
 }
 
 __device__ __forceinline__ void store_off(uint8_t* p, uint32_t type, uint64_t i, uint64_t v) {
-  if (type == RL_U64) reinterpret_cast<uint64_t*>(p)[i] = v;
-  else if (type == RL_I32) reinterpret_cast<int32_t*>(p)[i] = (int32_t)v;
-  else reinterpret_cast<uint32_t*>(p)[i] = (uint32_t)v;
+  if (type == RL_U64) gp(reinterpret_cast<uint64_t*>(p))[i] = v;
+  else if (type == RL_I32) gp(reinterpret_cast<int32_t*>(p))[i] = (int32_t)v;
+  else gp(reinterpret_cast<uint32_t*>(p))[i] = (uint32_t)v;
 }
 
 __device__ __forceinline__ uint64_t off_limit(uint32_t type) {
@@ -44,7 +53,7 @@ __device__ __forceinline__ uint64_t off_limit(uint32_t type) {
 }
 
 __device__ __forceinline__ void flag(uint32_t* status, uint32_t f) {
-  if (status) atomicOr(status, f);
+  if (status) __hip_atomic_fetch_or(gp(status), f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Copy `bytes` from global memory to LDS (the LDS side is 16-byte aligned).
@@ -53,18 +62,18 @@ __device__ __forceinline__ void g2l(uint8_t* lds, const uint8_t* g, uint32_t byt
                                     uint32_t tid, uint32_t nt) {
   if ((reinterpret_cast<uintptr_t>(g) & 15) == 0) {
     const uint32_t nv = bytes >> 4;
-    const v4u* gv = reinterpret_cast<const v4u*>(g);
+    const RL_G v4u* gv = gp(reinterpret_cast<const v4u*>(g));
     v4u* lv = reinterpret_cast<v4u*>(lds);
     for (uint32_t v = tid; v < nv; v += nt) lv[v] = gv[v];
-    for (uint32_t b = (nv << 4) + tid; b < bytes; b += nt) lds[b] = g[b];
+    for (uint32_t b = (nv << 4) + tid; b < bytes; b += nt) lds[b] = gp(g)[b];
   } else if ((reinterpret_cast<uintptr_t>(g) & 3) == 0) {
     const uint32_t nw = bytes >> 2;
-    const uint32_t* gw = reinterpret_cast<const uint32_t*>(g);
+    const RL_G uint32_t* gw = gp(reinterpret_cast<const uint32_t*>(g));
     uint32_t* lw = reinterpret_cast<uint32_t*>(lds);
     for (uint32_t v = tid; v < nw; v += nt) lw[v] = gw[v];
-    for (uint32_t b = (nw << 2) + tid; b < bytes; b += nt) lds[b] = g[b];
+    for (uint32_t b = (nw << 2) + tid; b < bytes; b += nt) lds[b] = gp(g)[b];
   } else {
-    for (uint32_t b = tid; b < bytes; b += nt) lds[b] = g[b];
+    for (uint32_t b = tid; b < bytes; b += nt) lds[b] = gp(g)[b];
   }
 }
 
@@ -73,18 +82,18 @@ __device__ __forceinline__ void l2g(uint8_t* g, const uint8_t* lds, uint32_t byt
                                     uint32_t tid, uint32_t nt) {
   if ((reinterpret_cast<uintptr_t>(g) & 15) == 0) {
     const uint32_t nv = bytes >> 4;
-    v4u* gv = reinterpret_cast<v4u*>(g);
+    RL_G v4u* gv = gp(reinterpret_cast<v4u*>(g));
     const v4u* lv = reinterpret_cast<const v4u*>(lds);
     for (uint32_t v = tid; v < nv; v += nt) gv[v] = lv[v];
-    for (uint32_t b = (nv << 4) + tid; b < bytes; b += nt) g[b] = lds[b];
+    for (uint32_t b = (nv << 4) + tid; b < bytes; b += nt) gp(g)[b] = lds[b];
   } else if ((reinterpret_cast<uintptr_t>(g) & 3) == 0) {
     const uint32_t nw = bytes >> 2;
-    uint32_t* gw = reinterpret_cast<uint32_t*>(g);
+    RL_G uint32_t* gw = gp(reinterpret_cast<uint32_t*>(g));
     const uint32_t* lw = reinterpret_cast<const uint32_t*>(lds);
     for (uint32_t v = tid; v < nw; v += nt) gw[v] = lw[v];
-    for (uint32_t b = (nw << 2) + tid; b < bytes; b += nt) g[b] = lds[b];
+    for (uint32_t b = (nw << 2) + tid; b < bytes; b += nt) gp(g)[b] = lds[b];
   } else {
-    for (uint32_t b = tid; b < bytes; b += nt) g[b] = lds[b];
+    for (uint32_t b = tid; b < bytes; b += nt) gp(g)[b] = lds[b];
   }
 }
 
@@ -197,7 +206,7 @@ __device__ __forceinline__ void load_side(const DenseDesc& d, uint8_t* img, uint
       const uint32_t c = d.unit_src[unit_of(d, v)];
       const LeafDesc& L = d.leaf[c];
       const uint32_t first_v = L.src_off >> 4;   // tile * prefix / 16
-      const v4u* col = reinterpret_cast<const v4u*>(L.src_col + idx0 * L.src_size);
+      const RL_G v4u* col = gp(reinterpret_cast<const v4u*>(L.src_col + idx0 * L.src_size));
       lv[v] = col[v - first_v];
     }
   } else {
@@ -225,7 +234,7 @@ __device__ __forceinline__ void store_side(const DenseDesc& d, const uint8_t* im
       const uint32_t c = d.unit_dst[unit_of(d, v)];
       const LeafDesc& L = d.leaf[c];
       const uint32_t first_v = L.dst_off >> 4;
-      v4u* col = reinterpret_cast<v4u*>(L.dst_col + idx0 * L.dst_size);
+      RL_G v4u* col = gp(reinterpret_cast<v4u*>(L.dst_col + idx0 * L.dst_size));
       col[v - first_v] = lv[v];
     }
   } else {
@@ -241,7 +250,7 @@ __device__ __forceinline__ DenseLds carve(uint8_t* smem, const DenseDesc& d) {
   DenseLds m;
   m.src = smem;
   m.dst = smem + round16(d.src.image_bytes);
-  m.wsum = reinterpret_cast<uint64_t*>(m.dst + round16(d.dst.image_bytes));
+  m.wsum = reinterpret_cast<uint64_t*>(m.dst + (d.dst_direct ? 0u : round16(d.dst.image_bytes)));
   return m;
 }
 
@@ -265,13 +274,11 @@ __device__ __forceinline__ void dense_count(const DenseDesc& d, uint64_t* count,
 
 // ------------------------------------------------------------------ tile pipeline
 //
-// A work-group converts a sequence of tiles.  While tile k is moved inside
-// LDS and written out, the 16-byte source vectors of tile k+1 are already
-// in flight into registers: global loads and stores of neighbouring tiles
-// overlap, and the in-order vector-memory counter never makes a tile's
-// loads wait behind the previous tile's stores.
-
-constexpr uint32_t kPrefetch = 4;   // 16-byte vectors per thread held in registers
+// A work-group converts a sequence of tiles.  Source images travel from
+// global memory straight into LDS (global_load_lds, 16 bytes per lane, no
+// registers in between): every vector of a tile is in flight at once, and
+// the next tile's vectors are issued as soon as the current source image
+// has been consumed, so they overlap the current tile's stores.
 
 struct TileJob {
   uint32_t valid;       // 0: no more work
@@ -279,48 +286,53 @@ struct TileJob {
   uint64_t tile, count, base;
 };
 
-// A full tile of a source whose runs are 16-byte aligned, small enough for
-// the register buffer, can be fetched ahead.
-__device__ __forceinline__ bool fetchable(const DenseDesc& d, const TileJob& j) {
-  if (!d.prefetch || j.base != 0) return false;
-  if ((j.tile + 1) * d.tile > j.count) return false;
-  return (d.src.image_bytes >> 4) <= kPrefetch * blockDim.x;
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Copy a 16-byte aligned global run of `bytes` into LDS (16-byte aligned)
+// by DMA; the last bytes % 16 go through registers.  Wave w takes the
+// 64-vector chunks w, w + waves, ...; lane l of a chunk lands at chunk
+// base + 16 l, the instruction's fixed LDS layout.
+__device__ __forceinline__ void dma_run(uint8_t* lds, const uint8_t* g, uint32_t bytes) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t nv = bytes >> 4;
+  for (uint32_t vb = wave * 64; vb < nv; vb += nw * 64) {
+    const uint32_t v = vb + lane;
+    if (v < nv) __builtin_amdgcn_global_load_lds(g + (size_t)v * 16, (lds_ptr)(lds + (size_t)vb * 16), 16, 0, 0);
+  }
+  for (uint32_t b = (nv << 4) + threadIdx.x; b < bytes; b += blockDim.x) lds[b] = gp(g)[b];
 }
 
-__device__ __forceinline__ void fetch(const DenseDesc& d, const TileJob& j, v4u* r) {
-  const uint32_t nv = d.src.image_bytes >> 4;
-  const uint64_t idx0 = j.tile * d.tile;
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  if (d.src.kind != KIND_SOA) {
-    // AoS records / AoSoA blocks: one contiguous run
-    const uint64_t per = d.src.kind == KIND_AOS ? d.src.stride : d.src.obj_bytes;
-    const v4u* run = reinterpret_cast<const v4u*>(d.src.base + idx0 * per);
-#pragma unroll
-    for (uint32_t k = 0; k < kPrefetch; ++k) {
-      const uint32_t v = tid + k * nt;
-      if (v < nv) r[k] = run[v];
-    }
-    return;
-  }
-  // SoA image: column c's run starts at vector tile * prefix(c) / 16
-#pragma unroll
-  for (uint32_t k = 0; k < kPrefetch; ++k) {
-    const uint32_t v = tid + k * nt;
-    if (v < nv) {
-      const LeafDesc& L = d.leaf[d.unit_src[unit_of(d, v)]];
-      r[k] = reinterpret_cast<const v4u*>(L.src_col + idx0 * L.src_size)[v - (L.src_off >> 4)];
-    }
-  }
-}
+// Wait for this wave's DMA into LDS (and every earlier vector-memory
+// operation: the counter retires in order).  A barrier must follow before
+// other waves read what this wave loaded.
+__device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
 
-__device__ __forceinline__ void commit(const DenseDesc& d, const v4u* r, uint8_t* img) {
-  const uint32_t nv = d.src.image_bytes >> 4;
-  v4u* lv = reinterpret_cast<v4u*>(img);
-#pragma unroll
-  for (uint32_t k = 0; k < kPrefetch; ++k) {
-    const uint32_t v = threadIdx.x + k * blockDim.x;
-    if (v < nv) lv[v] = r[k];
+// Start bringing a tile's source image into LDS: by DMA when every run is
+// 16-byte aligned, else through registers (complete on return).
+__device__ __forceinline__ void issue_source(const DenseDesc& d, uint8_t* img, const TileJob& j) {
+  const uint64_t i0 = j.tile * d.tile;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, j.count - i0);
+  const uint64_t idx0 = i0 + j.base;
+  const SideDesc& s = d.src;
+  if (d.dma) {
+    if (s.kind == KIND_AOS || s.kind == KIND_AOSOA) {
+      const uint8_t* run = s.base + idx0 * (s.kind == KIND_AOS ? s.stride : s.obj_bytes);
+      if (((uintptr_t)run & 15) == 0) {
+        dma_run(img, run, s.kind == KIND_AOS ? cnt * s.stride : image_used(s, cnt));
+        return;
+      }
+    } else if ((idx0 & 15) == 0) {
+      // SoA (16-byte aligned columns): every column run starts 16-byte
+      // aligned when the first index is a multiple of 16
+      for (uint32_t c = 0; c < d.n_leaves; ++c) {
+        const LeafDesc& L = d.leaf[c];
+        if (L.op == OP_PTR || L.op == OP_LEN) continue;
+        dma_run(img + L.src_off, L.src_col + idx0 * L.src_size, cnt * L.src_size);
+      }
+      return;
+    }
   }
+  load_side(d, img, idx0, cnt, cnt == d.tile && j.base == 0);
 }
 
 // Fused local scan of jagged counts held in the source records: writes the
@@ -379,7 +391,14 @@ __device__ __forceinline__ uint32_t at(uint32_t a, uint32_t off, uint32_t b) {
   return K == KIND_AOS ? a + off : a + off + b * SIZE;
 }
 
-template <uint32_t SK, uint32_t DK, bool FULL>
+// Store a value into an LDS image, or (GLOBAL) into global memory.
+template <bool GLOBAL, class T>
+__device__ __forceinline__ void put(uint8_t* p, T v) {
+  if (GLOBAL) *gp(reinterpret_cast<T*>(p)) = v;
+  else *reinterpret_cast<T*>(p) = v;
+}
+
+template <uint32_t SK, uint32_t DK, bool FULL, bool DIRECT>
 __device__ __forceinline__ void transform_pass(const DenseDesc& d, const DenseLds& m, uint64_t i0,
                                                uint32_t o0, uint32_t cnt) {
   constexpr uint32_t P = kObjPerThread;
@@ -394,17 +413,23 @@ __device__ __forceinline__ void transform_pass(const DenseDesc& d, const DenseLd
     obj_terms<DK>(d.dst, o, da[k], db[k]);
   }
   const uint8_t* S = m.src;
-  uint8_t* D = m.dst;
+  // Destination: the LDS image, or (DIRECT) the tile's place in global
+  // memory -- AoSoA: the tile's first block, whose runs sit at the image
+  // offsets; SoA: each column at the tile's first object.
+  uint8_t* const Dtile = DIRECT ? d.dst.base + i0 * d.dst.obj_bytes : m.dst;
 #define RL_MOVE(ST, DT, SS, DS, EXPR)                                                  \
   _Pragma("unroll") for (uint32_t k = 0; k < P; ++k) {                                 \
     if (FULL || ok[k]) {                                                               \
       const ST x = *reinterpret_cast<const ST*>(S + at<SK, SS>(sa[k], so, sb[k]));     \
-      *reinterpret_cast<DT*>(D + at<DK, DS>(da[k], dof, db[k])) = (EXPR);              \
+      put<DIRECT, DT>(D + at<DK, DS>(da[k], dof, db[k]), (EXPR));                      \
     }                                                                                  \
   }
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
     const LeafDesc& L = d.leaf[c];
-    const uint32_t so = L.src_off, dof = L.dst_off;
+    const uint32_t so = L.src_off;
+    const bool col = DIRECT && DK == KIND_SOA;
+    uint8_t* const D = col ? L.dst_col + i0 * L.dst_size : Dtile;
+    const uint32_t dof = col ? 0u : L.dst_off;
     switch (L.code) {
       case CODE_COPY1: RL_MOVE(uint8_t, uint8_t, 1, 1, x); break;
       case CODE_COPY2: RL_MOVE(uint16_t, uint16_t, 2, 2, x); break;
@@ -455,27 +480,68 @@ __device__ __forceinline__ void transform_slow(const DenseDesc& d, uint8_t* src_
   }
 }
 
-template <uint32_t SK, uint32_t DK>
+// Unused slots of the last AoSoA block of a partial tile, written as zeros
+// in global memory (the image path zero-fills its LDS image instead).
+__device__ __forceinline__ void zero_tail_direct(const DenseDesc& d, uint64_t i0, uint32_t cnt) {
+  const SideDesc& s = d.dst;
+  const uint32_t end = s.width == 1 ? cnt : __umulhi(cnt + s.width - 1, s.width_magic) * s.width;
+  uint8_t* const Dtile = s.base + i0 * s.obj_bytes;
+  for (uint32_t c = 0; c < d.n_leaves; ++c) {
+    const LeafDesc& L = d.leaf[c];
+    for (uint32_t o = cnt + threadIdx.x; o < end; o += blockDim.x) {
+      uint32_t a, b;
+      obj_terms<KIND_AOSOA>(s, o, a, b);
+      uint8_t* p = Dtile + a + L.dst_off + b * L.dst_size;
+      switch (L.dst_size) {
+        case 1: put<true, uint8_t>(p, 0); break;
+        case 2: put<true, uint16_t>(p, 0); break;
+        case 4: put<true, uint32_t>(p, 0); break;
+        default: put<true, uint64_t>(p, 0); break;
+      }
+    }
+  }
+}
+
+template <uint32_t SK, uint32_t DK, bool DIRECT>
 __device__ __forceinline__ void transform_kinds(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
   const uint32_t per_pass = kObjPerThread * blockDim.x;
   for (uint32_t o0 = 0; o0 < cnt; o0 += per_pass) {
-    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true>(d, m, i0, o0, cnt);
-    else transform_pass<SK, DK, false>(d, m, i0, o0, cnt);
+    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true, DIRECT>(d, m, i0, o0, cnt);
+    else transform_pass<SK, DK, false, DIRECT>(d, m, i0, o0, cnt);
+  }
+  if (DIRECT && DK == KIND_AOSOA) zero_tail_direct(d, i0, cnt);
+}
+
+// Direct destinations (SoA columns, AoSoA blocks): each leaf of a wave's
+// consecutive objects is one contiguous run in global memory, so the
+// stores coalesce without a destination image.
+__device__ __forceinline__ void transform_direct(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+  switch (d.src.kind * 3 + d.dst.kind) {
+    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true>(d, m, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true>(d, m, i0, cnt); break;
+    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true>(d, m, i0, cnt); break;
   }
 }
 
 __device__ __forceinline__ void transform_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+  if (d.dst_direct) {
+    transform_direct(d, m, i0, cnt);
+    return;
+  }
   if (d.slow_leaves) transform_slow(d, m.src, m.dst, i0, cnt);
   switch (d.src.kind * 3 + d.dst.kind) {
-    case KIND_AOS * 3 + KIND_AOS: transform_kinds<KIND_AOS, KIND_AOS>(d, m, i0, cnt); break;
-    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA>(d, m, i0, cnt); break;
-    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA>(d, m, i0, cnt); break;
-    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS>(d, m, i0, cnt); break;
-    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA>(d, m, i0, cnt); break;
-    default: transform_kinds<KIND_AOSOA, KIND_AOSOA>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_AOS: transform_kinds<KIND_AOS, KIND_AOS, false>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, false>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, false>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, false>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, false>(d, m, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, false>(d, m, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, false>(d, m, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, false>(d, m, i0, cnt); break;
+    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, false>(d, m, i0, cnt); break;
   }
 }
 
@@ -485,47 +551,39 @@ __device__ __forceinline__ void transform_tile(const DenseDesc& d, const DenseLd
 // into a loop-carried value, or the compiler copies it to scratch.)
 template <class Next, class Desc>
 __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc desc) {
-  v4u regs[kPrefetch];
   TileJob cur = next();
-  bool in_regs = false;
-  if (cur.valid && fetchable(desc(cur.item), cur)) {
-    fetch(desc(cur.item), cur, regs);
-    in_regs = true;
-  }
+  if (cur.valid) issue_source(desc(cur.item), smem, cur);
   while (cur.valid) {
     const DenseDesc& d = desc(cur.item);
     const DenseLds m = carve(smem, d);
     const uint64_t i0 = cur.tile * d.tile;
     const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, cur.count - i0);
     const bool full = cnt == d.tile;
-    // 1. source image
-    if (in_regs) commit(d, regs, m.src);
-    else load_side(d, m.src, i0 + cur.base, cnt, full && cur.base == 0);
+    // 1. source image in LDS
+    dma_wait();
     __syncthreads();
-    // 2. start fetching the next tile
-    const TileJob nxt = next();
-    in_regs = false;
-    if (nxt.valid && fetchable(desc(nxt.item), nxt)) {
-      fetch(desc(nxt.item), nxt, regs);
-      in_regs = true;
-    }
-    // 3. zero-filled destination where padding or unused block slots exist
-    if (d.zero_dst || (!full && d.dst.kind == KIND_AOSOA)) {
+    // 2. zero-filled destination image where padding or unused block slots exist
+    if (!d.dst_direct && (d.zero_dst || (!full && d.dst.kind == KIND_AOSOA))) {
       v4u* z = reinterpret_cast<v4u*>(m.dst);
       const uint32_t nv = d.dst.image_bytes >> 4;
       for (uint32_t v = threadIdx.x; v < nv; v += blockDim.x) z[v] = v4u{0u, 0u, 0u, 0u};
       __syncthreads();
     }
-    // 4. counts scan and value moves inside LDS
+    // 3. counts scan and value moves (into the destination image, or
+    //    straight to global memory)
     if (d.scan_offsets) scan_tile(d, m, i0, cnt);
     transform_tile(d, m, i0, cnt);
     __syncthreads();
-    // 5. destination image out
-    store_side(d, m.dst, i0, cnt, full);
-    // A next tile of another descriptor carves LDS differently: its source
-    // image may cover this tile's destination image, which other threads
-    // may still be reading.
-    if (nxt.valid && nxt.item != cur.item) __syncthreads();
+    // 4. this tile's destination image out, then the next tile's source
+    //    image in (its DMA is issued after the image reads, and overlaps
+    //    the stores).  A next tile of another descriptor carves LDS
+    //    differently: its source image may cover this destination image.
+    const TileJob nxt = next();
+    if (!d.dst_direct) {
+      store_side(d, m.dst, i0, cnt, full);
+      if (nxt.valid && nxt.item != cur.item) __syncthreads();
+    }
+    if (nxt.valid) issue_source(desc(nxt.item), smem, nxt);
     cur = nxt;
   }
 }
@@ -533,7 +591,7 @@ __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc de
 // Tiles blockIdx.x, blockIdx.x + gridDim.x, ... of one conversion.
 struct StridedTiles {
   uint64_t t, ntiles, count, base;
-  __device__ TileJob operator()() {
+  __device__ __forceinline__ TileJob operator()() {
     TileJob j{0, 0, 0, count, base};
     if (t < ntiles) {
       j.valid = 1;
@@ -544,7 +602,7 @@ struct StridedTiles {
   }
 };
 
-__global__ void __launch_bounds__(256, 4) dense_kernel(const DenseDesc d) {
+__global__ void __launch_bounds__(256, 8) dense_kernel(const DenseDesc d) {
   extern __shared__ uint4 smem_raw[];
   uint64_t count, base;
   dense_count(d, &count, &base);
@@ -623,13 +681,13 @@ __device__ __forceinline__ void gather_members(const GatherDesc& d, const uint64
 #pragma unroll
       for (uint32_t k = 0; k < 4; ++k)
 #pragma unroll
-        for (uint32_t q = 0; q < NW; ++q) w[k][q] = ok[k] ? reinterpret_cast<const uint32_t*>(src[k])[q] : 0u;
+        for (uint32_t q = 0; q < NW; ++q) w[k][q] = ok[k] ? gp(reinterpret_cast<const uint32_t*>(src[k]))[q] : 0u;
       const bool full = ok[0] && ok[1] && ok[2] && ok[3];
 #pragma unroll
       for (uint32_t q = 0; q < NW; ++q) {
-        uint32_t* col = reinterpret_cast<uint32_t*>(d.mcol[q]);
+        RL_G uint32_t* col = gp(reinterpret_cast<uint32_t*>(d.mcol[q]));
         if (full) {
-          *reinterpret_cast<v4u*>(col + base) = v4u{w[0][q], w[1][q], w[2][q], w[3][q]};
+          *reinterpret_cast<RL_G v4u*>(col + base) = v4u{w[0][q], w[1][q], w[2][q], w[3][q]};
         } else {
 #pragma unroll
           for (uint32_t k = 0; k < 4; ++k)
@@ -644,10 +702,10 @@ __device__ __forceinline__ void gather_members(const GatherDesc& d, const uint64
           const uint8_t* s = src[k] + d.moff[q];
           uint8_t* dst = d.mcol[q] + (base + k) * d.msize[q];
           switch (d.msize[q]) {
-            case 1: *dst = *s; break;
-            case 2: *reinterpret_cast<uint16_t*>(dst) = *reinterpret_cast<const uint16_t*>(s); break;
-            case 4: *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(s); break;
-            default: *reinterpret_cast<uint64_t*>(dst) = *reinterpret_cast<const uint64_t*>(s); break;
+            case 1: put<true, uint8_t>(dst, *gp(s)); break;
+            case 2: put<true, uint16_t>(dst, *gp(reinterpret_cast<const uint16_t*>(s))); break;
+            case 4: put<true, uint32_t>(dst, *gp(reinterpret_cast<const uint32_t*>(s))); break;
+            default: put<true, uint64_t>(dst, *gp(reinterpret_cast<const uint64_t*>(s))); break;
           }
         }
       }
@@ -680,8 +738,8 @@ __device__ void gather_tile(const GatherDesc& d, uint64_t t, uint8_t* smem) {
     if (d.n_members == 0) return;  // uniform: offsets only
     for (uint32_t o = tid; o < cnt; o += nt) {
       const uint8_t* rec = d.records + (i0 + o) * d.rec_stride;
-      const uint64_t p = *reinterpret_cast<const uint64_t*>(rec + d.ptr_off);
-      const uint64_t len = *reinterpret_cast<const uint32_t*>(rec + d.len_off);
+      const uint64_t p = *gp(reinterpret_cast<const uint64_t*>(rec + d.ptr_off));
+      const uint64_t len = *gp(reinterpret_cast<const uint32_t*>(rec + d.len_off));
       const bool good = (p & (uint64_t)(d.malign - 1)) == 0 && p <= pool_end &&
                         len <= (pool_end - p) / d.mstride;
       ptrs[o] = p;
@@ -737,7 +795,7 @@ __global__ void rebase_kernel(const RebaseDesc d) {
   rebase_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x, d.n);
 }
 
-__global__ void clear_status_kernel(uint32_t* status) { *status = 0; }
+__global__ void clear_status_kernel(uint32_t* status) { *gp(status) = 0; }
 
 // ------------------------------------------------------------------ batches
 
@@ -747,8 +805,8 @@ __global__ void batch_count_kernel(const BatchTables b) {
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < b.n_dense; k += gridDim.x * blockDim.x) {
     uint64_t count, base;
     dense_count(b.dense[k], &count, &base);
-    b.dense_counts[2 * k] = count;
-    b.dense_counts[2 * k + 1] = base;
+    gp(b.dense_counts)[2 * k] = count;
+    gp(b.dense_counts)[2 * k + 1] = base;
   }
 }
 
@@ -761,7 +819,7 @@ __global__ void batch_count_kernel(const BatchTables b) {
 // loads, whose completion the next LDS wait (same counter) would also wait
 // for; vector loads are waited for only where their values are used.
 __device__ __forceinline__ uint64_t vload(const uint64_t* p) {
-  return *reinterpret_cast<const volatile uint64_t*>(p);
+  return *reinterpret_cast<const volatile RL_G uint64_t*>(gp(p));
 }
 
 struct BatchTiles {
@@ -769,7 +827,7 @@ struct BatchTiles {
   uint64_t t;              // tile handed out by the next call
   uint64_t e1, e2;         // map entries of tiles t and t + grid
   uint64_t c1, base1;      // counts of tile t's step
-  __device__ BatchTiles(const BatchTables* tb, uint64_t first) : b(tb), t(first), e1(0), e2(0), c1(0), base1(0) {
+  __device__ __forceinline__ BatchTiles(const BatchTables* tb, uint64_t first) : b(tb), t(first), e1(0), e2(0), c1(0), base1(0) {
     const uint64_t g = gridDim.x;
     if (t < b->dense_tiles) {
       e1 = vload(b->dense_map + t);
@@ -779,7 +837,7 @@ struct BatchTiles {
     }
     if (t + g < b->dense_tiles) e2 = vload(b->dense_map + t + g);
   }
-  __device__ TileJob operator()() {
+  __device__ __forceinline__ TileJob operator()() {
     const uint64_t g = gridDim.x;
     while (t < b->dense_tiles) {
       const uint32_t item = __builtin_amdgcn_readfirstlane((uint32_t)(e1 >> 32));
@@ -842,7 +900,8 @@ __global__ void __launch_bounds__(1024) batch_gather_kernel(const BatchTables b)
 // ------------------------------------------------------------------ launchers
 
 uint32_t dense_lds_bytes(const DenseDesc& d) {
-  return round16(d.src.image_bytes) + round16(d.dst.image_bytes) + round16(17 * sizeof(uint64_t));
+  return round16(d.src.image_bytes) + (d.dst_direct ? 0u : round16(d.dst.image_bytes)) +
+         round16(17 * sizeof(uint64_t));
 }
 
 uint64_t dense_tiles(const DenseDesc& d) { return (d.n + d.tile - 1) / d.tile; }

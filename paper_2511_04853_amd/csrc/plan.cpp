@@ -159,10 +159,11 @@ rl_status build_dense(const SideSpec& s, const SideSpec& d, uint64_t n, uint32_t
     for (uint32_t c = 0; c < nl; ++c)
       for (uint32_t b = 0; b < k.leaf[c].src_size; ++b) k.unit_src[u++] = (uint8_t)c;
   }
-  // full source tiles can be fetched ahead as 16-byte vectors when every
-  // run starts 16-byte aligned (tiles hold a multiple of 16 objects)
-  if (s.kind == KIND_SOA) k.prefetch = k.units_src;
-  else k.prefetch = ((uintptr_t)s.base & 15) == 0 && sb + (s.kind == KIND_AOS ? s.stride : 0) > 0;
+  // source runs go to LDS by DMA when 16-byte aligned: SoA columns must
+  // be (tiles hold a multiple of 16 objects); record and block runs are
+  // checked per tile
+  if (s.kind == KIND_SOA) k.dma = cols_aligned16(s) ? 1 : 0;
+  else k.dma = 1;
   if (d.kind == KIND_SOA && db <= (uint32_t)kMaxUnits && db > 0 && cols_aligned16(d)) {
     k.units_dst = 1;
     uint32_t u = 0;
@@ -183,10 +184,24 @@ static uint32_t dense_threads(uint32_t tile, const PlanShape& shape) {
   return std::min<uint32_t>(kDenseMaxThreads, std::max<uint32_t>(64, t));
 }
 
+// Whether a dense step can store its values straight into the destination:
+// SoA columns or AoSoA blocks in device memory, every leaf on a fast path
+// (aligned, no record pointers), no padding to zero.
+static bool direct_ok(const DenseDesc& d) {
+  const SideDesc& o = d.dst;
+  if (o.kind == KIND_AOS || d.slow_leaves || d.zero_dst) return false;
+  if (o.kind == KIND_AOSOA) return ((uintptr_t)o.base & 15) == 0;
+  for (uint32_t c = 0; c < d.n_leaves; ++c)
+    if ((uintptr_t)d.leaf[c].dst_col % d.leaf[c].dst_size) return false;
+  return true;
+}
+
 static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& shape) {
   Step st;
   st.kind = Step::DENSE;
   st.dense = d;
+  st.dense.dst_direct = shape.direct != 0 && direct_ok(d) ? 1u : 0u;
+  if (shape.dma == 0) st.dense.dma = 0;
   st.threads = dense_threads(d.tile, shape);
   st.grid = default_grid(dense_tiles(d), shape);
   plan->steps.push_back(st);

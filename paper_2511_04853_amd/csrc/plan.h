@@ -11,6 +11,9 @@ struct PlanShape {
   uint32_t tile = 0;      // objects per tile (0: default)
   uint32_t threads = 0;   // threads per work-group (0: a quarter of the tile)
   uint32_t grid = 0;      // work-groups of dense steps (0: one per tile, capped)
+  int direct = -1;        // destination values stored straight to global memory:
+                          // -1 where the destination allows it, 0 never
+  int dma = -1;           // source runs DMA'd into LDS: -1 where aligned, 0 never
 };
 
 struct Step {

@@ -96,9 +96,11 @@ struct DenseDesc {
   uint32_t* status;        // device status word
   uint32_t units_src;      // 1: SoA source, full tiles walk the image by unit_src
   uint32_t units_dst;      // 1: SoA destination, full tiles walk the image by unit_dst
-  uint32_t prefetch;       // 1: full source tiles are 16-byte aligned runs (fetched ahead)
+  uint32_t dma;            // 1: source runs may be DMA'd into LDS (AoS / AoSoA: when a
+                           //    tile's run is 16-byte aligned; SoA: 16-byte aligned columns)
   uint32_t slow_leaves;    // 1: some leaf needs the generic (byte-wise / offsets) path
-  uint32_t pad1;
+  uint32_t dst_direct;     // 1: values go straight from the source image to global memory
+                           //    (SoA / AoSoA destination, no destination image in LDS)
   uint32_t vt_magic;       // ceil(2^32 / (tile / 16)): SoA image vector -> byte unit
   uint64_t src_capacity;   // with count_offsets: source member capacity (count <= it - base)
   LeafDesc leaf[kMaxLeaves];

@@ -154,7 +154,12 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
     }
     rl_view hv2{HL, hv.capacity, hv.member_capacity, alias.data()};
     Plan plan;
-    st = h2d ? make_plan(hv2, *dst, n, PlanShape{}, &plan) : make_plan(*src, hv2, n, PlanShape{}, &plan);
+    // kernels write host memory only in whole 16-byte vectors of an image,
+    // and read it through registers
+    PlanShape to_host, from_host;
+    to_host.direct = 0;
+    from_host.dma = 0;
+    st = h2d ? make_plan(hv2, *dst, n, from_host, &plan) : make_plan(*src, hv2, n, to_host, &plan);
     if (st) return st;
     return enqueue_plan(plan, stream);
   }
