@@ -12,9 +12,13 @@ HBM.
 Value: algorithmic bytes (source footprint read + destination footprint
 written, per conversion) per second of the timed region.
 
-The four conversions of a step run as one graph launch of the batch engine
-(persistent kernels over a device table; shape autotuned once, cached); the
-same conversions as a per-conversion launch loop are timed beside it.
+The four conversions of a step run as one launch of the batch engine
+(persistent kernels over a device table; tile shape, work-group count and
+graph replay vs direct launch autotuned once, cached); the same
+conversions as a per-conversion launch loop are timed beside it.  The
+timed region is K steps back to back between two events; a second pass
+over the same K steps with an event pair around every launch gives the
+mean launch duration used for the roofline.
 
 Extra legs, outside the timed region: 512 heterogeneous collections in one
 graph launch against the launch loop, a sweep at larger object counts, the
@@ -123,21 +127,30 @@ def main():
         run(k)
     assert P.sync(stream) == 0, P.rl_last_error()
 
+    # timed region: K steps back to back, bracketed by two events
     K = args.steps
-    evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(K)]
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
     for k in range(K):
-        evs[k][0].record(stream)
         run(k)
-        evs[k][1].record(stream)
     t1.record(stream)
     torch.cuda.synchronize()
     ms_total = t0.elapsed_time(t1)
     assert P.sync(stream) == 0, P.rl_last_error()
     ms_per_step = ms_total / K
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    # the same K steps again with an event pair around every launch (on the
+    # launch stream): the mean duration of one launch of the dense kernel
+    evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(K)]
+    torch.cuda.synchronize()
+    for k in range(K):
+        evs[k][0].record(stream)
+        run(k)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    assert P.sync(stream) == 0, P.rl_last_error()
     launch_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     mean_launch_ms = float(launch_ms.mean())
     achieved = step_bytes / (mean_launch_ms * 1e-3) / 1e9

@@ -46,7 +46,8 @@ struct Item {
 };
 
 struct Config {
-  uint32_t tile = 256, threads = 128, grid = 2048, width = 64;   // threads: dense work-groups
+  uint32_t tile = 256, threads = 128, width = 64;   // threads: dense work-groups
+  uint32_t grid = 0;     // dense work-groups; 0: as many as fit on the device at once
   uint32_t direct = 0;   // 1: launch the batch kernels directly instead of replaying the graph
 };
 
@@ -329,9 +330,13 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
   Config bc;
   for (uint32_t tile : {64u, 128u, 256u, 512u, 1024u})
     for (uint32_t threads : {64u, 128u, 256u})
-      for (uint32_t grid : {1024u, 2048u, 4096u, 8192u}) {
+      for (uint32_t grid : {0u, 1024u, 2048u, 4096u, 8192u}) {   // 0: as many as fit at once
         if (threads > 2 * tile) continue;   // at least half the threads hold an object
-        Config c{tile, threads, grid, 64};
+        Config c;
+        c.tile = tile;
+        c.threads = threads;
+        c.grid = grid;
+        c.width = 64;
         double us;
         rl_status st = time_config(b, c, s, &us);
         if (st) return st;
@@ -438,7 +443,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (const char* v = getenv("RL_BATCH_GRID")) c.grid = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_THREADS")) c.threads = (uint32_t)strtoul(v, nullptr, 10);
   if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 128;
-  if (c.grid < 1) c.grid = 2048;
+
   b->cfg = c;
   rl_status st = resolve_widths(b, c.width);
   if (!st) st = plan_all(b, c);
@@ -493,7 +498,9 @@ extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t*
   if (!b) return fail(RL_EINVAL, "batch is NULL");
   if (tile) *tile = b->cfg.tile;
   if (threads) *threads = b->cfg.threads;
-  if (grid) *grid = b->cfg.grid;
+  if (grid) *grid = b->cfg.grid ? b->cfg.grid
+                                 : batch_resident_blocks(std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads),
+                                                         b->dev.dense_lds);
   if (graph_replay) *graph_replay = b->cfg.direct ? 0 : 1;
   return RL_OK;
 }

@@ -17,6 +17,11 @@
 // members from the member pool.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "rl_internal.h"
 
 namespace rl {
@@ -33,6 +38,17 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 #define RL_G __attribute__((address_space(1)))
 template <class T>
 __device__ __forceinline__ RL_G T* gp(T* p) { return (RL_G T*)p; }
+
+// Descriptor tables of batches: written by the host before a launch and
+// never by kernels, so they are read as constant memory (address space 4),
+// through scalar loads.  Read through a generic pointer they would be
+// vector loads, each of which the in-order vector-memory counter makes
+// wait behind every store issued before it.
+#define RL_C __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const RL_C T& cdesc(const T* table, uint64_t i) {
+  return ((const RL_C T*)table)[i];
+}
 
 __device__ __forceinline__ uint64_t load_off(const uint8_t* p, uint32_t type, uint64_t i) {
   if (type == RL_U64) return gp(reinterpret_cast<const uint64_t*>(p))[i];
@@ -99,7 +115,8 @@ __device__ __forceinline__ void l2g(uint8_t* g, const uint8_t* lds, uint32_t byt
 
 // Bytes of a side's image that hold `cnt` objects (runs are contiguous for
 // AoS and AoSoA; for SoA this is only used for zeroing).
-__device__ __forceinline__ uint32_t image_used(const SideDesc& s, uint32_t cnt) {
+template <class SD>
+__device__ __forceinline__ uint32_t image_used(const SD& s, uint32_t cnt) {
   if (s.kind == KIND_AOS) return cnt * s.stride;
   if (s.kind == KIND_AOSOA) {
     const uint32_t nblk = s.width == 1 ? cnt : __umulhi(cnt + s.width - 1, s.width_magic);
@@ -113,7 +130,8 @@ __device__ __forceinline__ void copy_bytes(uint8_t* d, const uint8_t* s, uint32_
 }
 
 // Move one value inside LDS.
-__device__ __forceinline__ void move_value(uint8_t* dst, const uint8_t* src, const LeafDesc& L) {
+template <class LD>
+__device__ __forceinline__ void move_value(uint8_t* dst, const uint8_t* src, const LD& L) {
   if (L.op == OP_COPY) {
     if (L.byte_wise) { copy_bytes(dst, src, L.src_size); return; }
     switch (L.src_size) {
@@ -181,15 +199,17 @@ __host__ __device__ __forceinline__ uint32_t round16(uint32_t x) { return (x + 1
 
 // Byte unit of object size that SoA image vector v belongs to
 // (v / (tile / 16), by multiplier).
-__device__ __forceinline__ uint32_t unit_of(const DenseDesc& d, uint32_t v) {
+template <class DD>
+__device__ __forceinline__ uint32_t unit_of(const DD& d, uint32_t v) {
   return d.tile == 16 ? v : __umulhi(v, d.vt_magic);
 }
 
 // Load one side's tile into its LDS image.  `idx0` is the index of the
 // tile's first object on that side.
-__device__ __forceinline__ void load_side(const DenseDesc& d, uint8_t* img, uint64_t idx0, uint32_t cnt,
+template <class DD>
+__device__ __forceinline__ void load_side(const DD& d, uint8_t* img, uint64_t idx0, uint32_t cnt,
                           bool full) {
-  const SideDesc& s = d.src;
+  const auto& s = d.src;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   if (s.kind == KIND_AOS) {
     g2l(img, s.base + idx0 * s.stride, cnt * s.stride, tid, nt);
@@ -204,23 +224,24 @@ __device__ __forceinline__ void load_side(const DenseDesc& d, uint8_t* img, uint
     v4u* lv = reinterpret_cast<v4u*>(img);
     for (uint32_t v = tid; v < nv; v += nt) {
       const uint32_t c = d.unit_src[unit_of(d, v)];
-      const LeafDesc& L = d.leaf[c];
+      const auto& L = d.leaf[c];
       const uint32_t first_v = L.src_off >> 4;   // tile * prefix / 16
       const RL_G v4u* col = gp(reinterpret_cast<const v4u*>(L.src_col + idx0 * L.src_size));
       lv[v] = col[v - first_v];
     }
   } else {
     for (uint32_t c = 0; c < d.n_leaves; ++c) {
-      const LeafDesc& L = d.leaf[c];
+      const auto& L = d.leaf[c];
       if (L.op == OP_PTR || L.op == OP_LEN) continue;  // not in SoA images
       g2l(img + L.src_off, L.src_col + idx0 * L.src_size, cnt * L.src_size, tid, nt);
     }
   }
 }
 
-__device__ __forceinline__ void store_side(const DenseDesc& d, const uint8_t* img, uint64_t idx0, uint32_t cnt,
+template <class DD>
+__device__ __forceinline__ void store_side(const DD& d, const uint8_t* img, uint64_t idx0, uint32_t cnt,
                            bool full) {
-  const SideDesc& s = d.dst;
+  const auto& s = d.dst;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   if (s.kind == KIND_AOS) {
     l2g(s.base + idx0 * s.stride, img, cnt * s.stride, tid, nt);
@@ -232,21 +253,22 @@ __device__ __forceinline__ void store_side(const DenseDesc& d, const uint8_t* im
     const v4u* lv = reinterpret_cast<const v4u*>(img);
     for (uint32_t v = tid; v < nv; v += nt) {
       const uint32_t c = d.unit_dst[unit_of(d, v)];
-      const LeafDesc& L = d.leaf[c];
+      const auto& L = d.leaf[c];
       const uint32_t first_v = L.dst_off >> 4;
       RL_G v4u* col = gp(reinterpret_cast<v4u*>(L.dst_col + idx0 * L.dst_size));
       col[v - first_v] = lv[v];
     }
   } else {
     for (uint32_t c = 0; c < d.n_leaves; ++c) {
-      const LeafDesc& L = d.leaf[c];
+      const auto& L = d.leaf[c];
       if (L.op == OP_PTR || L.op == OP_LEN) continue;  // not in SoA images
       l2g(L.dst_col + idx0 * L.dst_size, img + L.dst_off, cnt * L.dst_size, tid, nt);
     }
   }
 }
 
-__device__ __forceinline__ DenseLds carve(uint8_t* smem, const DenseDesc& d) {
+template <class DD>
+__device__ __forceinline__ DenseLds carve(uint8_t* smem, const DD& d) {
   DenseLds m;
   m.src = smem;
   m.dst = smem + round16(d.src.image_bytes);
@@ -256,7 +278,8 @@ __device__ __forceinline__ DenseLds carve(uint8_t* smem, const DenseDesc& d) {
 
 // Count and source base of a conversion: host-given, or read on the device
 // from an offsets column (member columns of a jagged group).
-__device__ __forceinline__ void dense_count(const DenseDesc& d, uint64_t* count, uint64_t* base) {
+template <class DD>
+__device__ __forceinline__ void dense_count(const DD& d, uint64_t* count, uint64_t* base) {
   if (d.count_offsets) {
     const uint64_t b = load_off(d.count_offsets, d.count_off_type, 0);
     const uint64_t e = load_off(d.count_offsets, d.count_off_type, d.count_index);
@@ -286,18 +309,29 @@ struct TileJob {
   uint64_t tile, count, base;
 };
 
-typedef __attribute__((address_space(3))) void* lds_ptr;
+typedef __attribute__((address_space(3))) uint8_t* lds_ptr;
+
+// One 16-byte DMA per lane from global memory into LDS: lane l of the wave
+// lands at LDS byte lds_base + 16 l (lds_base wave-uniform).  Issued as
+// inline assembly: the compiler, which cannot tell which LDS bytes the DMA
+// writes, would otherwise wait for every outstanding vector-memory
+// operation (stores included) before each later LDS read.  Kernels wait
+// for the DMA themselves (dma_wait, then a barrier) before reading.
+__device__ __forceinline__ void dma16(const uint8_t* g, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :: "v"(g), "s"(lds_base) : "memory", "m0");
+}
 
 // Copy a 16-byte aligned global run of `bytes` into LDS (16-byte aligned)
 // by DMA; the last bytes % 16 go through registers.  Wave w takes the
-// 64-vector chunks w, w + waves, ...; lane l of a chunk lands at chunk
-// base + 16 l, the instruction's fixed LDS layout.
+// 64-vector chunks w, w + waves, ...
 __device__ __forceinline__ void dma_run(uint8_t* lds, const uint8_t* g, uint32_t bytes) {
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const uint32_t nv = bytes >> 4;
   for (uint32_t vb = wave * 64; vb < nv; vb += nw * 64) {
     const uint32_t v = vb + lane;
-    if (v < nv) __builtin_amdgcn_global_load_lds(g + (size_t)v * 16, (lds_ptr)(lds + (size_t)vb * 16), 16, 0, 0);
+    const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr)(lds + (size_t)vb * 16));
+    if (v < nv) dma16(g + (size_t)v * 16, base);
   }
   for (uint32_t b = (nv << 4) + threadIdx.x; b < bytes; b += blockDim.x) lds[b] = gp(g)[b];
 }
@@ -309,11 +343,12 @@ __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70);
 
 // Start bringing a tile's source image into LDS: by DMA when every run is
 // 16-byte aligned, else through registers (complete on return).
-__device__ __forceinline__ void issue_source(const DenseDesc& d, uint8_t* img, const TileJob& j) {
+template <class DD>
+__device__ __forceinline__ void issue_source(const DD& d, uint8_t* img, const TileJob& j) {
   const uint64_t i0 = j.tile * d.tile;
   const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, j.count - i0);
   const uint64_t idx0 = i0 + j.base;
-  const SideDesc& s = d.src;
+  const auto& s = d.src;
   if (d.dma) {
     if (s.kind == KIND_AOS || s.kind == KIND_AOSOA) {
       const uint8_t* run = s.base + idx0 * (s.kind == KIND_AOS ? s.stride : s.obj_bytes);
@@ -325,7 +360,7 @@ __device__ __forceinline__ void issue_source(const DenseDesc& d, uint8_t* img, c
       // SoA (16-byte aligned columns): every column run starts 16-byte
       // aligned when the first index is a multiple of 16
       for (uint32_t c = 0; c < d.n_leaves; ++c) {
-        const LeafDesc& L = d.leaf[c];
+        const auto& L = d.leaf[c];
         if (L.op == OP_PTR || L.op == OP_LEN) continue;
         dma_run(img + L.src_off, L.src_col + idx0 * L.src_size, cnt * L.src_size);
       }
@@ -338,7 +373,8 @@ __device__ __forceinline__ void issue_source(const DenseDesc& d, uint8_t* img, c
 // Fused local scan of jagged counts held in the source records: writes the
 // tile's exclusive offsets (entry i0 holds the tile total until the totals
 // pass replaces it with the tile's prefix).
-__device__ __forceinline__ void scan_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+template <class DD>
+__device__ __forceinline__ void scan_tile(const DD& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t per = (d.tile + nt - 1) / nt;
   const uint32_t o0 = tid * per;
@@ -370,9 +406,38 @@ __device__ __forceinline__ void scan_tile(const DenseDesc& d, const DenseLds& m,
 
 constexpr uint32_t kObjPerThread = 2;
 
+// A wave's copy of the fast-path fields of a descriptor's leaves: lane c
+// holds leaf c (a schema has at most one wavefront of leaves).  Loaded with
+// vector loads when a tile of another descriptor is issued, so the tile's
+// DMA wait covers them; the transform reads them with v_readlane and makes
+// no memory access per leaf.
+struct LeafLanes {
+  uint32_t src_off, dst_off, code, col_lo, col_hi;
+  uint32_t item;   // descriptor the lanes hold
+};
+
+template <class DD>
+__device__ __forceinline__ void load_lanes(const DD& d, uint32_t item, LeafLanes& t) {
+  const uint32_t lane = threadIdx.x & 63;
+  if (lane < d.n_leaves) {
+    const auto& L = d.leaf[lane];
+    t.src_off = L.src_off;
+    t.dst_off = L.dst_off;
+    t.code = L.code;
+    const uint64_t col = reinterpret_cast<uint64_t>(L.dst_col);
+    t.col_lo = (uint32_t)col;
+    t.col_hi = (uint32_t)(col >> 32);
+  }
+  t.item = item;
+}
+
+__device__ __forceinline__ uint32_t lane_of(uint32_t v, uint32_t c) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)c);
+}
+
 // Object-dependent address terms of one side: addr = a + off + b * size.
-template <uint32_t K>
-__device__ __forceinline__ void obj_terms(const SideDesc& s, uint32_t o, uint32_t& a, uint32_t& b) {
+template <uint32_t K, class SD>
+__device__ __forceinline__ void obj_terms(const SD& s, uint32_t o, uint32_t& a, uint32_t& b) {
   if (K == KIND_AOS) {
     a = o * s.stride;
     b = 0;
@@ -398,8 +463,8 @@ __device__ __forceinline__ void put(uint8_t* p, T v) {
   else *reinterpret_cast<T*>(p) = v;
 }
 
-template <uint32_t SK, uint32_t DK, bool FULL, bool DIRECT>
-__device__ __forceinline__ void transform_pass(const DenseDesc& d, const DenseLds& m, uint64_t i0,
+template <uint32_t SK, uint32_t DK, bool FULL, bool DIRECT, class DD>
+__device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
                                                uint32_t o0, uint32_t cnt) {
   constexpr uint32_t P = kObjPerThread;
   const uint32_t nt = blockDim.x;
@@ -421,16 +486,17 @@ __device__ __forceinline__ void transform_pass(const DenseDesc& d, const DenseLd
   _Pragma("unroll") for (uint32_t k = 0; k < P; ++k) {                                 \
     if (FULL || ok[k]) {                                                               \
       const ST x = *reinterpret_cast<const ST*>(S + at<SK, SS>(sa[k], so, sb[k]));     \
-      put<DIRECT, DT>(D + at<DK, DS>(da[k], dof, db[k]), (EXPR));                      \
+      put<DIRECT, DT>((col ? colp + i0 * DS : Dtile) + at<DK, DS>(da[k], dof, db[k]), (EXPR)); \
     }                                                                                  \
   }
-  for (uint32_t c = 0; c < d.n_leaves; ++c) {
-    const LeafDesc& L = d.leaf[c];
-    const uint32_t so = L.src_off;
+  const uint32_t nl = d.n_leaves;
+  for (uint32_t c = 0; c < nl; ++c) {
+    const uint32_t so = lane_of(lt.src_off, c);
     const bool col = DIRECT && DK == KIND_SOA;
-    uint8_t* const D = col ? L.dst_col + i0 * L.dst_size : Dtile;
-    const uint32_t dof = col ? 0u : L.dst_off;
-    switch (L.code) {
+    uint8_t* const colp = col ? reinterpret_cast<uint8_t*>(((uint64_t)lane_of(lt.col_hi, c) << 32) | lane_of(lt.col_lo, c))
+                              : nullptr;
+    const uint32_t dof = col ? 0u : lane_of(lt.dst_off, c);
+    switch (lane_of(lt.code, c)) {
       case CODE_COPY1: RL_MOVE(uint8_t, uint8_t, 1, 1, x); break;
       case CODE_COPY2: RL_MOVE(uint16_t, uint16_t, 2, 2, x); break;
       case CODE_COPY4: RL_MOVE(uint32_t, uint32_t, 4, 4, x); break;
@@ -445,10 +511,11 @@ __device__ __forceinline__ void transform_pass(const DenseDesc& d, const DenseLd
 
 // Leaves at misaligned image addresses and destination record (pointer,
 // count) pairs: one object per thread, generic address arithmetic.
-__device__ __forceinline__ void transform_slow(const DenseDesc& d, uint8_t* src_img, uint8_t* dst_img,
+template <class DD>
+__device__ __forceinline__ void transform_slow(const DD& d, uint8_t* src_img, uint8_t* dst_img,
                                             uint64_t i0, uint32_t cnt) {
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
-    const LeafDesc& L = d.leaf[c];
+    const auto& L = d.leaf[c];
     if (L.code < CODE_BYTES) continue;
     for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) {
       uint32_t sa, sb, da, db;
@@ -482,12 +549,13 @@ __device__ __forceinline__ void transform_slow(const DenseDesc& d, uint8_t* src_
 
 // Unused slots of the last AoSoA block of a partial tile, written as zeros
 // in global memory (the image path zero-fills its LDS image instead).
-__device__ __forceinline__ void zero_tail_direct(const DenseDesc& d, uint64_t i0, uint32_t cnt) {
-  const SideDesc& s = d.dst;
+template <class DD>
+__device__ __forceinline__ void zero_tail_direct(const DD& d, uint64_t i0, uint32_t cnt) {
+  const auto& s = d.dst;
   const uint32_t end = s.width == 1 ? cnt : __umulhi(cnt + s.width - 1, s.width_magic) * s.width;
   uint8_t* const Dtile = s.base + i0 * s.obj_bytes;
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
-    const LeafDesc& L = d.leaf[c];
+    const auto& L = d.leaf[c];
     for (uint32_t o = cnt + threadIdx.x; o < end; o += blockDim.x) {
       uint32_t a, b;
       obj_terms<KIND_AOSOA>(s, o, a, b);
@@ -502,12 +570,13 @@ __device__ __forceinline__ void zero_tail_direct(const DenseDesc& d, uint64_t i0
   }
 }
 
-template <uint32_t SK, uint32_t DK, bool DIRECT>
-__device__ __forceinline__ void transform_kinds(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+template <uint32_t SK, uint32_t DK, bool DIRECT, class DD>
+__device__ __forceinline__ void transform_kinds(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
+                                                uint32_t cnt) {
   const uint32_t per_pass = kObjPerThread * blockDim.x;
   for (uint32_t o0 = 0; o0 < cnt; o0 += per_pass) {
-    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true, DIRECT>(d, m, i0, o0, cnt);
-    else transform_pass<SK, DK, false, DIRECT>(d, m, i0, o0, cnt);
+    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true, DIRECT>(d, m, lt, i0, o0, cnt);
+    else transform_pass<SK, DK, false, DIRECT>(d, m, lt, i0, o0, cnt);
   }
   if (DIRECT && DK == KIND_AOSOA) zero_tail_direct(d, i0, cnt);
 }
@@ -515,33 +584,37 @@ __device__ __forceinline__ void transform_kinds(const DenseDesc& d, const DenseL
 // Direct destinations (SoA columns, AoSoA blocks): each leaf of a wave's
 // consecutive objects is one contiguous run in global memory, so the
 // stores coalesce without a destination image.
-__device__ __forceinline__ void transform_direct(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+template <class DD>
+__device__ __forceinline__ void transform_direct(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
+                                                 uint32_t cnt) {
   switch (d.src.kind * 3 + d.dst.kind) {
-    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true>(d, m, i0, cnt); break;
-    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true>(d, m, i0, cnt); break;
-    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true>(d, m, i0, cnt); break;
-    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true>(d, m, lt, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true>(d, m, lt, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true>(d, m, lt, i0, cnt); break;
+    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
   }
 }
 
-__device__ __forceinline__ void transform_tile(const DenseDesc& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+template <class DD>
+__device__ __forceinline__ void transform_tile(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
+                                               uint32_t cnt) {
   if (d.dst_direct) {
-    transform_direct(d, m, i0, cnt);
+    transform_direct(d, m, lt, i0, cnt);
     return;
   }
   if (d.slow_leaves) transform_slow(d, m.src, m.dst, i0, cnt);
   switch (d.src.kind * 3 + d.dst.kind) {
-    case KIND_AOS * 3 + KIND_AOS: transform_kinds<KIND_AOS, KIND_AOS, false>(d, m, i0, cnt); break;
-    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, false>(d, m, i0, cnt); break;
-    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, false>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, false>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, false>(d, m, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, false>(d, m, i0, cnt); break;
-    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, false>(d, m, i0, cnt); break;
-    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, false>(d, m, i0, cnt); break;
-    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, false>(d, m, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_AOS: transform_kinds<KIND_AOS, KIND_AOS, false>(d, m, lt, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, false>(d, m, lt, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, false>(d, m, lt, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, false>(d, m, lt, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, false>(d, m, lt, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, false>(d, m, lt, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, false>(d, m, lt, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, false>(d, m, lt, i0, cnt); break;
+    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, false>(d, m, lt, i0, cnt); break;
   }
 }
 
@@ -551,10 +624,14 @@ __device__ __forceinline__ void transform_tile(const DenseDesc& d, const DenseLd
 // into a loop-carried value, or the compiler copies it to scratch.)
 template <class Next, class Desc>
 __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc desc) {
+  LeafLanes lt;
   TileJob cur = next();
-  if (cur.valid) issue_source(desc(cur.item), smem, cur);
+  if (cur.valid) {
+    load_lanes(desc(cur.item), cur.item, lt);
+    issue_source(desc(cur.item), smem, cur);
+  }
   while (cur.valid) {
-    const DenseDesc& d = desc(cur.item);
+    const auto& d = desc(cur.item);
     const DenseLds m = carve(smem, d);
     const uint64_t i0 = cur.tile * d.tile;
     const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, cur.count - i0);
@@ -572,7 +649,7 @@ __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc de
     // 3. counts scan and value moves (into the destination image, or
     //    straight to global memory)
     if (d.scan_offsets) scan_tile(d, m, i0, cnt);
-    transform_tile(d, m, i0, cnt);
+    transform_tile(d, m, lt, i0, cnt);
     __syncthreads();
     // 4. this tile's destination image out, then the next tile's source
     //    image in (its DMA is issued after the image reads, and overlaps
@@ -583,7 +660,10 @@ __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc de
       store_side(d, m.dst, i0, cnt, full);
       if (nxt.valid && nxt.item != cur.item) __syncthreads();
     }
-    if (nxt.valid) issue_source(desc(nxt.item), smem, nxt);
+    if (nxt.valid) {
+      if (nxt.item != lt.item) load_lanes(desc(nxt.item), nxt.item, lt);
+      issue_source(desc(nxt.item), smem, nxt);
+    }
     cur = nxt;
   }
 }
@@ -602,7 +682,7 @@ struct StridedTiles {
   }
 };
 
-__global__ void __launch_bounds__(256, 8) dense_kernel(const DenseDesc d) {
+__global__ void __launch_bounds__(256, 7) dense_kernel(const DenseDesc d) {
   extern __shared__ uint4 smem_raw[];
   uint64_t count, base;
   dense_count(d, &count, &base);
@@ -616,7 +696,8 @@ __global__ void __launch_bounds__(256, 8) dense_kernel(const DenseDesc d) {
 // Exclusive scan of the per-tile totals left by the dense kernel's fused
 // scan (stored at entry tile * T), writing each tile's prefix there and the
 // grand total at entry n.  One work-group.
-__device__ void scan_totals_body(const ScanTotalsDesc& d, uint64_t* wsum) {
+template <class TD>
+__device__ void scan_totals_body(const TD& d, uint64_t* wsum) {
   const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
   uint64_t carry = 0;
   for (uint64_t c0 = 0; c0 < ntiles; c0 += blockDim.x) {
@@ -649,8 +730,8 @@ __global__ void __launch_bounds__(1024) scan_totals_kernel(const ScanTotalsDesc 
 // column then receives one 16-byte store per full group.  NW == 0: any
 // member record, value by value.  Every read stays inside the member block
 // the object's record validated against the pool (vlen).
-template <uint32_t NW>
-__device__ __forceinline__ void gather_members(const GatherDesc& d, const uint64_t* offs, const uint64_t* ptrs,
+template <uint32_t NW, class GD>
+__device__ __forceinline__ void gather_members(const GD& d, const uint64_t* offs, const uint64_t* ptrs,
                                                const uint32_t* vlen, uint32_t cnt, uint64_t m_lo, uint64_t m_hi) {
   const uint64_t start = m_lo & ~3ull;
   const uint64_t ngroups = (m_hi - start + 3) >> 2;
@@ -713,7 +794,8 @@ __device__ __forceinline__ void gather_members(const GatherDesc& d, const uint64
   }
 }
 
-__device__ void gather_tile(const GatherDesc& d, uint64_t t, uint8_t* smem) {
+template <class GD>
+__device__ void gather_tile(const GD& d, uint64_t t, uint8_t* smem) {
   uint64_t* offs = reinterpret_cast<uint64_t*>(smem);               // tile + 1
   uint64_t* ptrs = offs + (d.tile + 1);                             // tile
   uint32_t* vlen = reinterpret_cast<uint32_t*>(ptrs + d.tile);      // tile: validated count
@@ -775,7 +857,8 @@ __global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
 // Offsets column -> offsets column, rebased to start at 0, with the checks
 // of a well-formed source (non-decreasing, inside the source capacity) and
 // of the destination capacity.
-__device__ void rebase_range(const RebaseDesc& d, uint64_t begin, uint64_t step, uint64_t last) {
+template <class RD>
+__device__ void rebase_range(const RD& d, uint64_t begin, uint64_t step, uint64_t last) {
   const uint64_t first = load_off(d.src, d.off_type, 0);
   if (last > d.n) last = d.n;
   for (uint64_t i = begin; i <= last; i += step) {
@@ -804,7 +887,7 @@ __global__ void clear_status_kernel(uint32_t* status) { *gp(status) = 0; }
 __global__ void batch_count_kernel(const BatchTables b) {
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < b.n_dense; k += gridDim.x * blockDim.x) {
     uint64_t count, base;
-    dense_count(b.dense[k], &count, &base);
+    dense_count(cdesc(b.dense, k), &count, &base);
     gp(b.dense_counts)[2 * k] = count;
     gp(b.dense_counts)[2 * k + 1] = base;
   }
@@ -852,7 +935,7 @@ struct BatchTiles {
         e1 = e2;
         if (t + g < b->dense_tiles) e2 = vload(b->dense_map + t + g);
       }
-      const uint32_t tile = b->dense[item].tile;
+      const uint32_t tile = cdesc(b->dense, item).tile;
       if ((uint64_t)local * tile < count) {
         TileJob j{1, item, local, 0, 0};
         j.count = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(count >> 32)) << 32) |
@@ -866,10 +949,10 @@ struct BatchTiles {
   }
 };
 
-__global__ void __launch_bounds__(256, 4) batch_dense_kernel(const BatchTables b) {
+__global__ void __launch_bounds__(256, 7) batch_dense_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
   dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw), BatchTiles(&b, blockIdx.x),
-                 [&](uint32_t item) -> const DenseDesc& { return b.dense[item]; });
+                 [&](uint32_t item) -> const RL_C DenseDesc& { return cdesc(b.dense, item); });
 }
 
 // Tile-total scans (one work-group each) and offsets rebases.
@@ -877,13 +960,13 @@ __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   __shared__ uint64_t wsum[17];
   const uint32_t j = blockIdx.x;
   if (j < b.n_totals) {
-    scan_totals_body(b.totals[j], wsum);
+    scan_totals_body(cdesc(b.totals, j), wsum);
   } else if (j - b.n_totals < b.rebase_tiles) {
     // rebases in tiles of kRebaseTile entries, spread over work-groups
     const uint32_t t = j - b.n_totals;
     const uint32_t item = b.rebase_item[t];
     const uint64_t begin = (t - b.rebase_prefix[item]) * (uint64_t)kRebaseTile;
-    rebase_range(b.rebase[item], begin + threadIdx.x, blockDim.x, begin + kRebaseTile - 1);
+    rebase_range(cdesc(b.rebase, item), begin + threadIdx.x, blockDim.x, begin + kRebaseTile - 1);
   }
 }
 
@@ -892,7 +975,7 @@ __global__ void __launch_bounds__(1024) batch_gather_kernel(const BatchTables b)
   extern __shared__ uint4 smem_raw[];
   for (uint64_t t = blockIdx.x; t < b.gather_tiles; t += gridDim.x) {
     const uint32_t item = __builtin_amdgcn_readfirstlane(b.gather_item[t]);
-    gather_tile(b.gather[item], t - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw));
+    gather_tile(cdesc(b.gather, item), t - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw));
     __syncthreads();
   }
 }
@@ -906,9 +989,37 @@ uint32_t dense_lds_bytes(const DenseDesc& d) {
 
 uint64_t dense_tiles(const DenseDesc& d) { return (d.n + d.tile - 1) / d.tile; }
 
+// Work-groups of a kernel that fit on the device at once (occupancy x
+// compute units), per (device, kernel, threads, LDS bytes); 0 if unknown.
+static uint32_t resident_blocks(const void* kernel, uint32_t threads, uint32_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, uint32_t, uint32_t>, uint32_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(dev, kernel, threads, lds);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  uint32_t r = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)threads, lds) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0)
+    r = (uint32_t)(per_cu * cus);
+  cache[key] = r;
+  return r;
+}
+
+uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds) {
+  return resident_blocks(reinterpret_cast<const void*>(batch_dense_kernel), threads, lds);
+}
+
 hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid, hipStream_t s) {
   if (threads == 0 || threads > kDenseMaxThreads || threads % 64) return hipErrorInvalidValue;
   const uint32_t lds = dense_lds_bytes(d);
+  // persistent work-groups: no more than fit at once (a second round of
+  // work-groups would start late and leave the tail on few units)
+  const uint32_t res = resident_blocks(reinterpret_cast<const void*>(dense_kernel), threads, lds);
+  if (res && grid > res) grid = res;
   hipLaunchKernelGGL(dense_kernel, dim3(grid), dim3(threads), lds, s, d);
   return hipGetLastError();
 }
@@ -937,13 +1048,15 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
                         uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s) {
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
   if (gather_threads == 0 || gather_threads > 1024 || gather_threads % 64) return hipErrorInvalidValue;
+  const uint32_t dense_grid = grid ? grid : std::max<uint32_t>(1, batch_resident_blocks(dense_threads, dense_lds));
+  if (!grid) grid = 2048;   // gather kernel
   if (b.dense_tiles) {
     if (b.device_counts) {
       hipLaunchKernelGGL(batch_count_kernel, dim3((b.n_dense + 255) / 256), dim3(256), 0, s, b);
       hipError_t e0 = hipGetLastError();
       if (e0 != hipSuccess) return e0;
     }
-    hipLaunchKernelGGL(batch_dense_kernel, dim3(grid), dim3(dense_threads), dense_lds, s, b);
+    hipLaunchKernelGGL(batch_dense_kernel, dim3(dense_grid), dim3(dense_threads), dense_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

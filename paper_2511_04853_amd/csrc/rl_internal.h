@@ -188,6 +188,9 @@ hipError_t launch_clear_status(uint32_t* status, hipStream_t s);
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
                         uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s);
 uint32_t dense_lds_bytes(const DenseDesc& d);
+// Work-groups of the batch dense kernel that fit on the current device at
+// once for this block size and LDS size (0 if unknown).
+uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds);
 uint64_t dense_tiles(const DenseDesc& d);
 
 // ---- errors ----

@@ -234,7 +234,10 @@ def test_autotune_writes_and_reuses_cache(tmp_path):
     data = json.load(open(cache))
     assert len(data) == 1
     entry = next(iter(data.values()))
-    assert (entry["tile"], entry["threads"], entry["grid"]) == shape
+    assert (entry["tile"], entry["threads"]) == shape[:2]
+    # grid 0 in the cache means "as many work-groups as fit at once", which
+    # the shape reports resolved
+    assert entry["grid"] in (0, shape[2]) and shape[2] > 0
     # a second batch of the same shape takes the cached choice
     items2 = [Item(schemas, s, auto_width=True) for s in specs]
     b2 = Batch(autotune=0, cache=cache)
