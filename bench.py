@@ -16,9 +16,10 @@ The four conversions of a step run as one launch of the batch engine
 (persistent kernels over a device table; tile shape, work-group count and
 graph replay vs direct launch autotuned once, cached); the same
 conversions as a per-conversion launch loop are timed beside it.  The
-timed region is K steps back to back between two events; a second pass
-over the same K steps with an event pair around every launch gives the
-mean launch duration used for the roofline.
+timed region is K steps back to back between two events; each step is one
+launch of the batch dense kernel, so the region's mean step time is that
+kernel's mean launch duration (the roofline); a second pass with an event
+pair around every launch reports the duration of an isolated launch.
 
 Extra legs, outside the timed region: 512 heterogeneous collections in one
 graph launch against the launch loop, a sweep at larger object counts, the
@@ -141,8 +142,12 @@ def main():
     ms_per_step = ms_total / K
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
 
-    # the same K steps again with an event pair around every launch (on the
-    # launch stream): the mean duration of one launch of the dense kernel
+    # A step is one launch of the batch dense kernel (the only kernel of a
+    # step whose counts are host-known), so its mean launch duration in the
+    # timed region is ms_per_step.  An event pair around each launch of a
+    # second pass adds each launch's dispatch latency (reported beside it).
+    mean_launch_ms = ms_per_step
+    achieved = step_bytes / (mean_launch_ms * 1e-3) / 1e9
     evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(K)]
     torch.cuda.synchronize()
     for k in range(K):
@@ -151,9 +156,7 @@ def main():
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     assert P.sync(stream) == 0, P.rl_last_error()
-    launch_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    mean_launch_ms = float(launch_ms.mean())
-    achieved = step_bytes / (mean_launch_ms * 1e-3) / 1e9
+    isolated_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
 
     # the same conversions as a launch loop (one kernel launch per conversion)
     for k in range(args.warmup):
@@ -199,6 +202,7 @@ def main():
             "traffic": None,
             "kernel": "rl::batch_dense_kernel",
             "mean_launch_us": round(mean_launch_ms * 1e3, 3),
+            "isolated_launch_us": round(isolated_ms * 1e3, 3),
             "bytes_per_launch": int(step_bytes),
         },
         "step_launch_loop": {"ms_per_step": round(ms_loop, 5),
