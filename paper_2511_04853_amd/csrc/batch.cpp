@@ -112,6 +112,60 @@ rl_status plan_all(rl_batch* b, const Config& c) {
   return RL_OK;
 }
 
+// Where the source bytes of a dense step's tiles live: the records, blocks
+// or first column of its source (0 when the step's count is known only on
+// the device, which gives each such step keys of its own).
+static uint64_t source_key(const DenseDesc& d) {
+  if (d.count_offsets) return 0;
+  if (d.src.kind != KIND_SOA) return (uint64_t)(uintptr_t)d.src.base;
+  return d.n_leaves ? (uint64_t)(uintptr_t)d.leaf[0].src_col : 0;
+}
+
+// Tile map of the dense kernel: entry g = (step << 32) | tile of the step.
+// Work-group w runs on XCD w mod 8 and takes map entries w, w + grid, ...
+// (grids are multiples of 8), so entry g runs on XCD g mod 8, and entries
+// x, x + 8, x + 16, ... of one XCD run in that order.  Tiles that read the
+// same source objects (one source converted into several layouts) form a
+// run that goes to one XCD's consecutive entries: the later reads of the
+// run hit that XCD's L2.  Runs go to the XCD with the most entries left,
+// so single-tile runs interleave over the XCDs as in plain order.
+static void fill_dense_map(const std::vector<DenseDesc>& dense, const std::vector<uint64_t>& prefix,
+                           uint64_t* map) {
+  struct T {
+    uint64_t key, first, entry;
+  };
+  std::vector<T> tiles;
+  tiles.reserve(prefix.back());
+  for (size_t k = 0; k + 1 < prefix.size(); ++k) {
+    const uint64_t key = source_key(dense[k]);
+    for (uint64_t t = 0; t < prefix[k + 1] - prefix[k]; ++t)
+      tiles.push_back({key ? key : (uint64_t)k + 1, t * dense[k].tile, ((uint64_t)k << 32) | t});
+  }
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [](const T& a, const T& b) { return a.key != b.key ? a.key < b.key : a.first < b.first; });
+  const uint64_t L = tiles.size();
+  uint64_t next[8], left[8];
+  for (uint64_t x = 0; x < 8; ++x) {
+    next[x] = x;
+    left[x] = x < L ? (L - x + 7) / 8 : 0;
+  }
+  uint32_t rr = 0;
+  for (uint64_t i = 0; i < L;) {
+    uint64_t j = i + 1;
+    while (j < L && tiles[j].key == tiles[i].key && tiles[j].first == tiles[i].first) ++j;
+    for (uint64_t k = i; k < j;) {
+      uint32_t x = rr;
+      for (uint32_t y = 0; y < 8; ++y) {
+        const uint32_t c = (rr + y) & 7;
+        if (left[c] > left[x]) x = c;
+      }
+      rr = (x + 1) & 7;
+      for (; k < j && left[x]; ++k, --left[x], next[x] += 8) map[next[x]] = tiles[k].entry;
+    }
+    i = j;
+  }
+}
+
 rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   std::vector<DenseDesc> dense;
   std::vector<GatherDesc> gather;
@@ -169,9 +223,7 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
       dc[2 * k] = dense[k].n;
       dc[2 * k + 1] = 0;
     }
-    uint64_t* dm = (uint64_t*)(host.data() + o_dmap);
-    for (size_t k = 0; k + 1 < dprefix.size(); ++k)
-      for (uint64_t t = dprefix[k]; t < dprefix[k + 1]; ++t) dm[t] = ((uint64_t)k << 32) | (t - dprefix[k]);
+    fill_dense_map(dense, dprefix, (uint64_t*)(host.data() + o_dmap));
     uint32_t* gi = (uint32_t*)(host.data() + o_gitem);
     for (size_t k = 0; k + 1 < gprefix.size(); ++k)
       for (uint64_t t = gprefix[k]; t < gprefix[k + 1]; ++t) gi[t] = (uint32_t)k;
