@@ -445,6 +445,7 @@ PlanShape shape_from_env() {
   }
   if (const char* v = getenv("RL_GRID_BLOCKS")) s.grid = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_DST_DIRECT")) s.direct = atoi(v) ? -1 : 0;
+  if (const char* v = getenv("RL_SOURCE_DMA")) s.dma = atoi(v) ? -1 : 0;
   return s;
 }
 }  // namespace rl

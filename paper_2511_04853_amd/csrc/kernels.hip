@@ -341,10 +341,46 @@ __device__ __forceinline__ void dma_run(uint8_t* lds, const uint8_t* g, uint32_t
 // other waves read what this wave loaded.
 __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
 
+// A wave's copy of the fast-path fields of a descriptor's leaves: lane c
+// holds leaf c (a schema has at most one wavefront of leaves).  Loaded with
+// vector loads when a tile of another descriptor is issued, so the tile's
+// DMA wait covers them; the transform reads them with v_readlane and makes
+// no memory access per leaf.
+struct LeafLanes {
+  uint32_t src_off, dst_off;
+  uint32_t code;               // LeafCode | source size << 8 | op << 16
+  uint32_t col_lo, col_hi;     // SoA destination column
+  uint32_t scol_lo, scol_hi;   // SoA source column
+  uint32_t item;               // descriptor the lanes hold
+};
+
+template <class DD>
+__device__ __forceinline__ void load_lanes(const DD& d, uint32_t item, LeafLanes& t) {
+  const uint32_t lane = threadIdx.x & 63;
+  if (lane < d.n_leaves) {
+    const auto& L = d.leaf[lane];
+    t.src_off = L.src_off;
+    t.dst_off = L.dst_off;
+    t.code = (uint32_t)L.code | ((uint32_t)L.src_size << 8) | ((uint32_t)L.op << 16);
+    const uint64_t col = reinterpret_cast<uint64_t>(L.dst_col);
+    t.col_lo = (uint32_t)col;
+    t.col_hi = (uint32_t)(col >> 32);
+    const uint64_t scol = reinterpret_cast<uint64_t>(L.src_col);
+    t.scol_lo = (uint32_t)scol;
+    t.scol_hi = (uint32_t)(scol >> 32);
+  }
+  t.item = item;
+}
+
+__device__ __forceinline__ uint32_t lane_of(uint32_t v, uint32_t c) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)c);
+}
+
 // Start bringing a tile's source image into LDS: by DMA when every run is
 // 16-byte aligned, else through registers (complete on return).
 template <class DD>
-__device__ __forceinline__ void issue_source(const DD& d, uint8_t* img, const TileJob& j) {
+__device__ __forceinline__ void issue_source(const DD& d, uint8_t* img, const TileJob& j, const LeafLanes& lt,
+                                             bool lanes_ready) {
   const uint64_t i0 = j.tile * d.tile;
   const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, j.count - i0);
   const uint64_t idx0 = i0 + j.base;
@@ -358,11 +394,26 @@ __device__ __forceinline__ void issue_source(const DD& d, uint8_t* img, const Ti
       }
     } else if ((idx0 & 15) == 0) {
       // SoA (16-byte aligned columns): every column run starts 16-byte
-      // aligned when the first index is a multiple of 16
-      for (uint32_t c = 0; c < d.n_leaves; ++c) {
-        const auto& L = d.leaf[c];
-        if (L.op == OP_PTR || L.op == OP_LEN) continue;
-        dma_run(img + L.src_off, L.src_col + idx0 * L.src_size, cnt * L.src_size);
+      // aligned when the first index is a multiple of 16.  Column fields
+      // come from the wave's leaf lanes (no dependent memory access per
+      // column) unless those were just loaded: reading them then would wait
+      // for every earlier store of this wave (in-order counter).
+      const uint32_t nl = d.n_leaves;
+      if (lanes_ready) {
+        for (uint32_t c = 0; c < nl; ++c) {
+          const uint32_t w = lane_of(lt.code, c);
+          const uint32_t op = w >> 16, sz = (w >> 8) & 255;
+          if (op == OP_PTR || op == OP_LEN) continue;
+          const uint8_t* col =
+              reinterpret_cast<const uint8_t*>(((uint64_t)lane_of(lt.scol_hi, c) << 32) | lane_of(lt.scol_lo, c));
+          dma_run(img + lane_of(lt.src_off, c), col + idx0 * sz, cnt * sz);
+        }
+      } else {
+        for (uint32_t c = 0; c < nl; ++c) {
+          const auto& L = d.leaf[c];
+          if (L.op == OP_PTR || L.op == OP_LEN) continue;
+          dma_run(img + L.src_off, L.src_col + idx0 * L.src_size, cnt * L.src_size);
+        }
       }
       return;
     }
@@ -406,34 +457,6 @@ __device__ __forceinline__ void scan_tile(const DD& d, const DenseLds& m, uint64
 
 constexpr uint32_t kObjPerThread = 2;
 
-// A wave's copy of the fast-path fields of a descriptor's leaves: lane c
-// holds leaf c (a schema has at most one wavefront of leaves).  Loaded with
-// vector loads when a tile of another descriptor is issued, so the tile's
-// DMA wait covers them; the transform reads them with v_readlane and makes
-// no memory access per leaf.
-struct LeafLanes {
-  uint32_t src_off, dst_off, code, col_lo, col_hi;
-  uint32_t item;   // descriptor the lanes hold
-};
-
-template <class DD>
-__device__ __forceinline__ void load_lanes(const DD& d, uint32_t item, LeafLanes& t) {
-  const uint32_t lane = threadIdx.x & 63;
-  if (lane < d.n_leaves) {
-    const auto& L = d.leaf[lane];
-    t.src_off = L.src_off;
-    t.dst_off = L.dst_off;
-    t.code = L.code;
-    const uint64_t col = reinterpret_cast<uint64_t>(L.dst_col);
-    t.col_lo = (uint32_t)col;
-    t.col_hi = (uint32_t)(col >> 32);
-  }
-  t.item = item;
-}
-
-__device__ __forceinline__ uint32_t lane_of(uint32_t v, uint32_t c) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)c);
-}
 
 // Object-dependent address terms of one side: addr = a + off + b * size.
 template <uint32_t K, class SD>
@@ -496,7 +519,7 @@ __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, c
     uint8_t* const colp = col ? reinterpret_cast<uint8_t*>(((uint64_t)lane_of(lt.col_hi, c) << 32) | lane_of(lt.col_lo, c))
                               : nullptr;
     const uint32_t dof = col ? 0u : lane_of(lt.dst_off, c);
-    switch (lane_of(lt.code, c)) {
+    switch (lane_of(lt.code, c) & 255) {
       case CODE_COPY1: RL_MOVE(uint8_t, uint8_t, 1, 1, x); break;
       case CODE_COPY2: RL_MOVE(uint16_t, uint16_t, 2, 2, x); break;
       case CODE_COPY4: RL_MOVE(uint32_t, uint32_t, 4, 4, x); break;
@@ -628,7 +651,7 @@ __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc de
   TileJob cur = next();
   if (cur.valid) {
     load_lanes(desc(cur.item), cur.item, lt);
-    issue_source(desc(cur.item), smem, cur);
+    issue_source(desc(cur.item), smem, cur, lt, true);   // no stores outstanding yet
   }
   while (cur.valid) {
     const auto& d = desc(cur.item);
@@ -661,8 +684,9 @@ __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc de
       if (nxt.valid && nxt.item != cur.item) __syncthreads();
     }
     if (nxt.valid) {
-      if (nxt.item != lt.item) load_lanes(desc(nxt.item), nxt.item, lt);
-      issue_source(desc(nxt.item), smem, nxt);
+      const bool reuse = nxt.item == lt.item;
+      if (!reuse) load_lanes(desc(nxt.item), nxt.item, lt);
+      issue_source(desc(nxt.item), smem, nxt, lt, reuse);
     }
     cur = nxt;
   }
@@ -949,7 +973,7 @@ struct BatchTiles {
   }
 };
 
-__global__ void __launch_bounds__(256, 7) batch_dense_kernel(const BatchTables b) {
+__global__ void __launch_bounds__(256, 6) batch_dense_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
   dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw), BatchTiles(&b, blockIdx.x),
                  [&](uint32_t item) -> const RL_C DenseDesc& { return cdesc(b.dense, item); });
@@ -989,6 +1013,13 @@ uint32_t dense_lds_bytes(const DenseDesc& d) {
 
 uint64_t dense_tiles(const DenseDesc& d) { return (d.n + d.tile - 1) / d.tile; }
 
+// LDS is handed to work-groups in granules of 1,280 bytes on gfx950
+// (measured: residency against dynamic LDS size from 16 to 64 KiB in 512 B
+// steps matches floor(160 KiB / round_up(bytes, 1280)) exactly); the
+// occupancy query assumes finer granules and overcounts just below each
+// granule boundary.
+constexpr uint32_t kLdsGranule = 1280;
+
 // Work-groups of a kernel that fit on the device at once (occupancy x
 // compute units), per (device, kernel, threads, LDS bytes); 0 if unknown.
 static uint32_t resident_blocks(const void* kernel, uint32_t threads, uint32_t lds) {
@@ -1000,11 +1031,17 @@ static uint32_t resident_blocks(const void* kernel, uint32_t threads, uint32_t l
   std::lock_guard<std::mutex> g(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
-  int per_cu = 0, cus = 0;
+  int per_cu = 0, cus = 0, lds_cu = 0;
   uint32_t r = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)threads, lds) == hipSuccess &&
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0)
-    r = (uint32_t)(per_cu * cus);
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0) {
+    if (lds && hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        lds_cu > 0) {
+      const uint32_t granules = (lds + kLdsGranule - 1) / kLdsGranule;
+      per_cu = std::min<int>(per_cu, (int)((uint32_t)lds_cu / (granules * kLdsGranule)));
+    }
+    if (per_cu > 0) r = (uint32_t)(per_cu * cus);
+  }
   cache[key] = r;
   return r;
 }
