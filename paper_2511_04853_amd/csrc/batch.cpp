@@ -183,8 +183,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
           break;
         case Step::GATHER:
           gather.push_back(s.gather);
-          gprefix.push_back(gprefix.back() + (s.gather.n + s.gather.tile - 1) / s.gather.tile);
-          gather_lds = std::max(gather_lds, (2 * s.gather.tile + 1) * 8 + s.gather.tile * 4);
+          gprefix.push_back(gprefix.back() + (s.gather.n + s.gather.sub - 1) / s.gather.sub);
+          gather_lds = std::max(gather_lds, gather_lds_bytes(s.gather.sub, s.gather.packed_words));
           break;
         case Step::SCAN_TOTALS: totals.push_back(s.totals); break;
         case Step::REBASE:
@@ -265,7 +265,7 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
 
 rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s) {
   const uint32_t dt = std::min<uint32_t>(c.threads, kDenseMaxThreads);
-  hipError_t e = launch_batch(d.t, dt, 256, c.grid, d.dense_lds, d.gather_lds, s);
+  hipError_t e = launch_batch(d.t, dt, kGatherThreads, c.grid, d.dense_lds, d.gather_lds, s);
   return e == hipSuccess ? RL_OK : hip_fail(e, "batch launch");
 }
 
@@ -418,7 +418,8 @@ rl_status choose_launch(rl_batch* b, hipStream_t s) {
   for (int mode = 0; mode < 2; ++mode) {
     for (int k = 0; k < reps + 2; ++k) {
       if (k == 2) (void)hipEventRecord(e0, s);
-      hipError_t e = mode == 0 ? hipGraphLaunch(b->exec, s) : launch_batch(b->dev.t, std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads), 256, b->cfg.grid, b->dev.dense_lds, b->dev.gather_lds, s);
+      hipError_t e = mode == 0 ? hipGraphLaunch(b->exec, s) : launch_batch(b->dev.t, std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads), kGatherThreads, b->cfg.grid, b->dev.dense_lds,
+                                 b->dev.gather_lds, s);
       if (e != hipSuccess) return hip_fail(e, "tuning launch");
     }
     (void)hipEventRecord(e1, s);

@@ -818,64 +818,135 @@ __device__ __forceinline__ void gather_members(const GD& d, const uint64_t* offs
   }
 }
 
-template <class GD>
-__device__ void gather_tile(const GD& d, uint64_t t, uint8_t* smem) {
-  uint64_t* offs = reinterpret_cast<uint64_t*>(smem);               // tile + 1
-  uint64_t* ptrs = offs + (d.tile + 1);                             // tile
-  uint32_t* vlen = reinterpret_cast<uint32_t*>(ptrs + d.tile);      // tile: validated count
+// One 4-byte DMA per lane from global memory into LDS: lane l lands at
+// lds_base + 4 l (lds_base wave-uniform).  See dma16.
+__device__ __forceinline__ void dma4(const uint8_t* g, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off"
+               :: "v"(g), "s"(lds_base) : "memory", "m0");
+}
+
+// Members [m_lo, m_hi) whose records are NW packed 4-byte words: each lane
+// finds its member's owner (binary search over the staged offsets) and
+// DMAs the member's words into one LDS column per word; after one wait the
+// columns go out as 16-byte vectors.  No member's load waits behind another
+// member's store.  A member's LDS slot has the same address mod 16 as its
+// place in the destination column.  Members outside their record's
+// validated block are not loaded (their column entries are then
+// unspecified; the status word says so).
+template <uint32_t NW, class GD>
+__device__ __forceinline__ void gather_words(const GD& d, const uint64_t* offs, const uint64_t* ptrs,
+                                             const uint32_t* vlen, uint32_t cnt, uint64_t m_lo, uint64_t m_hi,
+                                             uint32_t* stage) {
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint64_t limit = off_limit(d.off_type);
-  const uint64_t pool_end = d.pool_bytes;
-  {
-    const uint64_t i0 = t * d.tile;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, d.n - i0);
-    const uint64_t prefix = load_off(d.offsets, d.off_type, i0);
-    for (uint32_t o = tid; o <= cnt; o += nt) {
-      uint64_t v;
-      if (o == 0) v = prefix;
-      else if (o == cnt) v = load_off(d.offsets, d.off_type, i0 + cnt);  // next tile's prefix or total
-      else {
-        v = load_off(d.offsets, d.off_type, i0 + o) + prefix;
-        store_off(d.offsets, d.off_type, i0 + o, v);
+  const uint32_t lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  for (uint64_t p0 = m_lo; p0 < m_hi; p0 += kGatherStage) {
+    const uint32_t pm = (uint32_t)min<uint64_t>(kGatherStage, m_hi - p0);
+    const uint32_t sh = (uint32_t)(p0 & 3);   // slot of member p0
+    for (uint32_t vb = wave * 64; vb < pm; vb += nw * 64) {
+      const uint32_t k = vb + lane;
+      const uint64_t m = p0 + k;
+      bool ok = k < pm;
+      const uint8_t* src = d.pool;
+      if (ok) {
+        uint32_t lo = 0, hi = cnt;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (offs[mid] <= m) lo = mid; else hi = mid;
+        }
+        const uint64_t j = m - offs[lo];
+        ok = m >= offs[lo] && j < vlen[lo];
+        src = d.pool + ptrs[lo] + j * d.mstride;
       }
-      offs[o] = v & limit;
-    }
-    __syncthreads();
-    if (d.n_members == 0) return;  // uniform: offsets only
-    for (uint32_t o = tid; o < cnt; o += nt) {
-      const uint8_t* rec = d.records + (i0 + o) * d.rec_stride;
-      const uint64_t p = *gp(reinterpret_cast<const uint64_t*>(rec + d.ptr_off));
-      const uint64_t len = *gp(reinterpret_cast<const uint32_t*>(rec + d.len_off));
-      const bool good = (p & (uint64_t)(d.malign - 1)) == 0 && p <= pool_end &&
-                        len <= (pool_end - p) / d.mstride;
-      ptrs[o] = p;
-      vlen[o] = good ? (uint32_t)len : 0u;   // members readable for this object
-      if (!good) flag(d.status, ST_FLAG_BOUNDS);
-    }
-    __syncthreads();
-    const uint64_t m_lo = offs[0];
-    uint64_t m_hi = offs[cnt];
-    if (m_hi > d.capacity) m_hi = d.capacity;
-    if (m_hi > m_lo) {
-      switch (d.packed_words) {
-        case 1: gather_members<1>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
-        case 2: gather_members<2>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
-        case 3: gather_members<3>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
-        case 4: gather_members<4>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
-        default: gather_members<0>(d, offs, ptrs, vlen, cnt, m_lo, m_hi); break;
+#pragma unroll
+      for (uint32_t q = 0; q < NW; ++q) {
+        uint8_t* col = reinterpret_cast<uint8_t*>(stage + q * (kGatherStage + 4) + sh + vb);
+        const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr)col);
+        if (ok) dma4(src + 4 * q, base);
       }
+    }
+    dma_wait();
+    __syncthreads();
+    // columns out: head words up to 16-byte alignment, vectors, tail words
+    const uint64_t a0 = min<uint64_t>((p0 + 3) & ~3ull, p0 + pm), a1 = max<uint64_t>(a0, (p0 + pm) & ~3ull);
+#pragma unroll
+    for (uint32_t q = 0; q < NW; ++q) {
+      const uint32_t* sq = stage + q * (kGatherStage + 4) + sh;   // member p0 + i at sq[i]
+      RL_G uint32_t* col = gp(reinterpret_cast<uint32_t*>(d.mcol[q])) + p0;
+      const uint32_t head = (uint32_t)(a0 - p0), body = (uint32_t)(a1 - a0) >> 2;
+      for (uint32_t i = tid; i < head; i += nt) col[i] = sq[i];
+      const v4u* sv = reinterpret_cast<const v4u*>(sq + head);
+      RL_G v4u* cv = reinterpret_cast<RL_G v4u*>(col + head);
+      for (uint32_t v = tid; v < body; v += nt) cv[v] = sv[v];
+      for (uint32_t i = head + 4 * body + tid; i < pm; i += nt) col[i] = sq[i];
     }
     __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(1024) gather_kernel(const GatherDesc d) {
-  extern __shared__ uint4 smem_raw[];
-  const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    gather_tile(d, t, reinterpret_cast<uint8_t*>(smem_raw));
-    __syncthreads();
+// Sub-tile u of d.sub objects (a part of a scan tile of d.tile objects):
+// its offsets made final and its objects' members copied from the pool into
+// the member columns.  The fused scan left tile-local offsets; the totals
+// pass put the tile's prefix at the tile's first entry.  Each work-group
+// reads and rewrites only its own entries plus that prefix (which keeps its
+// value); the end of its last object is final(last) + count(last), as the
+// scan computed it.  Objects (final offset, validated record pointer and
+// count) are staged in LDS; every pool read stays inside the member block
+// the record validated (vlen).
+template <class GD>
+__device__ void gather_sub(const GD& d, uint64_t u, uint8_t* smem) {
+  const uint32_t S = d.sub;
+  uint64_t* offs = reinterpret_cast<uint64_t*>(smem);   // S + 1
+  uint64_t* ptrs = offs + (S + 1);                      // S
+  uint32_t* vlen = reinterpret_cast<uint32_t*>(ptrs + S);
+  uint32_t* stage = reinterpret_cast<uint32_t*>(smem + gather_stage_offset(S));
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t i0 = u * S;
+  if (i0 >= d.n) return;   // uniform
+  const uint32_t cnt = (uint32_t)min<uint64_t>(S, d.n - i0);
+  const uint64_t t0 = i0 / d.tile * d.tile;
+  const uint64_t prefix = load_off(d.offsets, d.off_type, t0);
+  const uint64_t limit = off_limit(d.off_type);
+  const uint64_t pool_end = d.pool_bytes;
+  for (uint32_t k = tid; k < cnt; k += nt) {
+    const uint64_t i = i0 + k;
+    uint64_t v = prefix;
+    if (i != t0) {
+      v += load_off(d.offsets, d.off_type, i);
+      store_off(d.offsets, d.off_type, i, v);
+    }
+    offs[k] = v & limit;
+    if (d.n_members == 0 && k + 1 < cnt) continue;
+    const uint8_t* rec = d.records + i * d.rec_stride;
+    const uint64_t len = *gp(reinterpret_cast<const uint32_t*>(rec + d.len_off));
+    if (k + 1 == cnt) offs[cnt] = (v + len) & limit;
+    if (d.n_members == 0) continue;
+    const uint64_t p = *gp(reinterpret_cast<const uint64_t*>(rec + d.ptr_off));
+    const bool good = (p & (uint64_t)(d.malign - 1)) == 0 && p <= pool_end && len <= (pool_end - p) / d.mstride;
+    ptrs[k] = p;
+    vlen[k] = good ? (uint32_t)len : 0u;   // members readable for this object
+    if (!good) flag(d.status, ST_FLAG_BOUNDS);
   }
+  if (d.n_members == 0) return;   // uniform: offsets only
+  __syncthreads();
+  const uint64_t lo = offs[0];
+  uint64_t hi = offs[cnt];
+  if (hi > d.capacity) hi = d.capacity;
+  if (hi > lo) {
+    switch (d.packed_words) {
+      case 1: gather_words<1>(d, offs, ptrs, vlen, cnt, lo, hi, stage); break;
+      case 2: gather_words<2>(d, offs, ptrs, vlen, cnt, lo, hi, stage); break;
+      case 3: gather_words<3>(d, offs, ptrs, vlen, cnt, lo, hi, stage); break;
+      case 4: gather_words<4>(d, offs, ptrs, vlen, cnt, lo, hi, stage); break;
+      default: gather_members<0>(d, offs, ptrs, vlen, cnt, lo, hi); break;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) gather_kernel(const GatherDesc d) {
+  extern __shared__ uint4 smem_raw[];
+  const uint64_t nsub = (d.n + d.sub - 1) / d.sub;
+  for (uint64_t u = blockIdx.x; u < nsub; u += gridDim.x) gather_sub(d, u, reinterpret_cast<uint8_t*>(smem_raw));
 }
 
 // Offsets column -> offsets column, rebased to start at 0, with the checks
@@ -994,13 +1065,12 @@ __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   }
 }
 
-// Every gather tile of every jagged item, strided like the dense kernel.
-__global__ void __launch_bounds__(1024) batch_gather_kernel(const BatchTables b) {
+// Sub-tiles of every jagged item, strided like the dense kernel.
+__global__ void __launch_bounds__(256) batch_gather_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
-  for (uint64_t t = blockIdx.x; t < b.gather_tiles; t += gridDim.x) {
-    const uint32_t item = __builtin_amdgcn_readfirstlane(b.gather_item[t]);
-    gather_tile(cdesc(b.gather, item), t - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw));
-    __syncthreads();
+  for (uint64_t u = blockIdx.x; u < b.gather_tiles; u += gridDim.x) {
+    const uint32_t item = __builtin_amdgcn_readfirstlane(b.gather_item[u]);
+    gather_sub(cdesc(b.gather, item), u - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw));
   }
 }
 
@@ -1066,11 +1136,18 @@ hipError_t launch_scan_totals(const ScanTotalsDesc& d, hipStream_t s) {
   return hipGetLastError();
 }
 
+uint32_t gather_lds_bytes(uint32_t sub, uint32_t words) {
+  return gather_stage_offset(sub) + words * (kGatherStage + 4) * 4;
+}
+
 hipError_t launch_gather(const GatherDesc& d, uint32_t threads, hipStream_t s) {
-  const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
-  const uint32_t grid = (uint32_t)(ntiles < 65535ull * 8 ? ntiles : 65535ull * 8);
-  const uint32_t lds = (2 * d.tile + 1) * 8 + d.tile * 4;
-  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(threads), lds, s, d);
+  if (threads == 0 || threads > 256 || threads % 64 || d.sub == 0) return hipErrorInvalidValue;
+  const uint64_t nsub = (d.n + d.sub - 1) / d.sub;
+  const uint32_t lds = gather_lds_bytes(d.sub, d.packed_words);
+  uint64_t grid = std::min<uint64_t>(nsub ? nsub : 1, 65535ull * 8);
+  const uint32_t res = resident_blocks(reinterpret_cast<const void*>(gather_kernel), threads, lds);
+  if (res && grid > res) grid = res;
+  hipLaunchKernelGGL(gather_kernel, dim3((uint32_t)grid), dim3(threads), lds, s, d);
   return hipGetLastError();
 }
 
@@ -1084,9 +1161,9 @@ hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s) {
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
                         uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s) {
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
-  if (gather_threads == 0 || gather_threads > 1024 || gather_threads % 64) return hipErrorInvalidValue;
+  if (gather_threads == 0 || gather_threads > 256 || gather_threads % 64) return hipErrorInvalidValue;
   const uint32_t dense_grid = grid ? grid : std::max<uint32_t>(1, batch_resident_blocks(dense_threads, dense_lds));
-  if (!grid) grid = 2048;   // gather kernel
+  if (!grid) grid = 2048;   // finalisation and gather kernels
   if (b.dense_tiles) {
     if (b.device_counts) {
       hipLaunchKernelGGL(batch_count_kernel, dim3((b.n_dense + 255) / 256), dim3(256), 0, s, b);
@@ -1103,7 +1180,9 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
     if (e != hipSuccess) return e;
   }
   if (b.gather_tiles) {
-    hipLaunchKernelGGL(batch_gather_kernel, dim3(grid), dim3(gather_threads), gather_lds, s, b);
+    const uint32_t gres = resident_blocks(reinterpret_cast<const void*>(batch_gather_kernel), gather_threads, gather_lds);
+    const uint32_t ggrid = std::min<uint32_t>(b.gather_tiles, gres ? gres : grid);
+    hipLaunchKernelGGL(batch_gather_kernel, dim3(ggrid), dim3(gather_threads), gather_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

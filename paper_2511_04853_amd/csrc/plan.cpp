@@ -208,6 +208,17 @@ static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& sha
   return RL_OK;
 }
 
+// Objects per gather work-group: a power of two dividing the scan tile,
+// sized for one staging pass of members at the destination's mean members
+// per object (the capacity bounds the total), at least 16.
+static uint32_t gather_sub_objects(uint32_t tile, uint64_t n, uint64_t capacity) {
+  if (!capacity || !n) return tile;
+  const uint64_t per = std::max<uint64_t>(1, (capacity + n - 1) / n);
+  uint32_t sub = 16;
+  while (sub * 2 <= tile && tile % (sub * 2) == 0 && (uint64_t)sub * 2 * per <= kGatherStage) sub *= 2;
+  return sub;
+}
+
 // Scan + gather steps for group g of an AoS record source into an offsets
 // destination.  `fused` says the first pass already ran inside the objects'
 // dense step.
@@ -271,7 +282,8 @@ static rl_status push_scan_gather(Plan* plan, const rl_view& src, const rl_view&
       packed = G.msize[m] == 4 && G.moff[m] == 4 * m && ((uintptr_t)G.mcol[m] & 15) == 0;
     G.packed_words = packed ? G.n_members : 0;
   }
-  ga.threads = shape.threads ? shape.threads : 256;
+  G.sub = gather_sub_objects(tile, n, gather ? G.capacity : 0);
+  ga.threads = kGatherThreads;
   plan->steps.push_back(ga);
   return RL_OK;
 }

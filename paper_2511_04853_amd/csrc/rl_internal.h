@@ -134,6 +134,8 @@ struct GatherDesc {
   uint32_t malign;         // member record alignment
   uint32_t n_members;      // member leaves (0: offsets only)
   uint32_t packed_words;   // 1..4: member leaves are the words of a packed record (fast path); 0: generic
+  uint32_t sub;            // objects per gather work-group (divides tile)
+  uint32_t pad0;
   const uint8_t* pool;
   uint64_t pool_bytes;
   uint32_t* status;
@@ -164,10 +166,10 @@ struct BatchTables {
   uint32_t n_dense;
   uint32_t dense_tiles;
   const GatherDesc* gather;
-  const uint64_t* gather_prefix;
-  const uint32_t* gather_item;      // tile -> gather step
+  const uint64_t* gather_prefix;    // first sub-tile of each gather step
+  const uint32_t* gather_item;      // sub-tile -> gather step
   uint32_t n_gather;
-  uint32_t gather_tiles;
+  uint32_t gather_tiles;            // sub-tiles of all gather steps
   const ScanTotalsDesc* totals;
   uint32_t n_totals;
   uint32_t n_rebase;
@@ -187,6 +189,15 @@ hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s);
 hipError_t launch_clear_status(uint32_t* status, hipStream_t s);
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
                         uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s);
+// Members per pass of the packed-word gather (LDS staging per word).
+constexpr uint32_t kGatherStage = 1024;
+// LDS of a gather work-group: staged objects, then the word columns.
+__host__ __device__ inline uint32_t gather_stage_offset(uint32_t sub) {
+  return ((2 * sub + 1) * 8 + sub * 4 + 15) & ~15u;
+}
+uint32_t gather_lds_bytes(uint32_t sub, uint32_t words);
+// Threads of a gather work-group.
+constexpr uint32_t kGatherThreads = 128;
 uint32_t dense_lds_bytes(const DenseDesc& d);
 // Work-groups of the batch dense kernel that fit on the current device at
 // once for this block size and LDS size (0 if unknown).
