@@ -193,6 +193,7 @@ struct DenseLds {
   uint8_t* src;
   uint8_t* dst;
   uint64_t* wsum;
+  uint64_t* offs;   // staged offsets: [0] = entry 0, [1 + k] = entry i0 + k
 };
 
 __host__ __device__ __forceinline__ uint32_t round16(uint32_t x) { return (x + 15u) & ~15u; }
@@ -273,6 +274,7 @@ __device__ __forceinline__ DenseLds carve(uint8_t* smem, const DD& d) {
   m.src = smem;
   m.dst = smem + round16(d.src.image_bytes);
   m.wsum = reinterpret_cast<uint64_t*>(m.dst + (d.dst_direct ? 0u : round16(d.dst.image_bytes)));
+  m.offs = m.wsum + 18;
   return m;
 }
 
@@ -535,7 +537,7 @@ __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, c
 // Leaves at misaligned image addresses and destination record (pointer,
 // count) pairs: one object per thread, generic address arithmetic.
 template <class DD>
-__device__ __forceinline__ void transform_slow(const DD& d, uint8_t* src_img, uint8_t* dst_img,
+__device__ __forceinline__ void transform_slow(const DD& d, uint8_t* src_img, uint8_t* dst_img, const uint64_t* offs,
                                             uint64_t i0, uint32_t cnt) {
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
     const auto& L = d.leaf[c];
@@ -555,14 +557,15 @@ __device__ __forceinline__ void transform_slow(const DD& d, uint8_t* src_img, ui
       }
       // destination record (pointer, count) from the source offsets
       const uint64_t i = i0 + o;
-      const uint64_t first = load_off(L.src_col, L.off_type, 0);
-      const uint64_t a = load_off(L.src_col, L.off_type, i);
+      const bool staged = L.src_col == d.stage_offsets;
+      const uint64_t first = staged ? offs[0] : load_off(L.src_col, L.off_type, 0);
+      const uint64_t a = staged ? offs[1 + o] : load_off(L.src_col, L.off_type, i);
       if (L.code == CODE_PTR) {
         const uint64_t v = (a - first) * (uint64_t)L.mstride;
         if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 8);
         else *reinterpret_cast<uint64_t*>(dp) = v;
       } else {
-        const uint32_t v = (uint32_t)(load_off(L.src_col, L.off_type, i + 1) - a);
+        const uint32_t v = (uint32_t)((staged ? offs[2 + o] : load_off(L.src_col, L.off_type, i + 1)) - a);
         if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 4);
         else *reinterpret_cast<uint32_t*>(dp) = v;
       }
@@ -627,7 +630,16 @@ __device__ __forceinline__ void transform_tile(const DD& d, const DenseLds& m, c
     transform_direct(d, m, lt, i0, cnt);
     return;
   }
-  if (d.slow_leaves) transform_slow(d, m.src, m.dst, i0, cnt);
+  if (d.slow_leaves) {
+    if (d.stage_offsets) {
+      // the tile's offsets (and entry 0) in LDS: one round trip per tile
+      // instead of dependent global loads per object
+      for (uint32_t k = threadIdx.x; k <= cnt + 1; k += blockDim.x)
+        m.offs[k] = load_off(d.stage_offsets, d.stage_type, k == 0 ? 0 : i0 + k - 1);
+      __syncthreads();
+    }
+    transform_slow(d, m.src, m.dst, m.offs, i0, cnt);
+  }
   switch (d.src.kind * 3 + d.dst.kind) {
     case KIND_AOS * 3 + KIND_AOS: transform_kinds<KIND_AOS, KIND_AOS, false>(d, m, lt, i0, cnt); break;
     case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, false>(d, m, lt, i0, cnt); break;
@@ -1078,7 +1090,7 @@ __global__ void __launch_bounds__(256) batch_gather_kernel(const BatchTables b) 
 
 uint32_t dense_lds_bytes(const DenseDesc& d) {
   return round16(d.src.image_bytes) + (d.dst_direct ? 0u : round16(d.dst.image_bytes)) +
-         round16(17 * sizeof(uint64_t));
+         round16(17 * sizeof(uint64_t)) + (d.stage_offsets ? (d.tile + 2) * 8 : 0u);
 }
 
 uint64_t dense_tiles(const DenseDesc& d) { return (d.n + d.tile - 1) / d.tile; }

@@ -310,8 +310,13 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
   if (st) return st;
   dd.status = status;
   dd.zero_dst = DL->kind == RL_AOS && DL->has_gaps;
-  // destination records of a jagged schema get (ptr, len) from the source offsets
+  // destination records of a jagged schema get (ptr, len) from the source
+  // offsets (staged in LDS per tile when there is one group)
   if (ng && DL->kind == RL_AOS) {
+    if (ng == 1) {
+      dd.stage_offsets = (const uint8_t*)src.buffers[group_buffer(SL, 0)];
+      dd.stage_type = (uint32_t)sc->offset_types[0];
+    }
     for (uint32_t g = 0; g < ng; ++g) {
       const rl_type ot = sc->offset_types[g];
       const uint8_t* so = (const uint8_t*)src.buffers[group_buffer(SL, g)];

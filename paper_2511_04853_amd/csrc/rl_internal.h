@@ -103,6 +103,11 @@ struct DenseDesc {
                            //    (SoA / AoSoA destination, no destination image in LDS)
   uint32_t vt_magic;       // ceil(2^32 / (tile / 16)): SoA image vector -> byte unit
   uint64_t src_capacity;   // with count_offsets: source member capacity (count <= it - base)
+  // Offsets column staged in LDS per tile for the record (pointer, count)
+  // leaves of an AoS destination (null: read from global memory per object).
+  const uint8_t* stage_offsets;
+  uint32_t stage_type;     // rl_type of stage_offsets
+  uint32_t pad2;
   LeafDesc leaf[kMaxLeaves];
   uint8_t unit_src[kMaxUnits];   // SoA image: byte unit of object size -> leaf
   uint8_t unit_dst[kMaxUnits];
