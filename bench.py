@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--leg", choices=["round_trip", "jagged", "serving", "batched", "sweep", "h2d"],
+                    help="run only this extra leg and print its JSON (for profiling one leg)")
     return ap.parse_args()
 
 
@@ -70,6 +72,9 @@ def main():
     P.lib()
     stream = torch.cuda.current_stream()
     sp = P.stream_ptr(stream)
+    if args.leg:
+        print(json.dumps(run_leg(args.leg, P, W, torch, stream)), flush=True)
+        return
 
     # calibration copy of known size for the HBM byte counters (untimed)
     calib = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
@@ -348,6 +353,25 @@ def batched(P, W, torch, stream, tune_cache):
     del keep, b
     torch.cuda.empty_cache()
     return res
+
+
+def run_leg(name, P, W, torch, stream):
+    """One extra leg on its own (same code as in the full run)."""
+    if name == "round_trip":
+        return plain_round_trip(P, W, torch, stream)
+    if name == "jagged":
+        return jagged(P, W, torch, stream)
+    if name == "serving":
+        return serving(P, W, torch, stream)
+    if name == "batched":
+        return batched(P, W, torch, stream, os.path.join(os.environ.get("TMPDIR", "/tmp"),
+                                                         f"rl_tune_{os.getpid()}.json"))
+    if name == "sweep":
+        return sweep(P, W, torch, stream)
+    S = P.Schema(W.CELL)
+    aos = P.Layout(S, "aos")
+    soa = P.Layout(S, "soa", storage=["f32" if f.type == "f64" else f.type for f in W.CELL.fields])
+    return h2d_rate(P, W, torch, stream, S, aos, soa, W.cell_values(N_CELLS))
 
 
 def kernel_source_hash():
