@@ -196,7 +196,7 @@ def main():
             "bytes_per_step": step_bytes,
             "conversions_per_step": len(dsts),
             "launch": f"one batch launch per step (the 4 conversions; {shape[3]}), "
-                      f"tile {shape[0]} objects, {shape[1]} threads, {shape[2]} persistent blocks (autotuned)",
+                      f"tile {shape[0]} objects, {shape[1]} threads, {shape[2]} work-groups (autotuned)",
         },
         "roofline": {
             "bound": "hbm",

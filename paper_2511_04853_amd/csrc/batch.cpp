@@ -45,6 +45,8 @@ struct Item {
   bool auto_width() const { return dst_layout->kind == RL_AOSOA && dst_layout->width == 0; }
 };
 
+constexpr uint32_t kOnePerTile = 1u << 30;   // grid larger than any tile count
+
 struct Config {
   uint32_t tile = 256, threads = 128, width = 64;   // threads: dense work-groups
   uint32_t grid = 0;     // dense work-groups; 0: as many as fit on the device at once
@@ -382,7 +384,9 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
   Config bc;
   for (uint32_t tile : {64u, 128u, 256u, 512u, 1024u})
     for (uint32_t threads : {64u, 128u, 256u})
-      for (uint32_t grid : {0u, 1024u, 2048u, 4096u, 8192u}) {   // 0: as many as fit at once
+      // 0: as many work-groups as fit at once (persistent); kOnePerTile: one
+      // work-group per tile (the dispatcher balances uneven tiles)
+      for (uint32_t grid : {0u, 1024u, 2048u, 4096u, 8192u, kOnePerTile}) {
         if (threads > 2 * tile) continue;   // at least half the threads hold an object
         Config c;
         c.tile = tile;
@@ -551,9 +555,14 @@ extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t*
   if (!b) return fail(RL_EINVAL, "batch is NULL");
   if (tile) *tile = b->cfg.tile;
   if (threads) *threads = b->cfg.threads;
-  if (grid) *grid = b->cfg.grid ? b->cfg.grid
-                                 : batch_resident_blocks(std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads),
-                                                         b->dev.dense_lds);
+  if (grid) {
+    // dense work-groups as launched: the configured count or as many as fit
+    // at once, at most one per tile
+    const uint32_t g = b->cfg.grid ? b->cfg.grid
+                                   : batch_resident_blocks(std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads),
+                                                           b->dev.dense_lds);
+    *grid = std::min<uint32_t>(g, std::max(1u, b->dev.t.dense_tiles));
+  }
   if (graph_replay) *graph_replay = b->cfg.direct ? 0 : 1;
   return RL_OK;
 }

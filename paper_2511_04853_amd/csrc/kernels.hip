@@ -1174,7 +1174,8 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
                         uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s) {
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
   if (gather_threads == 0 || gather_threads > 256 || gather_threads % 64) return hipErrorInvalidValue;
-  const uint32_t dense_grid = grid ? grid : std::max<uint32_t>(1, batch_resident_blocks(dense_threads, dense_lds));
+  const uint32_t dense_grid = std::min<uint32_t>(
+      grid ? grid : std::max<uint32_t>(1, batch_resident_blocks(dense_threads, dense_lds)), std::max(1u, b.dense_tiles));
   if (!grid) grid = 2048;   // finalisation and gather kernels
   if (b.dense_tiles) {
     if (b.device_counts) {

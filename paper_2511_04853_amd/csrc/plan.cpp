@@ -66,12 +66,20 @@ uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target, uint
   if (s.kind == KIND_AOSOA) unit = lcm32(unit, s.width);
   if (d.kind == KIND_AOSOA) unit = lcm32(unit, d.width);
   if (unit > kMaxTile) return 0;
+  // Tile targets are object counts for objects of about 32 bytes: a tile
+  // carries a fixed cost (descriptor, DMA issue, barriers), so smaller
+  // objects (member records of a few bytes) get proportionally more of them.
+  const uint64_t per = std::max<uint64_t>(1, std::max(image_bytes(s, 1), image_bytes(d, 1)));
+  const uint32_t scale = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(16, 32 / per));
   if (!target) {
     // long column runs favour large tiles; small collections need enough
     // tiles to spread over the 256 compute units
-    target = kDefaultTile;
+    target = kDefaultTile * scale;
     while (target > 128 && n && (n + target - 1) / target < 1024) target /= 2;
+  } else {
+    target *= scale;
   }
+  target = std::min<uint32_t>(target, kMaxTile);
   uint32_t t = std::max(unit, target / unit * unit);
   while (t >= unit) {
     const uint64_t lds = ((image_bytes(s, t) + 15) & ~15ull) + ((image_bytes(d, t) + 15) & ~15ull) + 144;
