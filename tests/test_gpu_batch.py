@@ -249,3 +249,49 @@ def test_autotune_writes_and_reuses_cache(tmp_path):
     b2.launch()
     assert P.sync() == 0
     _check_against_oracle(items2, b2)
+
+
+class SharedSourceItem(Item):
+    """Another destination for the source of an existing item (the batch
+    converts one source into several layouts)."""
+
+    def __init__(self, base, dst_kind, narrow=None, width=None):
+        self.n, self.sp, self.decl = base.n, base.sp, base.decl
+        self.src, self.sbytes, self.src_mem, self.tot = base.src, base.sbytes, base.src_mem, base.tot
+        self.dsrc, self.sv = base.dsrc, base.sv
+        self.auto = dst_kind == "aosoa" and width is None
+        self.dst_kind = ("aosoa", width or 64) if dst_kind == "aosoa" else (dst_kind, 0)
+        self.narrow = narrow
+        self.dst = self.sp.layout(self.dst_kind[0], 0 if self.auto else self.dst_kind[1], storage=narrow)
+        self.ddst = H.alloc_device(self.dst.lib.buffer_bytes(self.n, self.tot))
+        self.dv = P.View(self.dst.lib, self.n, self.ddst, self.tot)
+
+
+@pytest.mark.parametrize("src", ["aos", "soa", "aosoa"])
+def test_one_source_into_several_layouts(src):
+    """Steps reading the same source tiles are converted from one load of
+    each tile: every destination must still be the oracle's."""
+    schemas = {k: H.SchemaPair(d) for k, d in DECLS.items()}
+    items = []
+    for sname in ("plain8", "cell", "cluster"):
+        base = Item(schemas, dict(schema=sname, n=30_001, src=src, dst="soa" if src != "soa" else "aos"))
+        items.append(base)
+        narrow = H.narrowed_storage(DECLS[sname]) if sname == "cell" else None
+        for dk, w in (("soa", None), ("aosoa", None), ("aosoa", 3), ("aosoa", 128), ("aos", None)):
+            if dk == src:
+                continue
+            items.append(SharedSourceItem(base, dk, narrow=None if dk == "aos" else narrow, width=w))
+    # unrelated collections in the same batch
+    items += [Item(schemas, s, auto_width=True) for s in _small_specs(6, seed=91)]
+    b = Batch()
+    for it in items:
+        b.add(it.sv, it.dv, it.n)
+    b.finalize()
+    for mode in ("graph", "loop"):
+        for it in items:
+            for t in it.ddst:
+                if t is not None:
+                    t.fill_(H.SENTINEL)
+        (b.launch if mode == "graph" else b.loop)()
+        assert P.sync() == 0, P.rl_last_error()
+        _check_against_oracle(items, b)
