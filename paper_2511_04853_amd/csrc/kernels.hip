@@ -50,6 +50,18 @@ __device__ __forceinline__ const RL_C T& cdesc(const T* table, uint64_t i) {
   return ((const RL_C T*)table)[i];
 }
 
+// A kernel's only argument, read in place in the kernel-argument segment
+// like a descriptor table entry.  The empty asm hides that every call
+// yields the same address: the compiler otherwise loads every field the
+// kernel uses into scalar registers at entry and keeps them live across
+// the whole kernel, spilling registers once the code grows.
+template <class T>
+__device__ __forceinline__ const RL_C T& kernel_arg() {
+  const RL_C T* p = (const RL_C T*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *p;
+}
+
 __device__ __forceinline__ uint64_t load_off(const uint8_t* p, uint32_t type, uint64_t i) {
   if (type == RL_U64) return gp(reinterpret_cast<const uint64_t*>(p))[i];
   if (type == RL_I32) return (uint64_t)(int64_t)gp(reinterpret_cast<const int32_t*>(p))[i];
@@ -193,7 +205,7 @@ struct DenseLds {
   uint8_t* src;
   uint8_t* dst;
   uint64_t* wsum;
-  uint64_t* offs;   // staged offsets: [0] = entry 0, [1 + k] = entry i0 + k
+  uint64_t* offs;   // staged offsets: 16 bytes holding entry 0, then raw entries i0 .. i0 + cnt
 };
 
 __host__ __device__ __forceinline__ uint32_t round16(uint32_t x) { return (x + 15u) & ~15u; }
@@ -349,8 +361,9 @@ __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70);
 // DMA wait covers them; the transform reads them with v_readlane and makes
 // no memory access per leaf.
 struct LeafLanes {
-  uint32_t src_off, dst_off;
-  uint32_t code;               // LeafCode | source size << 8 | op << 16
+  uint32_t src_off, dst_off;   // OP_PTR: src_off holds the member record stride
+  uint32_t code;               // LeafCode | source size << 8 | op << 16 | byte_wise << 24
+                               // | offsets rl_type << 25 (OP_PTR / OP_LEN)
   uint32_t col_lo, col_hi;     // SoA destination column
   uint32_t scol_lo, scol_hi;   // SoA source column
   uint32_t item;               // descriptor the lanes hold
@@ -361,9 +374,10 @@ __device__ __forceinline__ void load_lanes(const DD& d, uint32_t item, LeafLanes
   const uint32_t lane = threadIdx.x & 63;
   if (lane < d.n_leaves) {
     const auto& L = d.leaf[lane];
-    t.src_off = L.src_off;
+    t.src_off = L.op == OP_PTR ? (uint32_t)L.mstride : L.src_off;
     t.dst_off = L.dst_off;
-    t.code = (uint32_t)L.code | ((uint32_t)L.src_size << 8) | ((uint32_t)L.op << 16);
+    t.code = (uint32_t)L.code | ((uint32_t)L.src_size << 8) | ((uint32_t)L.op << 16) |
+             ((uint32_t)L.byte_wise << 24) | ((uint32_t)L.off_type << 25);
     const uint64_t col = reinterpret_cast<uint64_t>(L.dst_col);
     t.col_lo = (uint32_t)col;
     t.col_hi = (uint32_t)(col >> 32);
@@ -381,8 +395,8 @@ __device__ __forceinline__ uint32_t lane_of(uint32_t v, uint32_t c) {
 // Start bringing a tile's source image into LDS: by DMA when every run is
 // 16-byte aligned, else through registers (complete on return).
 template <class DD>
-__device__ __forceinline__ void issue_source(const DD& d, uint8_t* img, const TileJob& j, const LeafLanes& lt,
-                                             bool lanes_ready) {
+__device__ __forceinline__ void issue_image(const DD& d, uint8_t* img, const TileJob& j, const LeafLanes& lt,
+                                            bool lanes_ready) {
   const uint64_t i0 = j.tile * d.tile;
   const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, j.count - i0);
   const uint64_t idx0 = i0 + j.base;
@@ -404,7 +418,7 @@ __device__ __forceinline__ void issue_source(const DD& d, uint8_t* img, const Ti
       if (lanes_ready) {
         for (uint32_t c = 0; c < nl; ++c) {
           const uint32_t w = lane_of(lt.code, c);
-          const uint32_t op = w >> 16, sz = (w >> 8) & 255;
+          const uint32_t op = (w >> 16) & 255, sz = (w >> 8) & 255;
           if (op == OP_PTR || op == OP_LEN) continue;
           const uint8_t* col =
               reinterpret_cast<const uint8_t*>(((uint64_t)lane_of(lt.scol_hi, c) << 32) | lane_of(lt.scol_lo, c));
@@ -421,6 +435,42 @@ __device__ __forceinline__ void issue_source(const DD& d, uint8_t* img, const Ti
     }
   }
   load_side(d, img, idx0, cnt, cnt == d.tile && j.base == 0);
+}
+
+__device__ __forceinline__ uint32_t off_bytes(uint32_t type) { return type == RL_U64 ? 8u : 4u; }
+
+// Entry k of a raw offsets run staged in LDS.
+__device__ __forceinline__ uint64_t staged_off(const uint8_t* run, uint32_t type, uint32_t k) {
+  if (type == RL_U64) return reinterpret_cast<const uint64_t*>(run)[k];
+  if (type == RL_I32) return (uint64_t)(int64_t)reinterpret_cast<const int32_t*>(run)[k];
+  return reinterpret_cast<const uint32_t*>(run)[k];
+}
+
+// A tile's source image plus, for destination records of a jagged group,
+// the raw offsets entries i0 .. i0 + cnt and the column's first 16 bytes
+// (entry 0), which travel with the image: by DMA when the column is
+// 16-byte aligned, whole vectors while they stay inside the column's
+// n + 1 entries.  LDS holds entry 0's vector, then the run.
+template <class DD>
+__device__ __forceinline__ void issue_source(const DD& d, uint8_t* smem, const TileJob& j, const LeafLanes& lt,
+                                             bool lanes_ready) {
+  issue_image(d, smem, j, lt, lanes_ready);
+  if (!d.stage_offsets) return;
+  const uint64_t i0 = j.tile * d.tile;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, j.count - i0);
+  const uint32_t es = off_bytes(d.stage_type);
+  const uint8_t* g = d.stage_offsets + i0 * es;
+  uint8_t* head = reinterpret_cast<uint8_t*>(carve(smem, d).offs);
+  const uint32_t need = (cnt + 1) * es;
+  const uint64_t column = (d.n + 1) * es;
+  if (d.dma && ((uintptr_t)g & 15) == 0) {
+    const uint32_t up = round16(need);
+    dma_run(head, d.stage_offsets, column >= 16 ? 16u : es);
+    dma_run(head + 16, g, (uint64_t)up <= column - i0 * es ? up : need);
+  } else {
+    g2l(head, d.stage_offsets, es, threadIdx.x, blockDim.x);
+    g2l(head + 16, g, need, threadIdx.x, blockDim.x);
+  }
 }
 
 // Fused local scan of jagged counts held in the source records: writes the
@@ -535,41 +585,78 @@ __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, c
 }
 
 // Leaves at misaligned image addresses and destination record (pointer,
-// count) pairs: one object per thread, generic address arithmetic.
+// count) pairs: one object per thread, generic address arithmetic.  Which
+// leaves take this path, and the (pointer, count) fields, come from the
+// wave's leaf lanes.  `run` holds the staged offsets entries i0 .. i0 + cnt
+// of d.stage_offsets, whose entry 0 is `first`.
 template <class DD>
-__device__ __forceinline__ void transform_slow(const DD& d, uint8_t* src_img, uint8_t* dst_img, const uint64_t* offs,
-                                            uint64_t i0, uint32_t cnt) {
-  for (uint32_t c = 0; c < d.n_leaves; ++c) {
-    const auto& L = d.leaf[c];
-    if (L.code < CODE_BYTES) continue;
-    for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) {
-      uint32_t sa, sb, da, db;
-      if (d.src.kind == KIND_AOS) obj_terms<KIND_AOS>(d.src, o, sa, sb);
-      else if (d.src.kind == KIND_SOA) obj_terms<KIND_SOA>(d.src, o, sa, sb);
-      else obj_terms<KIND_AOSOA>(d.src, o, sa, sb);
-      if (d.dst.kind == KIND_AOS) obj_terms<KIND_AOS>(d.dst, o, da, db);
-      else if (d.dst.kind == KIND_SOA) obj_terms<KIND_SOA>(d.dst, o, da, db);
-      else obj_terms<KIND_AOSOA>(d.dst, o, da, db);
-      uint8_t* dp = dst_img + da + L.dst_off + db * L.dst_size;
-      if (L.code == CODE_BYTES) {
-        move_value(dp, src_img + sa + L.src_off + sb * L.src_size, L);
-        continue;
+__device__ __forceinline__ void transform_slow(const DD& d, const LeafLanes& lt, uint8_t* src_img, uint8_t* dst_img,
+                                               const uint8_t* run, uint64_t first, uint64_t i0, uint32_t cnt) {
+  const uint32_t nl = d.n_leaves;
+  for (uint32_t c = 0; c < nl; ++c) {
+    const uint32_t w = lane_of(lt.code, c);
+    const uint32_t code = w & 255;
+    if (code < CODE_BYTES) continue;
+    if (code == CODE_BYTES) {
+      const auto& L = d.leaf[c];
+      for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) {
+        uint32_t sa, sb, da, db;
+        if (d.src.kind == KIND_AOS) obj_terms<KIND_AOS>(d.src, o, sa, sb);
+        else if (d.src.kind == KIND_SOA) obj_terms<KIND_SOA>(d.src, o, sa, sb);
+        else obj_terms<KIND_AOSOA>(d.src, o, sa, sb);
+        if (d.dst.kind == KIND_AOS) obj_terms<KIND_AOS>(d.dst, o, da, db);
+        else if (d.dst.kind == KIND_SOA) obj_terms<KIND_SOA>(d.dst, o, da, db);
+        else obj_terms<KIND_AOSOA>(d.dst, o, da, db);
+        move_value(dst_img + da + L.dst_off + db * L.dst_size, src_img + sa + L.src_off + sb * L.src_size, L);
       }
-      // destination record (pointer, count) from the source offsets
-      const uint64_t i = i0 + o;
-      const bool staged = L.src_col == d.stage_offsets;
-      const uint64_t first = staged ? offs[0] : load_off(L.src_col, L.off_type, 0);
-      const uint64_t a = staged ? offs[1 + o] : load_off(L.src_col, L.off_type, i);
-      if (L.code == CODE_PTR) {
-        const uint64_t v = (a - first) * (uint64_t)L.mstride;
-        if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 8);
+      continue;
+    }
+    // destination record (pointer, count) from the source offsets: the
+    // destination is a record image
+    const uint32_t dof = lane_of(lt.dst_off, c), stride = d.dst.stride;
+    const bool byte_wise = (w >> 24) & 1;
+    const uint32_t ot = (w >> 25) & 15;
+    const uint8_t* col =
+        reinterpret_cast<const uint8_t*>(((uint64_t)lane_of(lt.scol_hi, c) << 32) | lane_of(lt.scol_lo, c));
+    const bool staged = col == d.stage_offsets;
+    const uint64_t f = staged ? first : load_off(col, ot, 0);
+    const uint64_t ms = lane_of(lt.src_off, c);
+    for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) {
+      uint8_t* dp = dst_img + o * stride + dof;
+      const uint64_t a = staged ? staged_off(run, ot, o) : load_off(col, ot, i0 + o);
+      if (code == CODE_PTR) {
+        const uint64_t v = (a - f) * ms;
+        if (byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 8);
         else *reinterpret_cast<uint64_t*>(dp) = v;
       } else {
-        const uint32_t v = (uint32_t)((staged ? offs[2 + o] : load_off(L.src_col, L.off_type, i + 1)) - a);
-        if (L.byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 4);
+        const uint32_t v = (uint32_t)((staged ? staged_off(run, ot, o + 1) : load_off(col, ot, i0 + o + 1)) - a);
+        if (byte_wise) copy_bytes(dp, reinterpret_cast<const uint8_t*>(&v), 4);
         else *reinterpret_cast<uint32_t*>(dp) = v;
       }
     }
+  }
+}
+
+// Checks of the staged offsets of a tile: non-decreasing and inside the
+// source member capacity for every object, and (last tile) the total
+// inside the destination member capacity.  Status flags as the offsets
+// pass sets them.
+template <class DD>
+__device__ __forceinline__ void check_staged(const DD& d, const uint8_t* run, uint64_t first, uint64_t i0,
+                                             uint32_t cnt) {
+  const uint32_t ot = d.stage_type;
+  const uint64_t cap = d.stage_src_capacity;
+  bool overflow = false, bounds = false;
+  for (uint32_t o = threadIdx.x; o < cnt; o += blockDim.x) {
+    const uint64_t a = staged_off(run, ot, o), b = staged_off(run, ot, o + 1);
+    if (b < a) overflow = true;
+    else if (a > cap || b - a > cap - a) bounds = true;
+  }
+  if (overflow) flag(d.status, ST_FLAG_OVERFLOW);
+  if (bounds) flag(d.status, ST_FLAG_BOUNDS);
+  if (i0 + cnt == d.n && threadIdx.x == 0) {
+    const uint64_t a = staged_off(run, ot, cnt);
+    if (a >= first && a - first > d.stage_dst_capacity) flag(d.status, ST_FLAG_CAPACITY);
   }
 }
 
@@ -631,14 +718,10 @@ __device__ __forceinline__ void transform_tile(const DD& d, const DenseLds& m, c
     return;
   }
   if (d.slow_leaves) {
-    if (d.stage_offsets) {
-      // the tile's offsets (and entry 0) in LDS: one round trip per tile
-      // instead of dependent global loads per object
-      for (uint32_t k = threadIdx.x; k <= cnt + 1; k += blockDim.x)
-        m.offs[k] = load_off(d.stage_offsets, d.stage_type, k == 0 ? 0 : i0 + k - 1);
-      __syncthreads();
-    }
-    transform_slow(d, m.src, m.dst, m.offs, i0, cnt);
+    const uint8_t* run = reinterpret_cast<const uint8_t*>(m.offs) + 16;
+    const uint64_t first = d.stage_offsets ? staged_off(run - 16, d.stage_type, 0) : 0;
+    if (d.stage_offsets) check_staged(d, run, first, i0, cnt);
+    transform_slow(d, lt, m.src, m.dst, run, first, i0, cnt);
   }
   switch (d.src.kind * 3 + d.dst.kind) {
     case KIND_AOS * 3 + KIND_AOS: transform_kinds<KIND_AOS, KIND_AOS, false>(d, m, lt, i0, cnt); break;
@@ -718,13 +801,14 @@ struct StridedTiles {
   }
 };
 
-__global__ void __launch_bounds__(256, 7) dense_kernel(const DenseDesc d) {
+__global__ void __launch_bounds__(256, 7) dense_kernel(const DenseDesc) {
   extern __shared__ uint4 smem_raw[];
+  const RL_C DenseDesc& d = kernel_arg<DenseDesc>();
   uint64_t count, base;
   dense_count(d, &count, &base);
   dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw),
                  StridedTiles{blockIdx.x, (count + d.tile - 1) / d.tile, count, base},
-                 [&](uint32_t) -> const DenseDesc& { return d; });
+                 [&](uint32_t) -> const RL_C DenseDesc& { return kernel_arg<DenseDesc>(); });
 }
 
 // ------------------------------------------------------------------ offsets
@@ -905,7 +989,7 @@ __device__ __forceinline__ void gather_words(const GD& d, const uint64_t* offs, 
 // count) are staged in LDS; every pool read stays inside the member block
 // the record validated (vlen).
 template <class GD>
-__device__ void gather_sub(const GD& d, uint64_t u, uint8_t* smem) {
+__device__ __forceinline__ void gather_sub(const GD& d, uint64_t u, uint8_t* smem) {
   const uint32_t S = d.sub;
   uint64_t* offs = reinterpret_cast<uint64_t*>(smem);   // S + 1
   uint64_t* ptrs = offs + (S + 1);                      // S
@@ -955,10 +1039,12 @@ __device__ void gather_sub(const GD& d, uint64_t u, uint8_t* smem) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) gather_kernel(const GatherDesc d) {
+__global__ void __launch_bounds__(256) gather_kernel(const GatherDesc) {
   extern __shared__ uint4 smem_raw[];
+  const RL_C GatherDesc& d = kernel_arg<GatherDesc>();
   const uint64_t nsub = (d.n + d.sub - 1) / d.sub;
-  for (uint64_t u = blockIdx.x; u < nsub; u += gridDim.x) gather_sub(d, u, reinterpret_cast<uint8_t*>(smem_raw));
+  for (uint64_t u = blockIdx.x; u < nsub; u += gridDim.x)
+    gather_sub(kernel_arg<GatherDesc>(), u, reinterpret_cast<uint8_t*>(smem_raw));
 }
 
 // Offsets column -> offsets column, rebased to start at 0, with the checks
@@ -1090,7 +1176,7 @@ __global__ void __launch_bounds__(256) batch_gather_kernel(const BatchTables b) 
 
 uint32_t dense_lds_bytes(const DenseDesc& d) {
   return round16(d.src.image_bytes) + (d.dst_direct ? 0u : round16(d.dst.image_bytes)) +
-         round16(17 * sizeof(uint64_t)) + (d.stage_offsets ? (d.tile + 2) * 8 : 0u);
+         round16(17 * sizeof(uint64_t)) + (d.stage_offsets ? (d.tile + 4) * 8 : 0u);
 }
 
 uint64_t dense_tiles(const DenseDesc& d) { return (d.n + d.tile - 1) / d.tile; }

@@ -324,6 +324,8 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
     if (ng == 1) {
       dd.stage_offsets = (const uint8_t*)src.buffers[group_buffer(SL, 0)];
       dd.stage_type = (uint32_t)sc->offset_types[0];
+      dd.stage_src_capacity = src.member_capacity[0];
+      dd.stage_dst_capacity = dst.member_capacity[0];
     }
     for (uint32_t g = 0; g < ng; ++g) {
       const rl_type ot = sc->offset_types[g];
@@ -360,13 +362,16 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
       continue;
     }
     // offsets-column source: check (and, for an offsets destination, copy
-    // rebased), then move the member values
-    Step r;
-    r.kind = Step::REBASE;
-    r.rebase = RebaseDesc{(const uint8_t*)src.buffers[group_buffer(SL, g)],
-                          DL->kind == RL_AOS ? nullptr : (uint8_t*)dst.buffers[group_buffer(DL, g)],
-                          n, (uint32_t)ot, src.member_capacity[g], dst.member_capacity[g], status};
-    plan->steps.push_back(r);
+    // rebased), then move the member values.  The records kernel checks
+    // the offsets it stages, so a single group into records needs no pass.
+    if (!dd.stage_offsets) {
+      Step r;
+      r.kind = Step::REBASE;
+      r.rebase = RebaseDesc{(const uint8_t*)src.buffers[group_buffer(SL, g)],
+                            DL->kind == RL_AOS ? nullptr : (uint8_t*)dst.buffers[group_buffer(DL, g)],
+                            n, (uint32_t)ot, src.member_capacity[g], dst.member_capacity[g], status};
+      plan->steps.push_back(r);
+    }
     SideSpec ms = member_side(SL, src.buffers, g);
     SideSpec md = member_side(DL, dst.buffers, g);
     const uint32_t mt = choose_tile(ms, md, shape.tile, dst.member_capacity[g]);

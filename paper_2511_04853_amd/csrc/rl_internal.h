@@ -105,9 +105,13 @@ struct DenseDesc {
   uint64_t src_capacity;   // with count_offsets: source member capacity (count <= it - base)
   // Offsets column staged in LDS per tile for the record (pointer, count)
   // leaves of an AoS destination (null: read from global memory per object).
+  // The kernel that stages them also checks them (non-decreasing, inside
+  // the source member capacity, total inside the destination's).
   const uint8_t* stage_offsets;
   uint32_t stage_type;     // rl_type of stage_offsets
   uint32_t pad2;
+  uint64_t stage_src_capacity;
+  uint64_t stage_dst_capacity;
   LeafDesc leaf[kMaxLeaves];
   uint8_t unit_src[kMaxUnits];   // SoA image: byte unit of object size -> leaf
   uint8_t unit_dst[kMaxUnits];

@@ -257,6 +257,54 @@ def test_offset_overflow_is_reported():
     assert P.sync() == P.RL_OK
 
 
+def _soa_offsets_src(n):
+    """A cluster collection as SoA columns + u32 offsets (buffer 6), and its
+    member total."""
+    sp, v, aos, soa, src = _cluster_src(n=n)
+    tot = v.total(0)
+    st, sbufs, _ = H.oracle_convert(aos, src, soa, v.n, [tot], [tot])
+    assert st == 0
+    return v, aos, soa, sbufs, tot
+
+
+_ORACLE_TO_RL = {oracle.ST_OVERFLOW: "RL_EOVERFLOW", oracle.ST_BOUNDS: "RL_EBOUNDS", oracle.ST_CAPACITY: "RL_ECAPACITY"}
+
+
+@pytest.mark.parametrize("n", [300, 5000])
+@pytest.mark.parametrize("case", ["decreasing_at_tile_edge", "decreasing_last", "past_source", "past_destination"])
+def test_offsets_source_checks_into_records(n, case):
+    """Offsets columns into (pointer, count) records: the records kernel
+    checks the offsets it stages (non-decreasing, inside the source member
+    storage, total inside the destination pool), with the oracle's status."""
+    v, aos, soa, sbufs, tot = _soa_offsets_src(n)
+    bad = [b.copy() for b in sbufs]
+    off = bad[6].view(np.uint32)
+    scap, dcap = tot, tot
+    if case == "decreasing_at_tile_edge":
+        off[128] = off[127] - 1
+    elif case == "decreasing_last":
+        off[n] = off[n - 1] - 1
+    elif case == "past_source":
+        off[n] = tot + 50
+        dcap = tot + 100
+    else:
+        dcap = tot - 1
+    st, _, _ = H.oracle_convert(soa, bad, aos, n, [scap], [dcap])
+    assert st in _ORACLE_TO_RL, st
+    rc, rs, _ = H.run_lib_convert(soa, bad, aos, n, [scap], [dcap])
+    assert rc == P.RL_OK and rs == getattr(P, _ORACLE_TO_RL[st]), (case, st, rs)
+    assert P.sync() == P.RL_OK
+
+
+def test_offsets_source_into_records_well_formed_is_clean():
+    v, aos, soa, sbufs, tot = _soa_offsets_src(5000)
+    st, want, _ = H.oracle_convert(soa, sbufs, aos, v.n, [tot], [tot])
+    assert st == 0
+    rc, rs, got = H.run_lib_convert(soa, sbufs, aos, v.n, [tot], [tot])
+    assert rc == P.RL_OK and rs == P.RL_OK
+    H.assert_same_bytes(got, want, "offsets -> records")
+
+
 # ------------------------------------------------------------------ offsets alone
 
 @pytest.mark.parametrize("n", [1, 1023, 1024, 1025, 50_000, 300_001])
