@@ -51,6 +51,7 @@ struct Config {
   uint32_t tile = 256, threads = 128, width = 64;   // threads: dense work-groups
   uint32_t grid = 0;     // dense work-groups; 0: as many as fit on the device at once
   uint32_t direct = 0;   // 1: launch the batch kernels directly instead of replaying the graph
+  uint32_t gather_threads = kGatherThreads;   // member-gather work-groups
 };
 
 struct DeviceTables {
@@ -267,7 +268,7 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
 
 rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s) {
   const uint32_t dt = std::min<uint32_t>(c.threads, kDenseMaxThreads);
-  hipError_t e = launch_batch(d.t, dt, kGatherThreads, c.grid, d.dense_lds, d.gather_lds, s);
+  hipError_t e = launch_batch(d.t, dt, c.gather_threads, c.grid, d.dense_lds, d.gather_lds, s);
   return e == hipSuccess ? RL_OK : hip_fail(e, "batch launch");
 }
 
@@ -319,6 +320,7 @@ bool cache_lookup(const std::string& path, const std::string& sig, Config* c) {
     Config t;
     if (num("tile", &t.tile) && num("threads", &t.threads) && num("grid", &t.grid) && num("width", &t.width)) {
       num("direct", &t.direct);
+      num("gather_threads", &t.gather_threads);
       *c = t;
       return true;
     }
@@ -340,8 +342,9 @@ void cache_store(const std::string& path, const std::string& sig, const Config& 
   }
   char buf[256];
   snprintf(buf, sizeof buf,
-           "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"direct\":%u, \"us\":%.2f}",
-           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, us);
+           "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"direct\":%u, "
+           "\"gather_threads\":%u, \"us\":%.2f}",
+           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, c.gather_threads, us);
   keep.push_back(buf);
   std::ofstream o(path + ".tmp");
   o << "{\n";
@@ -398,6 +401,17 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
         if (st) return st;
         if (us < best_us) { best_us = us; bc = c; }
       }
+  // member gathers: one-wave work-groups keep more sub-tiles in flight,
+  // larger ones fewer instructions per member
+  if (std::any_of(b->items.begin(), b->items.end(), [](const Item& i) { return !i.src_layout->schema->members.empty(); }))
+    for (uint32_t gt : {64u, 256u}) {
+      Config c = bc;
+      c.gather_threads = gt;
+      double us;
+      rl_status st = time_config(b, c, s, &us);
+      if (st) return st;
+      if (us < best_us * 0.98) { best_us = us; bc = c; }
+    }
   if (any_auto)
     for (uint32_t w : kAutoWidths) {
       Config c = bc;
@@ -422,7 +436,7 @@ rl_status choose_launch(rl_batch* b, hipStream_t s) {
   for (int mode = 0; mode < 2; ++mode) {
     for (int k = 0; k < reps + 2; ++k) {
       if (k == 2) (void)hipEventRecord(e0, s);
-      hipError_t e = mode == 0 ? hipGraphLaunch(b->exec, s) : launch_batch(b->dev.t, std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads), kGatherThreads, b->cfg.grid, b->dev.dense_lds,
+      hipError_t e = mode == 0 ? hipGraphLaunch(b->exec, s) : launch_batch(b->dev.t, std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads), b->cfg.gather_threads, b->cfg.grid, b->dev.dense_lds,
                                  b->dev.gather_lds, s);
       if (e != hipSuccess) return hip_fail(e, "tuning launch");
     }
@@ -499,7 +513,9 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (const char* v = getenv("RL_BATCH_TILE")) c.tile = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_GRID")) c.grid = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_THREADS")) c.threads = (uint32_t)strtoul(v, nullptr, 10);
+  if (const char* v = getenv("RL_BATCH_GATHER_THREADS")) c.gather_threads = (uint32_t)strtoul(v, nullptr, 10);
   if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 128;
+  if (c.gather_threads < 64 || c.gather_threads > 256 || c.gather_threads % 64) c.gather_threads = kGatherThreads;
 
   b->cfg = c;
   rl_status st = resolve_widths(b, c.width);

@@ -238,6 +238,7 @@ def test_autotune_writes_and_reuses_cache(tmp_path):
     # grid 0 in the cache means "as many work-groups as fit at once"; the
     # shape reports the work-groups launched (at most one per tile)
     assert shape[2] > 0 and (entry["grid"] == 0 or entry["grid"] >= shape[2])
+    assert entry["gather_threads"] in (64, 128, 256)
     # a second batch of the same shape takes the cached choice
     items2 = [Item(schemas, s, auto_width=True) for s in specs]
     b2 = Batch(autotune=0, cache=cache)
@@ -249,6 +250,24 @@ def test_autotune_writes_and_reuses_cache(tmp_path):
     b2.launch()
     assert P.sync() == 0
     _check_against_oracle(items2, b2)
+
+
+@pytest.mark.parametrize("gather_threads", [64, 256])
+def test_member_gather_work_group_sizes(gather_threads, monkeypatch):
+    """The member gather of a batch at each work-group size the tuner may
+    pick, against the oracle."""
+    monkeypatch.setenv("RL_BATCH_GATHER_THREADS", str(gather_threads))
+    schemas = {k: H.SchemaPair(d) for k, d in DECLS.items()}
+    specs = _small_specs(12, seed=7)
+    assert any(s["schema"] == "cluster" and s["src"] == "aos" for s in specs)   # member gathers
+    items = [Item(schemas, s) for s in specs]
+    b = Batch()
+    for it in items:
+        b.add(it.sv, it.dv, it.n)
+    b.finalize()
+    b.launch()
+    assert P.sync() == 0
+    _check_against_oracle(items, b)
 
 
 class SharedSourceItem(Item):
