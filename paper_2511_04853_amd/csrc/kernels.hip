@@ -556,7 +556,7 @@ __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, c
   // Destination: the LDS image, or (DIRECT) the tile's place in global
   // memory -- AoSoA: the tile's first block, whose runs sit at the image
   // offsets; SoA: each column at the tile's first object.
-  uint8_t* const Dtile = DIRECT ? d.dst.base + i0 * d.dst.obj_bytes : m.dst;
+  uint8_t* const Dtile = DIRECT ? d.dst.base + i0 * (DK == KIND_AOS ? d.dst.stride : d.dst.obj_bytes) : m.dst;
 #define RL_MOVE(ST, DT, SS, DS, EXPR)                                                  \
   _Pragma("unroll") for (uint32_t k = 0; k < P; ++k) {                                 \
     if (FULL || ok[k]) {                                                               \
@@ -706,6 +706,8 @@ __device__ __forceinline__ void transform_direct(const DD& d, const DenseLds& m,
     case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true>(d, m, lt, i0, cnt); break;
     case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
     case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true>(d, m, lt, i0, cnt); break;
+    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, true>(d, m, lt, i0, cnt); break;
+    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, true>(d, m, lt, i0, cnt); break;
     default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
   }
 }

@@ -63,6 +63,24 @@ def test_dense_pairs(decl, src_kind, dst_kind):
     _check(decl, src_kind, dst_kind, 1037, seed=1)
 
 
+# Records of at most 8 bytes without gaps are written straight from the
+# source image (no destination image); wider ones keep the image.
+_SMALL_RECORDS = [
+    W.SchemaDecl("u32", (W.Field("a", "u32"),)),
+    W.SchemaDecl("u32_f32", (W.Field("i", "u32"), W.Field("w", "f32"))),
+    W.SchemaDecl("u16_u16_u32", (W.Field("p", "u16"), W.Field("q", "u16"), W.Field("r", "u32"))),
+    W.SchemaDecl("u64", (W.Field("c", "u64"),)),
+    W.SchemaDecl("u8x4_f32", (W.Field("b", "u8", extent=4), W.Field("x", "f32"))),
+]
+
+
+@pytest.mark.parametrize("decl", _SMALL_RECORDS, ids=lambda d: d.name)
+@pytest.mark.parametrize("src_kind", [("soa", 0), ("aosoa", 1), ("aosoa", 3), ("aosoa", 64)], ids=str)
+@pytest.mark.parametrize("n", [1, 1000, 70_001])
+def test_small_records_from_columns(decl, src_kind, n):
+    _check(decl, src_kind, ("aos", 0), n, seed=n)
+
+
 @pytest.mark.parametrize("decl", [W.CLUSTER, W.PARTICLE], ids=lambda d: d.name)
 @pytest.mark.parametrize("pair", [(("aos", 0), ("soa", 0)), (("aos", 0), ("aosoa", 32)),
                                   (("soa", 0), ("aos", 0)), (("aosoa", 64), ("aos", 0)),
