@@ -432,9 +432,35 @@ def plain_round_trip(P, W, torch, stream, sets=64):
     return {"objects": n, "us_per_round_trip": round(ms * 1e3, 2), "GBps": round(by / (ms * 1e-3) / 1e9, 1)}
 
 
+def _shuffle_pool(torch, rec, pool, offs, n, stride, g):
+    """The same collection with its member blocks in a random order in the
+    pool: records' byte pointers updated (the pointer field is found as the
+    8-byte slot holding 8 * offsets of the canonical pool)."""
+    lens = offs[1:] - offs[:-1]
+    tot = int(offs[-1].item())
+    r = rec.view(n, stride)
+    ptr_off = None
+    for o in range(0, stride - 7, 8):
+        if torch.equal(r[:, o:o + 8].contiguous().view(torch.int64).view(-1), offs[:-1] * 8):
+            ptr_off = o
+            break
+    assert ptr_off is not None, "no pointer field in the records"
+    order = torch.randperm(n, device="cuda", generator=g)
+    start = torch.zeros(n, dtype=torch.int64, device="cuda")
+    start[order] = torch.cumsum(lens[order], 0) - lens[order]
+    owner = torch.repeat_interleave(torch.arange(n, device="cuda"), lens)
+    j = torch.arange(tot, device="cuda") - offs[:-1][owner]
+    new_pool = torch.empty_like(pool)
+    new_pool.view(-1, 8)[start[owner] + j] = pool.view(-1, 8)[:tot]
+    new_rec = rec.clone()
+    new_rec.view(n, stride)[:, ptr_off:ptr_off + 8] = (start * 8).view(torch.uint8).view(n, 8)
+    return new_rec, new_pool
+
+
 def jagged(P, W, torch, stream, sets=8):
     """50,000 clusters with Poisson(40) (index, weight) members: AoS records
-    + shuffled-free pool -> SoA + offsets (scan + gather), and back."""
+    + pool -> SoA + offsets (scan + gather), and back.  Forward from pools
+    whose member blocks are shuffled, and from pools in object order."""
     S = P.Schema(W.CLUSTER)
     aos, soa = P.Layout(S, "aos"), P.Layout(S, "soa")
     n = 50_000
@@ -454,16 +480,31 @@ def jagged(P, W, torch, stream, sets=8):
         av = P.View(aos, n, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in aos.buffer_bytes(n, [tot])],
                     [tot])
         P.convert(sv, av, n)
+        assert P.sync(stream) == 0
+        rec_s, pool_s = _shuffle_pool(torch, av.tensors[0], av.tensors[1], offs, n,
+                                      aos.buffer_bytes(1, [0])[0], g)
+        avs = P.View(aos, n, [rec_s, pool_s], [tot])
         dv = P.View(soa, n, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in soa.buffer_bytes(n, [tot])],
                     [tot])
-        vals.append((av, dv, tot))
+        if r == 0:   # both pools give the same columns
+            dv2 = P.View(soa, n, [torch.empty(x, dtype=torch.uint8, device="cuda")
+                                  for x in soa.buffer_bytes(n, [tot])], [tot])
+            P.convert(av, dv, n)
+            P.convert(avs, dv2, n)
+            assert P.sync(stream) == 0
+            assert all(torch.equal(a, b) for a, b in zip(dv.tensors, dv2.tensors)), "shuffled pool differs"
+            del dv2
+        vals.append((av, dv, tot, avs))
     assert P.sync(stream) == 0
+    fwd_s = _time(lambda k=0: lib.rl_convert(vals[k % sets][3].ref(), vals[k % sets][1].ref(), n, sp), stream, torch)
     fwd = _time(lambda k=0: lib.rl_convert(vals[k % sets][0].ref(), vals[k % sets][1].ref(), n, sp), stream, torch)
     rev = _time(lambda k=0: lib.rl_convert(vals[k % sets][1].ref(), vals[k % sets][0].ref(), n, sp), stream, torch)
     assert P.sync(stream) == 0
     tot = int(np.mean([v[2] for v in vals]))
     by = sum(aos.buffer_bytes(n, [tot])) + sum(soa.buffer_bytes(n, [tot]))
     return {"objects": n, "members": tot, "bytes_each_way": by,
+            "forward_shuffled_pool_us": round(fwd_s * 1e3, 2),
+            "forward_shuffled_pool_GBps": round(by / (fwd_s * 1e-3) / 1e9, 1),
             "forward_us": round(fwd * 1e3, 2), "forward_GBps": round(by / (fwd * 1e-3) / 1e9, 1),
             "reverse_us": round(rev * 1e3, 2), "reverse_GBps": round(by / (rev * 1e-3) / 1e9, 1)}
 
