@@ -509,7 +509,7 @@ def jagged(P, W, torch, stream, sets=8):
             "reverse_us": round(rev * 1e3, 2), "reverse_GBps": round(by / (rev * 1e-3) / 1e9, 1)}
 
 
-def serving(P, W, torch, stream, rates=(1000, 3000), n_events=3000, hold=512, pool_events=64):
+def serving(P, W, torch, stream, rates=(1000, 3000), n_events=10_000, hold=512, pool_events=64, warmup=1000):
     """Open-loop Poisson arrivals; each event one collection per schema
     (plain / cell / cluster, log-normal sizes with medians 10k / 100k / 20k,
     sigma 0.5) in pinned host AoS memory; converted into device SoA under a
@@ -557,7 +557,7 @@ def serving(P, W, torch, stream, rates=(1000, 3000), n_events=3000, hold=512, po
     ev_bytes = [sum(sum(v.layout.buffer_bytes(n, list(v._mcap)[:1] if v.layout.schema.n_groups else []))
                     for v, _, n in items) for items in events]
     res = {"event_pool": pool_events, "mean_event_h2d_MB": round(float(np.mean(ev_bytes)) / 1e6, 2),
-           "budget_GiB": 16, "hold": hold, "warmup_events": 500}
+           "budget_GiB": 16, "hold": hold, "warmup_events": warmup}
     # one server for the whole leg; a warm-up run first takes the first-use
     # costs (per-stream staging buffers, pool pages) out of the measurement
     srv = P.Server(16 << 30, max_in_flight=32, n_streams=8)
@@ -615,7 +615,7 @@ def serving(P, W, torch, stream, rates=(1000, 3000), n_events=3000, hold=512, po
                 "events_per_s": round(count / span, 1),
                 "link_GBps": round(count * float(np.mean(ev_bytes)) / span / 1e9, 2)}
 
-    run(1000, 500, seed=2004)   # warm-up
+    run(1000, warmup, seed=2004)   # warm-up (1 s at 1,000 events/s)
     for rate in rates:
         res[f"{rate}/s"] = run(rate, n_events, seed=1004 + rate)
     st = srv.stats()
