@@ -618,6 +618,10 @@ def serving(P, W, torch, stream, rates=(1000, 3000), n_events=10_000, hold=512, 
     run(1000, warmup, seed=2004)   # warm-up (1 s at 1,000 events/s)
     for rate in rates:
         res[f"{rate}/s"] = run(rate, n_events, seed=1004 + rate)
+    # offered load above the host link's rate: throughput saturates there
+    # (latency then grows with the queue, so only the rates are reported)
+    sat = run(6000, n_events, seed=1004 + 6000)
+    res["saturation_offered_6000/s"] = {"events_per_s": sat["events_per_s"], "link_GBps": sat["link_GBps"]}
     st = srv.stats()
     res["peak_resident_GB"] = round(st["peak_bytes"] / 1e9, 3)
     srv.close()
