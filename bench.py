@@ -65,7 +65,7 @@ def main():
         sys.exit(2)
     import torch
     import paper_2511_04853_amd as P
-    from paper_2511_04853_amd import workloads as W
+    import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)

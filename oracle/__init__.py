@@ -43,7 +43,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from paper_2511_04853_amd.workloads import NP_DTYPE, TYPE_CODES, TYPE_SIZE, SchemaDecl, Values
+from workloads import NP_DTYPE, TYPE_CODES, TYPE_SIZE, SchemaDecl, Values
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")

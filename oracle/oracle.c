@@ -66,6 +66,20 @@ static unsigned char* leaf_addr(const or_objects* L, uint32_t c, uint64_t i) {
   }
 }
 
+/* A NaN keeps its sign and the leading bits of its payload through a change
+   of precision and comes out quiet (the quiet bit is the payload's leading
+   bit in both formats).  Built from the bit fields, so the result does not
+   depend on how the host's conversion instructions treat NaNs. */
+static uint32_t nan_to_f32(uint64_t b) {
+  return (uint32_t)((b >> 63) << 31) | 0x7FC00000u
+         | (uint32_t)((b & 0x000FFFFFFFFFFFFFull) >> 29);
+}
+
+static uint64_t nan_to_f64(uint32_t b) {
+  return ((uint64_t)(b >> 31) << 63) | 0x7FF8000000000000ull
+         | ((uint64_t)(b & 0x007FFFFFu) << 29);
+}
+
 /* One value: copy, narrow (f64 -> f32) or widen (f32 -> f64). */
 static int move_value(int32_t st, const unsigned char* s, int32_t dt, unsigned char* d) {
   if (st == dt) {
@@ -75,6 +89,13 @@ static int move_value(int32_t st, const unsigned char* s, int32_t dt, unsigned c
   if (st == T_F64 && dt == T_F32) {
     double x; float y;
     memcpy(&x, s, 8);
+    if (x != x) {
+      uint64_t b; uint32_t r;
+      memcpy(&b, s, 8);
+      r = nan_to_f32(b);
+      memcpy(d, &r, 4);
+      return ST_OK;
+    }
     y = (float)x;
     memcpy(d, &y, 4);
     return ST_OK;
@@ -82,6 +103,13 @@ static int move_value(int32_t st, const unsigned char* s, int32_t dt, unsigned c
   if (st == T_F32 && dt == T_F64) {
     float x; double y;
     memcpy(&x, s, 4);
+    if (x != x) {
+      uint32_t b; uint64_t r;
+      memcpy(&b, s, 4);
+      r = nan_to_f64(b);
+      memcpy(d, &r, 8);
+      return ST_OK;
+    }
     y = (double)x;
     memcpy(d, &y, 8);
     return ST_OK;

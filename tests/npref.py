@@ -3,7 +3,7 @@ numpy's own structured-dtype rules, and block views built by reshaping.
 None of this is used by the oracle or by the library."""
 import numpy as np
 
-from paper_2511_04853_amd.workloads import NP_DTYPE
+from workloads import NP_DTYPE
 
 
 def record_dtype(decl, align=True):

@@ -4,7 +4,7 @@ import numpy as np
 
 import oracle
 import paper_2511_04853_amd as P
-from paper_2511_04853_amd import workloads as W
+import workloads as W
 
 SENTINEL = 0xAB
 

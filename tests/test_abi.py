@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import paper_2511_04853_amd as P
-from paper_2511_04853_amd import workloads as W
+import workloads as W
 from tests.rlhelp import SchemaPair
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))

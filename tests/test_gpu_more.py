@@ -9,7 +9,7 @@ from hypothesis import HealthCheck, given, settings, strategies as st
 
 import oracle
 import paper_2511_04853_amd as P
-from paper_2511_04853_amd import workloads as W
+import workloads as W
 from tests import rlhelp as H
 from tests.test_oracle_pins import schemas
 

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import paper_2511_04853_amd as P
-from paper_2511_04853_amd import workloads as W
+import workloads as W
 from tests import rlhelp as H
 
 pytestmark = pytest.mark.gpu

@@ -7,7 +7,7 @@ import pytest
 from hypothesis import given, settings, strategies as st, HealthCheck
 
 import oracle
-from paper_2511_04853_amd import workloads as W
+import workloads as W
 from tests import npref
 
 ALL = [W.PLAIN8, W.CELL, W.CLUSTER, W.SENSOR, W.PARTICLE]
@@ -492,3 +492,181 @@ def test_brute_force_random_schemas(decl, width, nsel):
         canon = oracle.pack(S, v, aos, pool_order=False)
         for x, y in zip(back, canon):
             assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------ widening and NaNs (P9)
+
+def _oracle_widen(f):
+    decl = W.SchemaDecl("w1", (W.Field("x", "f32"),))
+    S = oracle.Schema(decl)
+    src = oracle.make_layout(S, "soa")
+    dst = oracle.make_layout(S, "soa", storage=["f64"])
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    st, out, _ = oracle.convert(src, [f.view(np.uint8)], dst, f.size)
+    assert st == 0
+    return out[0].view(np.uint64)
+
+
+def widening_vector():
+    """Every class of single-precision value: zeros, subnormals, normals,
+    the extremes, infinities (NaNs are covered separately)."""
+    rng = np.random.default_rng(123)
+    fi = np.finfo(np.float32)
+    special = np.array([0.0, -0.0, 2.0**-149, -2.0**-149, 2.0**-127, 2.0**-126, fi.max, -fi.max,
+                        np.inf, -np.inf, 1.0, -1.0, 0.1, 1e-30], dtype=np.float32)
+    bits = rng.integers(0, 2**32, size=50_000, dtype=np.uint64).astype(np.uint32)
+    rand = bits.view(np.float32)
+    return np.concatenate([special, rand[np.isfinite(rand)]])
+
+
+def test_widening_is_exact_and_matches_numpy():
+    f = widening_vector()
+    got = _oracle_widen(f)
+    assert np.array_equal(got, f.astype(np.float64).view(np.uint64))
+    # exactness: narrowing the widened value gives back the same bits
+    assert np.array_equal(got.view(np.float64).astype(np.float32).view(np.uint32), f.view(np.uint32))
+
+
+def nan_vectors():
+    """NaN encodings: quiet and signalling, both signs, empty and full
+    payloads, payload bits at both ends."""
+    d = np.array([0x7FF8000000000000, 0xFFF8000000000000, 0x7FF0000000000001, 0xFFF0000000000001,
+                  0x7FFFFFFFFFFFFFFF, 0xFFFFFFFFFFFFFFFF, 0x7FF4000000000000, 0x7FF8DEADBEEF0001,
+                  0xFFF0000020000000, 0x7FF000001FFFFFFF, 0x7FFA5A5A5A5A5A5A], dtype=np.uint64)
+    f = np.array([0x7FC00000, 0xFFC00000, 0x7F800001, 0xFF800001, 0x7FFFFFFF, 0xFFFFFFFF,
+                  0x7FA00000, 0x7FC0BEEF, 0xFF812345, 0x7F8FFFFF], dtype=np.uint32)
+    return d, f
+
+
+def _nan_narrow_bits(b):
+    """Reading of a NaN through narrowing: quiet, sign kept, leading 22
+    payload bits kept (IEEE 754-2008 6.2.3 recommends keeping the payload
+    as far as the destination format allows)."""
+    b = np.asarray(b, dtype=np.uint64)
+    return (((b >> np.uint64(63)) << np.uint64(31)) | np.uint64(0x7FC00000)
+            | ((b & np.uint64((1 << 52) - 1)) >> np.uint64(29))).astype(np.uint32)
+
+
+def _nan_widen_bits(b):
+    b = np.asarray(b, dtype=np.uint32).astype(np.uint64)
+    return (((b >> np.uint64(31)) << np.uint64(63)) | np.uint64(0x7FF8000000000000)
+            | ((b & np.uint64(0x7FFFFF)) << np.uint64(29)))
+
+
+def test_nan_through_narrowing_and_widening():
+    d, f = nan_vectors()
+    # the bit-field reading, and numpy's own casts (IEEE hardware conversion)
+    assert np.array_equal(_oracle_narrow(d.view(np.float64)), _nan_narrow_bits(d))
+    with np.errstate(invalid="ignore"):
+        assert np.array_equal(_oracle_narrow(d.view(np.float64)), d.view(np.float64).astype(np.float32).view(np.uint32))
+        assert np.array_equal(_oracle_widen(f.view(np.float32)), f.view(np.float32).astype(np.float64).view(np.uint64))
+    assert np.array_equal(_oracle_widen(f.view(np.float32)), _nan_widen_bits(f))
+    # every result is a quiet NaN with the input's sign
+    nb = _oracle_narrow(d.view(np.float64))
+    assert np.all((nb & 0x7FC00000) == 0x7FC00000)
+    assert np.array_equal(nb >> 31, (d >> np.uint64(63)).astype(np.uint32))
+
+
+# ------------------------------------------------------------ offsets sources not starting at 0 (P7, P8)
+
+def _slice_view(v, k, n):
+    """Objects k .. k+n-1 of a collection held in soa form, viewed in place:
+    each per-object column starts at object k, the offsets column is entries
+    k .. k+n of the whole collection's (so its first entry is the number of
+    members before object k), and the member columns are the whole
+    collection's."""
+    S = oracle.Schema(v.schema)
+    soa = oracle.make_layout(S, "soa")
+    full = oracle.values_buffers(S, v)
+    bufs = []
+    for c, t in enumerate(S.leaf_types()):
+        sz = W.TYPE_SIZE[t]
+        bufs.append(full[c][k * sz:(k + n) * sz].copy())
+    base = len(S.leaves)
+    for g in range(S.n_groups):
+        es = W.TYPE_SIZE[v.schema.offset_types[g]]
+        bufs.append(full[base][k * es:(k + n + 1) * es].copy())
+        bufs += [full[base + 1 + m].copy() for m in range(len(S.members[g]))]
+        base += 1 + len(S.members[g])
+    return S, soa, bufs
+
+
+@pytest.mark.parametrize("decl", [W.CLUSTER, W.PARTICLE], ids=lambda d: d.name)
+@pytest.mark.parametrize("dst_kind", ["aos", "soa", "aosoa"])
+def test_offsets_source_with_a_nonzero_first_entry(decl, dst_kind):
+    v = W.generic_values(decl, 300, seed=8, mean_len=3.0)
+    k, n = 117, 150
+    S, soa, bufs = _slice_view(v, k, n)
+    off = np.concatenate([[0], np.cumsum(v.lengths[0].astype(np.int64))])
+    assert off[k] > 0
+    total = int(off[k + n] - off[k])
+    cap = [len(bufs[len(S.leaves) + 1]) // W.TYPE_SIZE[S.member_types(0)[0]]]
+    dst = oracle.make_layout(S, dst_kind, width=16 if dst_kind == "aosoa" else 0)
+    st, out, tots = oracle.convert(soa, bufs, dst, n, cap, [total])
+    assert st == 0 and tots == [total]
+    # the same objects packed from index 0 give the same bytes
+    sub = W.Values(decl, n)
+    for f in decl.object_fields():
+        sub.fields[f.name] = v.fields[f.name][k:k + n]
+    sub.lengths = [v.lengths[0][k:k + n]]
+    for f in decl.member_fields(0):
+        sub.members[f.name] = v.members[f.name][off[k]:off[k + n]]
+    sub.block_order = [np.arange(n)]
+    want = oracle.pack(S, sub, dst)
+    for x, y in zip(out, want):
+        assert np.array_equal(x, y)
+    # and directly: member j of object i is entry off[k + i] + j of the columns
+    if dst_kind == "soa":
+        got_off = out[len(S.leaves)].view(W.NP_DTYPE[decl.offset_types[0]]).astype(np.int64)
+        assert np.array_equal(got_off, off[k:k + n + 1] - off[k])
+        f0 = decl.member_fields(0)[0]
+        col = out[len(S.leaves) + 1].view(W.NP_DTYPE[f0.type])
+        for i in (0, 1, n // 2, n - 1):
+            ln = int(v.lengths[0][k + i])
+            assert np.array_equal(col[got_off[i]:got_off[i] + ln],
+                                  v.members[f0.name][off[k + i]:off[k + i] + ln])
+
+
+def test_offsets_source_past_its_member_columns_is_a_bounds_error():
+    v = W.generic_values(W.CLUSTER, 100, seed=9, mean_len=3.0)
+    S, soa, bufs = _slice_view(v, 40, 50)
+    off = np.concatenate([[0], np.cumsum(v.lengths[0].astype(np.int64))])
+    total = int(off[90] - off[40])
+    aos = oracle.make_layout(S, "aos")
+    # the member columns hold only the first off[60] members
+    st, _, _ = oracle.convert(soa, bufs, aos, 50, [int(off[60])], [total])
+    assert st == oracle.ST_BOUNDS
+    st, _, _ = oracle.convert(soa, bufs, aos, 50, [int(off[90])], [total])
+    assert st == oracle.ST_OK
+
+
+# ------------------------------------------------------------ records restrided (P2)
+
+@pytest.mark.parametrize("decl", [W.PLAIN8, W.CELL, W.SENSOR], ids=lambda d: d.name)
+def test_natural_records_to_packed_records_match_numpy(decl):
+    """AoS -> AoS between C natural alignment and a packed struct (explicit
+    slot offsets, no padding): numpy's unaligned structured dtype of the
+    same fields is the packed record."""
+    S = oracle.Schema(decl)
+    v = W.generic_values(decl, 301, seed=12)
+    nat = oracle.make_layout(S, "aos")
+    pdt = npref.record_dtype(decl, align=False)
+    offs = []
+    for f, e in S.leaves:
+        if f.subgroup >= 0:
+            sub = pdt.fields[f"sub{f.subgroup}"]
+            offs.append(sub[1] + sub[0].fields[f.name][1] + e * W.TYPE_SIZE[f.type])
+        else:
+            offs.append(pdt.fields[f.name][1] + e * W.TYPE_SIZE[f.type])
+    packed = oracle.make_layout(S, "aos", slot_offsets=offs, stride=pdt.itemsize)
+    src = oracle.pack(S, v, nat)
+    st, out, _ = oracle.convert(nat, src, packed, v.n)
+    assert st == 0 and len(out[0]) == v.n * pdt.itemsize
+    want = np.zeros(v.n, dtype=pdt)
+    natural = src[0].view(npref.record_dtype(decl))
+    for name in pdt.names:
+        want[name] = natural[name]
+    assert np.array_equal(out[0], want.view(np.uint8))
+    # and back: padding of the natural records comes out zero
+    st, back, _ = oracle.convert(packed, out, nat, v.n)
+    assert st == 0 and np.array_equal(back[0], src[0])
