@@ -17,7 +17,8 @@
  *  - Validation failures found on the host return at once and enqueue no
  *    work.  Failures that only the device can see (a member total beyond a
  *    capacity, an offset-type overflow, a member block outside its pool)
- *    are recorded in a per-device status word and returned by rl_sync().
+ *    are recorded in a status word of the stream the work was enqueued on
+ *    and returned by rl_sync() on that stream.
  *  - The caller owns every data buffer; the library never frees them.
  *    Handles (schemas, layouts, batches, servers) are owned by the library
  *    until their destroy call; schemas and layouts are immutable and may be
@@ -223,9 +224,11 @@ rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t group,
 typedef enum rl_xfer_mode {
   RL_XFER_AUTO = 0,      /* zero-copy for pinned collections without jagged
                             groups, staged otherwise */
-  RL_XFER_STAGED = 1,    /* DMA copies of the host buffers into a
-                            stream-ordered device allocation, conversion
-                            from (or into) it, on the caller's stream */
+  RL_XFER_STAGED = 1,    /* DMA copies of the host buffers into a device
+                            staging buffer of the library (one per stream,
+                            grown on demand, kept until the process ends),
+                            conversion from (or into) it, on the caller's
+                            stream */
   RL_XFER_ZERO_COPY = 2  /* the conversion kernels read/write the pinned
                             host buffers directly (one pass, no staging) */
 } rl_xfer_mode;
@@ -246,10 +249,13 @@ typedef struct rl_xfer_opts {
 rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n,
                       void* stream, const rl_xfer_opts* opts);
 
-/* Wait for `stream`, then return (and clear) the device status word of the
- * current device: RL_EOVERFLOW, RL_ECAPACITY or RL_EBOUNDS (in that order
- * of precedence) if any conversion since the last rl_sync on this device
- * found one, else RL_OK; RL_EHIP if the wait failed. */
+/* Wait for `stream`, then return (and clear) the device status word of
+ * that stream: RL_EOVERFLOW, RL_ECAPACITY or RL_EBOUNDS (in that order of
+ * precedence) if any conversion, transfer, offsets step or batch enqueued
+ * on `stream` since the last rl_sync on it found one, else RL_OK; RL_EHIP
+ * if the wait failed.  Each stream has its own word (up to 4,095 streams
+ * per device and process; streams beyond those share one word), so work
+ * on other streams neither sets nor clears it. */
 rl_status rl_sync(void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -271,7 +277,11 @@ typedef struct rl_batch_opts {
  * whose kernels walk a device-resident table of all items.  Items are added
  * with the same arguments as rl_convert and must be device views.  An
  * AoSoA destination layout whose block width is 0 lets the batch choose the
- * width ("auto"); the chosen width is readable with rl_batch_item_width. */
+ * width ("auto"); the chosen width is readable with rl_batch_item_width.
+ * The items of one launch run concurrently: rl_batch_finalize returns
+ * RL_EOVERLAP if a destination of one item overlaps a buffer (source or
+ * destination) of another; sources may be shared.  Device-detected errors
+ * go to the status word of the stream the batch is launched on. */
 rl_status rl_batch_create(const rl_batch_opts* opts, rl_batch** out);
 rl_status rl_batch_add(rl_batch* batch, const rl_view* src, const rl_view* dst,
                        uint64_t n);
@@ -322,7 +332,10 @@ typedef struct rl_event_result {
   uint64_t bytes;                     /* device bytes held */
   void* const* const* buffers;        /* per item: the device buffers */
   const uint64_t* member_capacity;    /* per item and group, flattened */
-  rl_status status;                   /* device status of this event */
+  rl_status status;                   /* RL_OK, a host error of its enqueue, or
+                                         the device status of this event's
+                                         conversions alone (RL_EOVERFLOW,
+                                         RL_ECAPACITY, RL_EBOUNDS) */
 } rl_event_result;
 
 typedef struct rl_server_stats {
@@ -335,10 +348,13 @@ typedef struct rl_server_stats {
 } rl_server_stats;
 
 /* A serving loop: events are admitted in arrival order while their result
- * bytes fit the budget and a slot is free; admitted events convert
- * concurrently on the server's streams; results stay resident until
- * released.  The caller keeps each event's host sources alive until its
- * wait returns. */
+ * bytes (plus, while converting, the device staging of collections that
+ * are copied before conversion: jagged or pageable ones) fit the budget
+ * and a slot is free; admitted events convert concurrently on the server's
+ * streams; results stay resident until released.  All of it is carved
+ * from one device allocation of budget_bytes made at creation.  The caller
+ * keeps each event's host sources alive until its wait returns.
+ * max_in_flight: 1..65536; n_streams: 1..64. */
 rl_status rl_server_create(const rl_server_opts* opts, rl_server** out);
 /* Errors: RL_EBUDGET (the event alone exceeds the budget), RL_EINVAL. */
 rl_status rl_server_submit(rl_server* server, const rl_event* event,

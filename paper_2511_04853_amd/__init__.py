@@ -310,7 +310,10 @@ class Server:
         st = lib().rl_server_wait(self.h, ticket, timeout_ms, ctypes.byref(r))
         if st == RL_EBUSY:
             return None
-        check(st, "rl_server_wait")
+        # a finished event reports its own status in the result; other
+        # statuses (an unknown or released ticket) are errors of the call
+        if st not in (RL_OK, RL_EOVERFLOW, RL_ECAPACITY, RL_EBOUNDS, RL_EHIP) or r.n_items != len(self._keep[ticket][1]):
+            check(st, "rl_server_wait")
         out = {"latency_ns": r.latency_ns, "bytes": r.bytes, "status": r.status, "buffers": []}
         _, items = self._keep[ticket]
         for k, (view, layout, n) in enumerate(items):

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <fstream>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <sstream>
@@ -75,12 +76,15 @@ struct rl_batch {
   std::vector<Plan> plans;   // per item (for the launch loop)
   DeviceTables dev;
   hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // captured graphs, one per status word of the streams launched on (the
+  // kernels report device-detected errors to the launching stream's word)
+  std::map<uint32_t*, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
   double tuned_us = 0;
   ~rl_batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (auto& g : graphs) {
+      if (g.second.second) (void)hipGraphExecDestroy(g.second.second);
+      if (g.second.first) (void)hipGraphDestroy(g.second.first);
+    }
     if (cap) (void)hipStreamDestroy(cap);
     dev.release();
   }
@@ -266,10 +270,20 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   return RL_OK;
 }
 
-rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s) {
+// Launch the batch kernels on `s`, reporting device-detected errors to
+// `status` (the status word of the stream the batch is launched for).
+rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s, uint32_t* status) {
   const uint32_t dt = std::min<uint32_t>(c.threads, kDenseMaxThreads);
-  hipError_t e = launch_batch(d.t, dt, c.gather_threads, c.grid, d.dense_lds, d.gather_lds, s);
+  BatchTables t = d.t;
+  t.status = status;
+  hipError_t e = launch_batch(t, dt, c.gather_threads, c.grid, d.dense_lds, d.gather_lds, s);
   return e == hipSuccess ? RL_OK : hip_fail(e, "batch launch");
+}
+
+rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s) {
+  uint32_t* status = stream_status(s);
+  if (!status) return fail(RL_EHIP, "status words of the current device");
+  return launch_tables(d, c, s, status);
 }
 
 // Signature of a batch for the tuning cache: item shapes with object counts
@@ -426,6 +440,76 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
   return RL_OK;
 }
 
+// The captured graph of the batch kernels for launches on stream `s`
+// (captured on first use for the status word of `s`).
+rl_status graph_for(rl_batch* b, hipStream_t s, hipGraphExec_t* out) {
+  uint32_t* status = stream_status(s);
+  if (!status) return fail(RL_EHIP, "status words of the current device");
+  auto it = b->graphs.find(status);
+  if (it != b->graphs.end()) {
+    *out = it->second.second;
+    return RL_OK;
+  }
+  hipError_t e;
+  if (!b->cap && (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(e, "stream");
+  if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(e, "hipStreamBeginCapture");
+  rl_status st = launch_tables(b->dev, b->cfg, b->cap, status);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->graphs[status] = {g, x};
+  *out = x;
+  return RL_OK;
+}
+
+// Reject batches in which an item writes memory that another item reads or
+// writes: the items of one launch run at the same time, in no order.
+// Sources shared between items (read-only) are allowed.
+rl_status check_items_disjoint(const rl_batch* b) {
+  struct R {
+    uintptr_t lo, hi;
+    size_t item;
+    bool dst;
+  };
+  std::vector<R> rs;
+  for (size_t k = 0; k < b->items.size(); ++k) {
+    const Item& it = b->items[k];
+    if (!it.n) continue;
+    std::vector<Range> s, d;
+    rl_view sv = it.src_view(), dv = it.dst_view();
+    if (validate_view(&sv, it.n, "src", &s, true) || validate_view(&dv, it.n, "dst", &d, true))
+      return RL_EINVAL;
+    for (const auto& r : s) rs.push_back({r.lo, r.hi, k, false});
+    for (const auto& r : d) rs.push_back({r.lo, r.hi, k, true});
+  }
+  std::sort(rs.begin(), rs.end(), [](const R& a, const R& b) { return a.lo < b.lo; });
+  // sweep: every range against the earlier ones still open at its start
+  std::vector<const R*> open;
+  for (const R& r : rs) {
+    size_t w = 0;
+    for (size_t j = 0; j < open.size(); ++j)
+      if (open[j]->hi > r.lo) open[w++] = open[j];
+    open.resize(w);
+    for (const R* o : open)
+      if (o->item != r.item && (o->dst || r.dst))
+        return fail(RL_EOVERLAP, "batch items %zu and %zu: a destination overlaps the other item's buffers",
+                    std::min(o->item, r.item), std::max(o->item, r.item));
+    open.push_back(&r);
+  }
+  return RL_OK;
+}
+
 // Time graph replay against direct launches of the chosen configuration.
 rl_status choose_launch(rl_batch* b, hipStream_t s) {
   hipEvent_t e0, e1;
@@ -436,9 +520,15 @@ rl_status choose_launch(rl_batch* b, hipStream_t s) {
   for (int mode = 0; mode < 2; ++mode) {
     for (int k = 0; k < reps + 2; ++k) {
       if (k == 2) (void)hipEventRecord(e0, s);
-      hipError_t e = mode == 0 ? hipGraphLaunch(b->exec, s) : launch_batch(b->dev.t, std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads), b->cfg.gather_threads, b->cfg.grid, b->dev.dense_lds,
-                                 b->dev.gather_lds, s);
-      if (e != hipSuccess) return hip_fail(e, "tuning launch");
+      rl_status st = RL_OK;
+      if (mode == 0) {
+        hipGraphExec_t x = nullptr;
+        if ((st = graph_for(b, s, &x))) return st;
+        const hipError_t e = hipGraphLaunch(x, s);
+        if (e != hipSuccess) return hip_fail(e, "tuning launch");
+      } else if ((st = launch_tables(b->dev, b->cfg, s))) {
+        return st;
+      }
     }
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
@@ -499,6 +589,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (!b) return fail(RL_EINVAL, "batch is NULL");
   if (b->finalized) return fail(RL_EBUSY, "batch already finalized");
   hipStream_t s = (hipStream_t)stream;
+  if (rl_status st0 = check_items_disjoint(b)) return st0;
   Config c;
   const std::string sig = signature(b);
   bool have = false;
@@ -522,16 +613,8 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (!st) st = plan_all(b, c);
   if (!st) st = build_tables(b, c, &b->dev);
   if (st) return st;
-  hipError_t e;
-  if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-  if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-    return hip_fail(e, "hipStreamBeginCapture");
-  st = launch_tables(b->dev, c, b->cap);
-  e = hipStreamEndCapture(b->cap, &b->graph);
-  if (st) return st;
-  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
-    return hip_fail(e, "hipGraphInstantiate");
+  hipGraphExec_t x = nullptr;
+  if ((st = graph_for(b, s, &x))) return st;
   if (b->autotune) {
     if ((st = choose_launch(b, s))) return st;
     if (!b->cache.empty()) cache_store(b->cache, sig, b->cfg, b->tuned_us);
@@ -544,7 +627,9 @@ extern "C" rl_status rl_batch_launch(rl_batch* b, void* stream) {
   if (!b || !b->finalized) return fail(RL_EINVAL, "batch not finalized");
   if (!b->dev.t.dense_tiles && !b->dev.t.gather_tiles && !b->dev.t.n_totals && !b->dev.t.rebase_tiles) return RL_OK;
   if (b->cfg.direct) return launch_tables(b->dev, b->cfg, (hipStream_t)stream);
-  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  hipGraphExec_t x = nullptr;
+  if (rl_status st = graph_for(b, (hipStream_t)stream, &x)) return st;
+  hipError_t e = hipGraphLaunch(x, (hipStream_t)stream);
   return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphLaunch");
 }
 

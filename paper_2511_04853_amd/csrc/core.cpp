@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 
 #include "plan.h"
@@ -38,24 +39,43 @@ rl_status hip_fail(hipError_t e, const char* what) {
 
 // ------------------------------------------------------------------ device state
 
+// Status words: slot k of a device's array belongs to the k-th stream that
+// ran a conversion on that device in this process (slots are never
+// reused; beyond kStatusSlots - 1 streams, the later ones share the last
+// slot).  A slot is written only by kernels of its stream, so rl_sync can
+// read and clear it on that stream without racing other streams.
 static std::mutex g_dev_mu;
-static uint32_t* g_status[64] = {};
-static uint32_t* g_status_host[64] = {};
+struct DeviceSlots {
+  uint32_t* words = nullptr;                 // device address of the array
+  std::map<hipStream_t, uint32_t> slot;      // stream -> slot
+  uint32_t next = 0;
+};
+static std::map<int, DeviceSlots> g_slots;
 
-uint32_t* device_status(int device) {
-  if (device < 0 || device >= 64) return nullptr;
+static uint32_t* stream_status_on(int dev, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_dev_mu);
-  if (!g_status[device]) {
-    uint32_t* p = nullptr;
-    if (hipMalloc(&p, 256) != hipSuccess) return nullptr;
-    if (hipMemset(p, 0, 256) != hipSuccess) return nullptr;
-    if (hipHostMalloc(&g_status_host[device], 256, hipHostMallocDefault) != hipSuccess) return nullptr;
-    g_status[device] = p;
+  DeviceSlots& d = g_slots[dev];
+  if (!d.words) {
+    uint32_t* w = nullptr;
+    if (status_words(&w) != hipSuccess || !w) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    d.words = w;
   }
-  return g_status[device];
+  auto it = d.slot.find(s);
+  if (it == d.slot.end()) {
+    const uint32_t k = d.next < kStatusSlots - 1 ? d.next++ : kStatusSlots - 1;
+    it = d.slot.emplace(s, k).first;
+  }
+  return d.words + it->second;
 }
 
-static uint32_t* device_status_host(int device) { return g_status_host[device]; }
+uint32_t* stream_status(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  return stream_status_on(dev, s);
+}
 
 uint32_t type_size(rl_type t) {
   switch (t) {
@@ -506,23 +526,36 @@ extern "C" rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t
   return RL_OK;
 }
 
-extern "C" rl_status rl_sync(void* stream) {
-  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  int dev = 0;
-  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
-  uint32_t* ds = device_status(dev);
-  if (!ds) return fail(RL_ENOMEM, "device status word");
-  uint32_t* hs = device_status_host(dev);
-  if ((e = hipMemcpyAsync(hs, ds, 4, hipMemcpyDeviceToHost, (hipStream_t)stream)) != hipSuccess)
-    return hip_fail(e, "hipMemcpyAsync(status)");
-  if ((e = launch_clear_status(ds, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "clear status");
-  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  const uint32_t f = *hs;
+namespace rl {
+rl_status status_of_flags(uint32_t f) {
   if (f & ST_FLAG_OVERFLOW) return fail(RL_EOVERFLOW, "a member total does not fit the offset type");
   if (f & ST_FLAG_CAPACITY) return fail(RL_ECAPACITY, "members exceed the destination capacity");
   if (f & ST_FLAG_BOUNDS) return fail(RL_EBOUNDS, "a source member block lies outside its storage or is misaligned");
   return RL_OK;
+}
+}  // namespace rl
+
+// Per-thread pinned word that rl_sync receives a stream's flags in.
+static thread_local uint32_t* t_sync_word = nullptr;
+
+extern "C" rl_status rl_sync(void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  uint32_t* ds = stream_status(s);
+  if (!ds) return fail(RL_EHIP, "status words of the current device");
+  if (!t_sync_word) {
+    // leaked at thread exit (4 bytes of pinned memory per thread that syncs)
+    if ((e = hipHostMalloc((void**)&t_sync_word, 64, hipHostMallocDefault)) != hipSuccess)
+      return hip_fail(e, "hipHostMalloc(status)");
+  }
+  uint32_t* dev_alias = nullptr;
+  if ((e = hipHostGetDevicePointer((void**)&dev_alias, t_sync_word, 0)) != hipSuccess)
+    return hip_fail(e, "hipHostGetDevicePointer(status)");
+  *t_sync_word = 0;
+  if ((e = launch_take_status(ds, dev_alias, s)) != hipSuccess) return hip_fail(e, "take status");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return status_of_flags(*(volatile uint32_t*)t_sync_word);
 }
 
 extern "C" const char* rl_last_error(void) { return g_err; }

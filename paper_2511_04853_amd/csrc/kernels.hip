@@ -141,6 +141,26 @@ __device__ __forceinline__ void copy_bytes(uint8_t* d, const uint8_t* s, uint32_
   for (uint32_t k = 0; k < n; ++k) d[k] = s[k];
 }
 
+// Change of precision of one value.  Numbers: IEEE round to nearest even
+// (v_cvt_f32_f64; overflow to infinity, subnormal results kept) and exact
+// widening (v_cvt_f64_f32).  NaNs: the result is a quiet NaN with the
+// input's sign and the leading bits of its payload (as many as the
+// destination holds), assembled from the bit fields so that it does not
+// depend on how the conversion instructions treat NaN operands.
+__device__ __forceinline__ float narrow_value(double x) {
+  const float y = (float)x;
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t q = (uint32_t)((b >> 63) << 31) | 0x7FC00000u | (uint32_t)((b & 0x000FFFFFFFFFFFFFull) >> 29);
+  return __builtin_isnan(x) ? __uint_as_float(q) : y;
+}
+
+__device__ __forceinline__ double widen_value(float x) {
+  const double y = (double)x;
+  const uint32_t b = __float_as_uint(x);
+  const uint64_t q = ((uint64_t)(b >> 31) << 63) | 0x7FF8000000000000ull | ((uint64_t)(b & 0x007FFFFFu) << 29);
+  return __builtin_isnan(x) ? __longlong_as_double((long long)q) : y;
+}
+
 // Move one value inside LDS.
 template <class LD>
 __device__ __forceinline__ void move_value(uint8_t* dst, const uint8_t* src, const LD& L) {
@@ -156,14 +176,14 @@ __device__ __forceinline__ void move_value(uint8_t* dst, const uint8_t* src, con
     double x;
     if (L.byte_wise) copy_bytes(reinterpret_cast<uint8_t*>(&x), src, 8);
     else x = *reinterpret_cast<const double*>(src);
-    const float y = (float)x;   // v_cvt_f32_f64: IEEE round to nearest even
+    const float y = narrow_value(x);
     if (L.byte_wise) copy_bytes(dst, reinterpret_cast<const uint8_t*>(&y), 4);
     else *reinterpret_cast<float*>(dst) = y;
   } else {  // OP_WIDEN
     float x;
     if (L.byte_wise) copy_bytes(reinterpret_cast<uint8_t*>(&x), src, 4);
     else x = *reinterpret_cast<const float*>(src);
-    const double y = (double)x;
+    const double y = widen_value(x);
     if (L.byte_wise) copy_bytes(dst, reinterpret_cast<const uint8_t*>(&y), 8);
     else *reinterpret_cast<double*>(dst) = y;
   }
@@ -477,7 +497,8 @@ __device__ __forceinline__ void issue_source(const DD& d, uint8_t* smem, const T
 // tile's exclusive offsets (entry i0 holds the tile total until the totals
 // pass replaces it with the tile's prefix).
 template <class DD>
-__device__ __forceinline__ void scan_tile(const DD& d, const DenseLds& m, uint64_t i0, uint32_t cnt) {
+__device__ __forceinline__ void scan_tile(const DD& d, const DenseLds& m, uint64_t i0, uint32_t cnt,
+                                          uint32_t* status) {
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t per = (d.tile + nt - 1) / nt;
   const uint32_t o0 = tid * per;
@@ -495,7 +516,7 @@ __device__ __forceinline__ void scan_tile(const DD& d, const DenseLds& m, uint64
       run += *reinterpret_cast<const uint32_t*>(m.src + o * d.src.stride + d.scan_len_off);
     }
   }
-  if (tid == 0 && total > off_limit(d.scan_off_type)) flag(d.status, ST_FLAG_OVERFLOW);
+  if (tid == 0 && total > off_limit(d.scan_off_type)) flag(status, ST_FLAG_OVERFLOW);
 }
 
 // ------------------------------------------------------------------ transform
@@ -576,8 +597,8 @@ __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, c
       case CODE_COPY2: RL_MOVE(uint16_t, uint16_t, 2, 2, x); break;
       case CODE_COPY4: RL_MOVE(uint32_t, uint32_t, 4, 4, x); break;
       case CODE_COPY8: RL_MOVE(uint64_t, uint64_t, 8, 8, x); break;
-      case CODE_NARROW: RL_MOVE(double, float, 8, 4, (float)x); break;  // v_cvt_f32_f64: round to nearest even
-      case CODE_WIDEN: RL_MOVE(float, double, 4, 8, (double)x); break;
+      case CODE_NARROW: RL_MOVE(double, float, 8, 4, narrow_value(x)); break;
+      case CODE_WIDEN: RL_MOVE(float, double, 4, 8, widen_value(x)); break;
       default: break;   // slow leaves: transform_slow
     }
   }
@@ -643,7 +664,7 @@ __device__ __forceinline__ void transform_slow(const DD& d, const LeafLanes& lt,
 // pass sets them.
 template <class DD>
 __device__ __forceinline__ void check_staged(const DD& d, const uint8_t* run, uint64_t first, uint64_t i0,
-                                             uint32_t cnt) {
+                                             uint32_t cnt, uint32_t* status) {
   const uint32_t ot = d.stage_type;
   const uint64_t cap = d.stage_src_capacity;
   bool overflow = false, bounds = false;
@@ -652,11 +673,11 @@ __device__ __forceinline__ void check_staged(const DD& d, const uint8_t* run, ui
     if (b < a) overflow = true;
     else if (a > cap || b - a > cap - a) bounds = true;
   }
-  if (overflow) flag(d.status, ST_FLAG_OVERFLOW);
-  if (bounds) flag(d.status, ST_FLAG_BOUNDS);
+  if (overflow) flag(status, ST_FLAG_OVERFLOW);
+  if (bounds) flag(status, ST_FLAG_BOUNDS);
   if (i0 + cnt == d.n && threadIdx.x == 0) {
     const uint64_t a = staged_off(run, ot, cnt);
-    if (a >= first && a - first > d.stage_dst_capacity) flag(d.status, ST_FLAG_CAPACITY);
+    if (a >= first && a - first > d.stage_dst_capacity) flag(status, ST_FLAG_CAPACITY);
   }
 }
 
@@ -714,7 +735,7 @@ __device__ __forceinline__ void transform_direct(const DD& d, const DenseLds& m,
 
 template <class DD>
 __device__ __forceinline__ void transform_tile(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
-                                               uint32_t cnt) {
+                                               uint32_t cnt, uint32_t* status) {
   if (d.dst_direct) {
     transform_direct(d, m, lt, i0, cnt);
     return;
@@ -722,7 +743,7 @@ __device__ __forceinline__ void transform_tile(const DD& d, const DenseLds& m, c
   if (d.slow_leaves) {
     const uint8_t* run = reinterpret_cast<const uint8_t*>(m.offs) + 16;
     const uint64_t first = d.stage_offsets ? staged_off(run - 16, d.stage_type, 0) : 0;
-    if (d.stage_offsets) check_staged(d, run, first, i0, cnt);
+    if (d.stage_offsets) check_staged(d, run, first, i0, cnt, status);
     transform_slow(d, lt, m.src, m.dst, run, first, i0, cnt);
   }
   switch (d.src.kind * 3 + d.dst.kind) {
@@ -743,7 +764,7 @@ __device__ __forceinline__ void transform_tile(const DD& d, const DenseLds& m, c
 // pointer: the address of a kernel-argument descriptor must not escape
 // into a loop-carried value, or the compiler copies it to scratch.)
 template <class Next, class Desc>
-__device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc desc) {
+__device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc desc, uint32_t* status) {
   LeafLanes lt;
   TileJob cur = next();
   if (cur.valid) {
@@ -768,8 +789,8 @@ __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc de
     }
     // 3. counts scan and value moves (into the destination image, or
     //    straight to global memory)
-    if (d.scan_offsets) scan_tile(d, m, i0, cnt);
-    transform_tile(d, m, lt, i0, cnt);
+    if (d.scan_offsets) scan_tile(d, m, i0, cnt, status);
+    transform_tile(d, m, lt, i0, cnt, status);
     __syncthreads();
     // 4. this tile's destination image out, then the next tile's source
     //    image in (its DMA is issued after the image reads, and overlaps
@@ -810,7 +831,7 @@ __global__ void __launch_bounds__(256, 7) dense_kernel(const DenseDesc) {
   dense_count(d, &count, &base);
   dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw),
                  StridedTiles{blockIdx.x, (count + d.tile - 1) / d.tile, count, base},
-                 [&](uint32_t) -> const RL_C DenseDesc& { return kernel_arg<DenseDesc>(); });
+                 [&](uint32_t) -> const RL_C DenseDesc& { return kernel_arg<DenseDesc>(); }, d.status);
 }
 
 // ------------------------------------------------------------------ offsets
@@ -819,7 +840,7 @@ __global__ void __launch_bounds__(256, 7) dense_kernel(const DenseDesc) {
 // scan (stored at entry tile * T), writing each tile's prefix there and the
 // grand total at entry n.  One work-group.
 template <class TD>
-__device__ void scan_totals_body(const TD& d, uint64_t* wsum) {
+__device__ void scan_totals_body(const TD& d, uint64_t* wsum, uint32_t* status) {
   const uint64_t ntiles = (d.n + d.tile - 1) / d.tile;
   uint64_t carry = 0;
   for (uint64_t c0 = 0; c0 < ntiles; c0 += blockDim.x) {
@@ -832,14 +853,14 @@ __device__ void scan_totals_body(const TD& d, uint64_t* wsum) {
   }
   if (threadIdx.x == 0) {
     store_off(d.offsets, d.off_type, d.n, carry);
-    if (carry > off_limit(d.off_type)) flag(d.status, ST_FLAG_OVERFLOW);
-    else if (carry > d.capacity) flag(d.status, ST_FLAG_CAPACITY);
+    if (carry > off_limit(d.off_type)) flag(status, ST_FLAG_OVERFLOW);
+    else if (carry > d.capacity) flag(status, ST_FLAG_CAPACITY);
   }
 }
 
 __global__ void __launch_bounds__(1024) scan_totals_kernel(const ScanTotalsDesc d) {
   __shared__ uint64_t wsum[17];
-  scan_totals_body(d, wsum);
+  scan_totals_body(d, wsum, d.status);
 }
 
 // Add tile prefixes, then copy the members of the tile's objects from the
@@ -991,7 +1012,7 @@ __device__ __forceinline__ void gather_words(const GD& d, const uint64_t* offs, 
 // count) are staged in LDS; every pool read stays inside the member block
 // the record validated (vlen).
 template <class GD>
-__device__ __forceinline__ void gather_sub(const GD& d, uint64_t u, uint8_t* smem) {
+__device__ __forceinline__ void gather_sub(const GD& d, uint64_t u, uint8_t* smem, uint32_t* status) {
   const uint32_t S = d.sub;
   uint64_t* offs = reinterpret_cast<uint64_t*>(smem);   // S + 1
   uint64_t* ptrs = offs + (S + 1);                      // S
@@ -1022,7 +1043,7 @@ __device__ __forceinline__ void gather_sub(const GD& d, uint64_t u, uint8_t* sme
     const bool good = (p & (uint64_t)(d.malign - 1)) == 0 && p <= pool_end && len <= (pool_end - p) / d.mstride;
     ptrs[k] = p;
     vlen[k] = good ? (uint32_t)len : 0u;   // members readable for this object
-    if (!good) flag(d.status, ST_FLAG_BOUNDS);
+    if (!good) flag(status, ST_FLAG_BOUNDS);
   }
   if (d.n_members == 0) return;   // uniform: offsets only
   __syncthreads();
@@ -1046,14 +1067,14 @@ __global__ void __launch_bounds__(256) gather_kernel(const GatherDesc) {
   const RL_C GatherDesc& d = kernel_arg<GatherDesc>();
   const uint64_t nsub = (d.n + d.sub - 1) / d.sub;
   for (uint64_t u = blockIdx.x; u < nsub; u += gridDim.x)
-    gather_sub(kernel_arg<GatherDesc>(), u, reinterpret_cast<uint8_t*>(smem_raw));
+    gather_sub(kernel_arg<GatherDesc>(), u, reinterpret_cast<uint8_t*>(smem_raw), d.status);
 }
 
 // Offsets column -> offsets column, rebased to start at 0, with the checks
 // of a well-formed source (non-decreasing, inside the source capacity) and
 // of the destination capacity.
 template <class RD>
-__device__ void rebase_range(const RD& d, uint64_t begin, uint64_t step, uint64_t last) {
+__device__ void rebase_range(const RD& d, uint64_t begin, uint64_t step, uint64_t last, uint32_t* status) {
   const uint64_t first = load_off(d.src, d.off_type, 0);
   if (last > d.n) last = d.n;
   for (uint64_t i = begin; i <= last; i += step) {
@@ -1061,19 +1082,31 @@ __device__ void rebase_range(const RD& d, uint64_t begin, uint64_t step, uint64_
     if (d.dst) store_off(d.dst, d.off_type, i, a - first);
     if (i < d.n) {
       const uint64_t b = load_off(d.src, d.off_type, i + 1);
-      if (b < a) flag(d.status, ST_FLAG_OVERFLOW);
-      else if (a > d.src_capacity || b - a > d.src_capacity - a) flag(d.status, ST_FLAG_BOUNDS);
+      if (b < a) flag(status, ST_FLAG_OVERFLOW);
+      else if (a > d.src_capacity || b - a > d.src_capacity - a) flag(status, ST_FLAG_BOUNDS);
     } else if (a >= first && a - first > d.dst_capacity) {
-      flag(d.status, ST_FLAG_CAPACITY);
+      flag(status, ST_FLAG_CAPACITY);
     }
   }
 }
 
 __global__ void rebase_kernel(const RebaseDesc d) {
-  rebase_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x, d.n);
+  rebase_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x, d.n, d.status);
 }
 
-__global__ void clear_status_kernel(uint32_t* status) { *gp(status) = 0; }
+// Status words of streams: one per stream that has run a conversion (the
+// host assigns slots), so that reading and clearing one stream's word never
+// races with another stream's kernels.
+__device__ __align__(256) uint32_t g_status_words[kStatusSlots];
+
+// Hand a stream's status flags to `out` (device memory, or the device
+// address of pinned host memory) and clear them, in stream order.
+__global__ void take_status_kernel(uint32_t* status, uint32_t* out) {
+  RL_G uint32_t* w = gp(status);
+  const uint32_t f = *w;
+  *w = 0;
+  *gp(out) = f;
+}
 
 // ------------------------------------------------------------------ batches
 
@@ -1147,7 +1180,7 @@ struct BatchTiles {
 __global__ void __launch_bounds__(256, 6) batch_dense_kernel(const BatchTables b) {
   extern __shared__ uint4 smem_raw[];
   dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw), BatchTiles(&b, blockIdx.x),
-                 [&](uint32_t item) -> const RL_C DenseDesc& { return cdesc(b.dense, item); });
+                 [&](uint32_t item) -> const RL_C DenseDesc& { return cdesc(b.dense, item); }, b.status);
 }
 
 // Tile-total scans (one work-group each) and offsets rebases.
@@ -1155,13 +1188,13 @@ __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   __shared__ uint64_t wsum[17];
   const uint32_t j = blockIdx.x;
   if (j < b.n_totals) {
-    scan_totals_body(cdesc(b.totals, j), wsum);
+    scan_totals_body(cdesc(b.totals, j), wsum, b.status);
   } else if (j - b.n_totals < b.rebase_tiles) {
     // rebases in tiles of kRebaseTile entries, spread over work-groups
     const uint32_t t = j - b.n_totals;
     const uint32_t item = b.rebase_item[t];
     const uint64_t begin = (t - b.rebase_prefix[item]) * (uint64_t)kRebaseTile;
-    rebase_range(cdesc(b.rebase, item), begin + threadIdx.x, blockDim.x, begin + kRebaseTile - 1);
+    rebase_range(cdesc(b.rebase, item), begin + threadIdx.x, blockDim.x, begin + kRebaseTile - 1, b.status);
   }
 }
 
@@ -1170,7 +1203,7 @@ __global__ void __launch_bounds__(256) batch_gather_kernel(const BatchTables b) 
   extern __shared__ uint4 smem_raw[];
   for (uint64_t u = blockIdx.x; u < b.gather_tiles; u += gridDim.x) {
     const uint32_t item = __builtin_amdgcn_readfirstlane(b.gather_item[u]);
-    gather_sub(cdesc(b.gather, item), u - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw));
+    gather_sub(cdesc(b.gather, item), u - b.gather_prefix[item], reinterpret_cast<uint8_t*>(smem_raw), b.status);
   }
 }
 
@@ -1290,9 +1323,13 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
   return hipSuccess;
 }
 
-hipError_t launch_clear_status(uint32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, s, status);
+hipError_t launch_take_status(uint32_t* status, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(take_status_kernel, dim3(1), dim3(1), 0, s, status, out);
   return hipGetLastError();
+}
+
+hipError_t status_words(uint32_t** out) {
+  return hipGetSymbolAddress(reinterpret_cast<void**>(out), HIP_SYMBOL(g_status_words));
 }
 
 }  // namespace rl

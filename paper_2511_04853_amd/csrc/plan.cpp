@@ -308,10 +308,7 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
   const rl_layout* DL = dst.layout;
   const rl_schema* sc = SL->schema;
   const uint32_t ng = (uint32_t)sc->members.size();
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  uint32_t* status = device_status(dev);
-  if (!status) return fail(RL_ENOMEM, "device status word");
+  uint32_t* const status = nullptr;   // stamped with the stream's word at enqueue
   if (ng && SL->kind == RL_AOS && DL->kind == RL_AOS)
     return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
 
@@ -399,10 +396,7 @@ rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t g, 
                             const PlanShape& shape, Plan* plan) {
   const rl_layout* SL = src.layout;
   const rl_schema* sc = SL->schema;
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  uint32_t* status = device_status(dev);
-  if (!status) return fail(RL_ENOMEM, "device status word");
+  uint32_t* const status = nullptr;   // stamped with the stream's word at enqueue
   if (SL->kind == RL_AOS) {
     SideSpec s = object_side(SL, src.buffers, 0);
     s.types.clear();
@@ -422,13 +416,17 @@ rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t g, 
 }
 
 rl_status enqueue_plan(const Plan& plan, hipStream_t stream) {
-  for (const Step& s : plan.steps) {
+  // device-detected errors go to the status word of the launching stream
+  uint32_t* const status = stream_status(stream);
+  if (!status) return fail(RL_EHIP, "status words of the current device");
+  for (const Step& s0 : plan.steps) {
+    Step s = s0;
     hipError_t e = hipSuccess;
     switch (s.kind) {
-      case Step::DENSE: e = launch_dense(s.dense, s.threads, s.grid, stream); break;
-      case Step::SCAN_TOTALS: e = launch_scan_totals(s.totals, stream); break;
-      case Step::GATHER: e = launch_gather(s.gather, s.threads, stream); break;
-      case Step::REBASE: e = launch_rebase(s.rebase, stream); break;
+      case Step::DENSE: s.dense.status = status; e = launch_dense(s.dense, s.threads, s.grid, stream); break;
+      case Step::SCAN_TOTALS: s.totals.status = status; e = launch_scan_totals(s.totals, stream); break;
+      case Step::GATHER: s.gather.status = status; e = launch_gather(s.gather, s.threads, stream); break;
+      case Step::REBASE: s.rebase.status = status; e = launch_rebase(s.rebase, stream); break;
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }

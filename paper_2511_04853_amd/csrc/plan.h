@@ -72,4 +72,12 @@ rl_status enqueue_plan(const Plan& plan, hipStream_t stream);
 PlanShape shape_from_env();
 bool auto_width(const rl_view* v);
 
+// Host <-> device transfer (rl_transfer) with an optional staging block
+// owned by the caller (device memory of at least staging_bytes(host view)
+// bytes; nullptr: the library's per-stream staging buffer).
+rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipStream_t stream,
+                        const rl_xfer_opts* opts, uint8_t* stage, uint64_t stage_bytes);
+uint64_t staging_bytes(const rl_view& host_view, uint64_t n);
+bool transfer_is_staged(const rl_view& host_view, const rl_xfer_opts* opts);
+
 }  // namespace rl

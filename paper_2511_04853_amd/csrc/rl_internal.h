@@ -20,6 +20,7 @@ constexpr int kMaxUnits = 256;        // SoA images up to this many bytes per ob
 constexpr int kMaxExtent = 64;
 constexpr uint32_t kAutoWidthMax = 128; // "auto" AoSoA widths are 32, 64 or 128
 constexpr uint32_t kDenseMaxThreads = 256;  // launch bound of the dense kernels
+constexpr uint32_t kStatusSlots = 4096;     // device status words (one per stream)
 
 // Kinds of one side of a dense conversion (match rl_kind).
 enum SideKind : uint32_t { KIND_AOS = 0, KIND_SOA = 1, KIND_AOSOA = 2 };
@@ -186,6 +187,7 @@ struct BatchTables {
   const uint64_t* rebase_prefix;    // first rebase tile of each rebase step
   const uint32_t* rebase_item;      // rebase tile -> rebase step
   uint32_t rebase_tiles;
+  uint32_t* status;                 // status word of the launching stream
 };
 constexpr uint32_t kRebaseTile = 8192;   // offsets entries per rebase work-group
 
@@ -195,7 +197,9 @@ hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid,
 hipError_t launch_scan_totals(const ScanTotalsDesc& d, hipStream_t s);
 hipError_t launch_gather(const GatherDesc& d, uint32_t threads, hipStream_t s);
 hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s);
-hipError_t launch_clear_status(uint32_t* status, hipStream_t s);
+hipError_t launch_take_status(uint32_t* status, uint32_t* out, hipStream_t s);
+// Device address of the status words of the current device.
+hipError_t status_words(uint32_t** out);
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
                         uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s);
 // Members per pass of the packed-word gather (LDS staging per word).
@@ -219,7 +223,10 @@ rl_status fail(rl_status st, const char* fmt, ...);
 rl_status hip_fail(hipError_t e, const char* what);
 
 // ---- device state ----
-uint32_t* device_status(int device);  // lazily allocated per device
+// Status word of a stream on the current device (nullptr on a HIP error).
+uint32_t* stream_status(hipStream_t s);
+// The status (and message) of a set of device status flags.
+rl_status status_of_flags(uint32_t flags);
 
 }  // namespace rl
 

@@ -50,6 +50,9 @@ struct Event {
   EvState state = EvState::QUEUED;
   hipEvent_t done = nullptr;
   uint32_t stream = 0;
+  uint32_t slot = 0;                  // in-flight slot (status word) while admitted
+  uint64_t stage_need = 0;            // device staging bytes while converting
+  uint64_t stage_off = UINT64_MAX;    // pool offset of the staging block
   rl_status status = RL_OK;
   // result views handed to the client
   std::vector<void* const*> buf_ptrs;
@@ -64,6 +67,11 @@ struct rl_server {
   std::vector<hipStream_t> streams;
   uint8_t* slab = nullptr;
   SlabAllocator pool;
+  // one pinned word per in-flight slot: the device status flags of the
+  // event in that slot, handed over in stream order when it completes
+  uint32_t* slot_words = nullptr;
+  uint32_t* slot_words_dev = nullptr;
+  std::vector<uint32_t> free_slots;
   std::mutex mu;
   std::condition_variable cv_done;   // events finished
   std::condition_variable cv_work;   // new submissions or releases
@@ -83,13 +91,12 @@ struct rl_server {
 
 namespace {
 
+// Result bytes of an event as the pool places them (buffers of 0 bytes
+// take no block).
 uint64_t event_bytes(Event& e) {
   uint64_t total = 0;
-  for (auto& it : e.items) total += [&] {
-    uint64_t s = 0;
-    for (auto b : it.dst_bytes) s += (b + 255) / 256 * 256;
-    return s;
-  }();
+  for (auto& it : e.items)
+    for (auto b : it.dst_bytes) total += (b + 255) / 256 * 256;
   return total;
 }
 
@@ -97,21 +104,27 @@ uint64_t event_bytes(Event& e) {
 // a slot is free, placing their result buffers (caller holds mu).
 std::vector<Event*> admit(rl_server* s) {
   std::vector<Event*> out;
-  while (!s->queue.empty() && s->running < s->opts.max_in_flight) {
+  while (!s->queue.empty() && s->running < s->opts.max_in_flight && !s->free_slots.empty()) {
     Event& e = *s->events[s->queue.front()];
     std::vector<uint64_t> sizes;
     for (auto& it : e.items)
-      for (auto b : it.dst_bytes) sizes.push_back(b);
+      for (auto b : it.dst_bytes)
+        if (b) sizes.push_back(b);
+    if (e.stage_need) sizes.push_back(e.stage_need);
     if (!s->pool.fits(sizes)) break;   // head of line waits for releases
     for (auto& it : e.items) {
       it.dst_offsets.clear();
       it.dst_bufs.clear();
       for (auto b : it.dst_bytes) {
-        const uint64_t off = s->pool.alloc(b);
+        const uint64_t off = b ? s->pool.alloc(b) : UINT64_MAX;
         it.dst_offsets.push_back(off);
         it.dst_bufs.push_back(b ? s->slab + off : nullptr);
       }
     }
+    e.stage_off = e.stage_need ? s->pool.alloc(e.stage_need) : UINT64_MAX;
+    e.slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    s->slot_words[e.slot] = 0;
     s->peak = std::max<uint64_t>(s->peak, s->pool.in_use());
     s->queue.pop_front();
     e.stream = s->next_stream;
@@ -128,15 +141,24 @@ std::vector<Event*> admit(rl_server* s) {
 uint64_t launch(rl_server* s, Event& e) {
   uint64_t h2d = 0;
   hipStream_t st = s->streams[e.stream];
+  uint8_t* stage = e.stage_need ? s->slab + e.stage_off : nullptr;
   for (auto& it : e.items) {
     rl_view sv{it.src_layout, it.src_cap, it.src_mcap.empty() ? nullptr : it.src_mcap.data(), it.src_bufs.data()};
     rl_view dv{it.dst_layout, it.n, it.dst_mcap.empty() ? nullptr : it.dst_mcap.data(), it.dst_bufs.data()};
     rl_xfer_opts o{RL_XFER_AUTO};
-    const rl_status r = rl_transfer(&sv, &dv, it.n, st, &o);
+    // items of an event run one after another on its stream, so they share
+    // the event's staging block
+    const rl_status r = transfer_impl(&sv, &dv, it.n, st, &o, stage, e.stage_need);
     if (r != RL_OK && e.status == RL_OK) e.status = r;
     std::vector<uint64_t> hb(layout_n_buffers(it.src_layout));
     layout_buffer_bytes(it.src_layout, it.n, it.src_mcap.empty() ? nullptr : it.src_mcap.data(), hb.data());
     for (auto b : hb) h2d += b;
+  }
+  // the stream's device status flags (this event's alone: the stream runs
+  // events in order and each hand-over clears them) go to the slot's word
+  uint32_t* word = stream_status(st);
+  if (!word || launch_take_status(word, s->slot_words_dev + e.slot, st) != hipSuccess) {
+    if (e.status == RL_OK) e.status = RL_EHIP;
   }
   if (hipEventRecord(e.done, st) != hipSuccess && e.status == RL_OK) e.status = RL_EHIP;
   return h2d;
@@ -151,6 +173,12 @@ bool reap(rl_server* s) {
     const hipError_t q = hipEventQuery(e.done);
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess && e.status == RL_OK) e.status = RL_EHIP;
+    if (e.status == RL_OK) e.status = status_of_flags(((volatile uint32_t*)s->slot_words)[e.slot]);
+    s->free_slots.push_back(e.slot);
+    if (e.stage_off != UINT64_MAX) {
+      s->pool.release(e.stage_off);
+      e.stage_off = UINT64_MAX;
+    }
     e.state = EvState::DONE;
     e.done_at = Clock::now();
     const double ms = std::chrono::duration<double, std::milli>(e.done_at - e.submitted).count();
@@ -195,8 +223,9 @@ void scheduler_loop(rl_server* s) {
 extern "C" rl_status rl_server_create(const rl_server_opts* opts, rl_server** out) {
   if (!opts || !out) return fail(RL_EINVAL, "rl_server_create: NULL argument");
   *out = nullptr;
-  if (!opts->budget_bytes || !opts->max_in_flight || !opts->n_streams || opts->n_streams > 64)
-    return fail(RL_EINVAL, "budget, slots and 1..64 streams are required");
+  if (!opts->budget_bytes || !opts->max_in_flight || !opts->n_streams || opts->n_streams > 64 ||
+      opts->max_in_flight > 65536)
+    return fail(RL_EINVAL, "budget, 1..65536 slots and 1..64 streams are required");
   auto s = std::make_unique<rl_server>();
   s->opts = *opts;
   hipError_t e = hipGetDevice(&s->device);
@@ -205,10 +234,22 @@ extern "C" rl_status rl_server_create(const rl_server_opts* opts, rl_server** ou
     return fail(RL_ENOMEM, "serving pool of %llu bytes: %s", (unsigned long long)opts->budget_bytes,
                 hipGetErrorString(e));
   s->pool.reset(opts->budget_bytes, 256);
+  if ((e = hipHostMalloc((void**)&s->slot_words, opts->max_in_flight * sizeof(uint32_t), hipHostMallocDefault)) !=
+      hipSuccess) {
+    (void)hipFree(s->slab);
+    return hip_fail(e, "hipHostMalloc(status words)");
+  }
+  if ((e = hipHostGetDevicePointer((void**)&s->slot_words_dev, s->slot_words, 0)) != hipSuccess) {
+    (void)hipHostFree(s->slot_words);
+    (void)hipFree(s->slab);
+    return hip_fail(e, "hipHostGetDevicePointer(status words)");
+  }
+  for (uint32_t k = opts->max_in_flight; k-- > 0;) s->free_slots.push_back(k);
   for (uint32_t k = 0; k < opts->n_streams; ++k) {
     hipStream_t st;
     if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
       for (auto x : s->streams) (void)hipStreamDestroy(x);
+      (void)hipHostFree(s->slot_words);
       (void)hipFree(s->slab);
       return hip_fail(e, "hipStreamCreate");
     }
@@ -249,12 +290,16 @@ extern "C" rl_status rl_server_submit(rl_server* s, const rl_event* ev, uint64_t
     }
     c.dst_bytes.resize(layout_n_buffers(it.dst_layout));
     layout_buffer_bytes(it.dst_layout, it.n, c.dst_mcap.empty() ? nullptr : c.dst_mcap.data(), c.dst_bytes.data());
+    rl_xfer_opts o{RL_XFER_AUTO};
+    if (it.n && transfer_is_staged(it.src, &o))
+      e->stage_need = std::max<uint64_t>(e->stage_need, staging_bytes(it.src, it.n));
     e->items.push_back(std::move(c));
   }
   e->bytes = event_bytes(*e);
-  if (e->bytes > s->pool.capacity())
-    return fail(RL_EBUDGET, "event needs %llu bytes, budget is %llu", (unsigned long long)e->bytes,
-                (unsigned long long)s->pool.capacity());
+  const uint64_t need = e->bytes + (e->stage_need + 255) / 256 * 256;
+  if (need > s->pool.capacity())
+    return fail(RL_EBUDGET, "event needs %llu bytes (results and staging), budget is %llu",
+                (unsigned long long)need, (unsigned long long)s->pool.capacity());
   hipError_t he = hipEventCreateWithFlags(&e->done, hipEventDisableTiming);
   if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
   std::lock_guard<std::mutex> lk(s->mu);
@@ -308,7 +353,8 @@ extern "C" rl_status rl_server_release(rl_server* s, uint64_t ticket) {
   Event* e = it->second.get();
   if (e->state != EvState::DONE) return fail(RL_EBUSY, "event %llu not done", (unsigned long long)ticket);
   for (auto& c : e->items)
-    for (size_t b = 0; b < c.dst_offsets.size(); ++b) s->pool.release(c.dst_offsets[b]);
+    for (size_t b = 0; b < c.dst_offsets.size(); ++b)
+      if (c.dst_offsets[b] != UINT64_MAX) s->pool.release(c.dst_offsets[b]);
   (void)hipEventDestroy(e->done);
   s->events.erase(it);
   s->cv_work.notify_one();
@@ -348,5 +394,6 @@ extern "C" void rl_server_destroy(rl_server* s) {
   for (auto& kv : s->events)
     if (kv.second->done) (void)hipEventDestroy(kv.second->done);
   if (s->slab) (void)hipFree(s->slab);
+  if (s->slot_words) (void)hipHostFree(s->slot_words);
   delete s;
 }

@@ -51,8 +51,11 @@ void* device_alias(void* p) {
   return (uint8_t*)a.devicePointer + (a.hostPointer ? off : 0);
 }
 
-// Stage every buffer of the host side whole.
-rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t stream, bool h2d) {
+// Stage every buffer of the host side whole, in `given` (device memory of
+// at least staging_bytes(), owned by the caller) or else in the staging
+// buffer of (device, stream).
+rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t stream, bool h2d,
+                 uint8_t* given, uint64_t given_bytes) {
   const rl_view& hv = h2d ? src : dst;
   const rl_layout* HL = hv.layout;
   const uint32_t nb = layout_n_buffers(HL);
@@ -66,10 +69,14 @@ rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t
   }
   // one staging buffer per (device, stream), reused in stream order; the
   // lock keeps the enqueue of one call from interleaving with another's
-  std::lock_guard<std::mutex> lk(g_stage_mu);
+  std::unique_lock<std::mutex> lk(g_stage_mu, std::defer_lock);
   uint8_t* stage = nullptr;
   hipError_t e;
-  {
+  if (given) {
+    if (given_bytes < total) return fail(RL_EINVAL, "staging block too small");
+    stage = given;
+  } else {
+    lk.lock();
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
     StageBuf& sbuf = g_stage[{dev, stream}];
@@ -112,8 +119,24 @@ rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t
 
 }  // namespace
 
+uint64_t staging_bytes(const rl_view& hv, uint64_t n) {
+  const uint32_t nb = layout_n_buffers(hv.layout);
+  std::vector<uint64_t> bytes(nb);
+  layout_buffer_bytes(hv.layout, n, hv.member_capacity, bytes.data());
+  uint64_t total = 0;
+  for (auto b : bytes) total += (b + 255) & ~255ull;
+  return total;
+}
+
+bool transfer_is_staged(const rl_view& hv, const rl_xfer_opts* opts) {
+  const rl_xfer_mode m = opts ? opts->mode : RL_XFER_AUTO;
+  if (m == RL_XFER_STAGED) return true;
+  if (m == RL_XFER_ZERO_COPY) return false;
+  return !hv.layout->schema->members.empty() || hv.layout->space != RL_SPACE_HOST_PINNED;
+}
+
 rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipStream_t stream,
-                        const rl_xfer_opts* opts) {
+                        const rl_xfer_opts* opts, uint8_t* stage, uint64_t stage_bytes) {
   std::vector<Range> rs, rd;
   rl_status st = validate_view(src, n, "src", &rs, false);
   if (st) return st;
@@ -163,12 +186,12 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
     if (st) return st;
     return enqueue_plan(plan, stream);
   }
-  return staged(*src, *dst, n, stream, h2d);
+  return staged(*src, *dst, n, stream, h2d, stage, stage_bytes);
 }
 
 }  // namespace rl
 
 extern "C" rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n, void* stream,
                                  const rl_xfer_opts* opts) {
-  return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts);
+  return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
 }

@@ -12,13 +12,16 @@ SENTINEL = 0xAB
 class Pair:
     """A layout built twice: in the library and in the oracle."""
 
-    def __init__(self, schema_pair, kind, width=0, storage=None, space="device"):
+    def __init__(self, schema_pair, kind, width=0, storage=None, space="device", slot_offsets=None,
+                 stride=None):
         self.sp = schema_pair
         self.kind, self.width, self.storage = kind, width, storage
-        self.lib = P.Layout(schema_pair.lib, kind, space=space, width=width, storage=storage)
+        self.lib = P.Layout(schema_pair.lib, kind, space=space, width=width, storage=storage,
+                            slot_offsets=slot_offsets, stride=stride or 0)
         # an AoSoA width of 0 ("auto", chosen by a batch) has no oracle layout until resolved
         self.orc = (None if kind == "aosoa" and width == 0
-                    else oracle.make_layout(schema_pair.orc, kind, width=width, storage=storage))
+                    else oracle.make_layout(schema_pair.orc, kind, width=width, storage=storage,
+                                            slot_offsets=slot_offsets, stride=stride))
 
 
 class SchemaPair:
@@ -27,8 +30,8 @@ class SchemaPair:
         self.lib = P.Schema(decl)
         self.orc = oracle.Schema(decl)
 
-    def layout(self, kind, width=0, storage=None, space="device"):
-        return Pair(self, kind, width, storage, space)
+    def layout(self, kind, width=0, storage=None, space="device", slot_offsets=None, stride=None):
+        return Pair(self, kind, width, storage, space, slot_offsets, stride)
 
 
 def narrowed_storage(decl):

@@ -31,8 +31,6 @@ KINDS = [("aos", 0), ("soa", 0), ("aosoa", 1), ("aosoa", 8), ("aosoa", 48)]
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(decl=schemas(), si=st.integers(0, 4), di=st.integers(0, 4), n=st.sampled_from([1, 7, 100, 1001]))
 def test_random_schemas_every_pair(decl, si, di, n):
-    if si == di:
-        return
     src_k, dst_k = KINDS[si], KINDS[di]
     if decl.offset_types and src_k[0] == "aos" and dst_k[0] == "aos":
         return   # not supported for jagged schemas

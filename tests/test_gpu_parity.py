@@ -58,8 +58,6 @@ def _check(decl, src_kind, dst_kind, n, seed=0, narrow=False, shuffle=True, mean
 @pytest.mark.parametrize("src_kind", _kinds(), ids=str)
 @pytest.mark.parametrize("dst_kind", _kinds(), ids=str)
 def test_dense_pairs(decl, src_kind, dst_kind):
-    if src_kind == dst_kind:
-        pytest.skip("same layout")
     _check(decl, src_kind, dst_kind, 1037, seed=1)
 
 

@@ -141,3 +141,42 @@ def test_event_larger_than_budget_is_refused():
         ev.submit(srv, 0)
     assert e.value.status == P.RL_EBUDGET
     srv.close()
+
+
+def test_each_event_reports_its_own_device_status():
+    """One event whose jagged source has a member block past the end of its
+    pool (the kernels' bounds check rejects it, nothing is read out of
+    bounds): that event alone reports RL_EBOUNDS, every other event's
+    result is the oracle's."""
+    from tests import npref
+    ev = Events(12, scale=10, seed=2024)
+    bad_e = 5
+    item = ev.events[bad_e][2]                       # the cluster collection
+    rec = item["view"].tensors[0].numpy().view(npref.record_dtype(W.CLUSTER))
+    i = int(np.nonzero(rec["len0"])[0][0])
+    rec["ptr0"][i] = item["view"].tensors[1].numel() - 8
+    srv = P.Server(1 << 30, max_in_flight=8, n_streams=4)
+    tickets = [ev.submit(srv, e) for e in range(len(ev.events))]
+    for e, t in enumerate(tickets):
+        res = srv.wait(t)
+        if e == bad_e:
+            assert res["status"] == P.RL_EBOUNDS
+        else:
+            assert res["status"] == 0, (e, res["status"])
+            ev.check(e, res)
+    for t in tickets:
+        srv.release(t)
+    srv.close()
+
+
+def test_zero_object_items_take_no_pool_block():
+    """An event whose collections hold no objects fits a budget of its
+    (zero) result bytes and completes."""
+    ev = Events(1, scale=10)
+    srv = P.Server(1 << 20, max_in_flight=2, n_streams=1)
+    items = [(it["view"], ev.dst[j].lib, 0) for j, it in enumerate(ev.events[0])]
+    t = srv.submit(items)
+    res = srv.wait(t, timeout_ms=20_000)
+    assert res is not None and res["status"] == 0
+    srv.release(t)
+    srv.close()
