@@ -50,7 +50,8 @@ typedef enum rl_status {
   RL_EUNSUPPORTED = 8,  /* a valid request this library does not perform */
   RL_EHIP = 9,          /* a HIP runtime call failed (message has its text) */
   RL_EBUSY = 10,        /* the object is in use (e.g. ticket not complete) */
-  RL_EBOUNDS = 11       /* a source member block outside its pool/columns, or misaligned */
+  RL_EBOUNDS = 11,      /* a source member block outside its pool/columns, or misaligned */
+  RL_ELIMIT = 12        /* a request beyond a fixed size limit of the library */
 } rl_status;
 
 /* Scalar types of a property (Sec. VI: per-item properties hold one native
@@ -248,6 +249,25 @@ typedef struct rl_xfer_opts {
  * Zero-copy needs pinned host memory.  Errors as rl_convert. */
 rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n,
                       void* stream, const rl_xfer_opts* opts);
+
+/* rl_transfer for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and errors as rl_transfer, but the call makes
+ * no device or pinned-memory allocation (no hipMalloc / hipFree): staged
+ * transfers stage the host side in a fixed device array of the library
+ * (RL_TRANSFER_NOALLOC_LIMIT bytes = 32 MiB; one copy per device, held
+ * from library load until the process ends) instead of the library's
+ * per-stream staging buffers.  A staged transfer whose host side needs
+ * more than the limit (every host buffer rounded up to 256 bytes) returns
+ * RL_ELIMIT and enqueues nothing; zero-copy transfers need no staging and
+ * have no limit.  Every call on one device shares that device's array:
+ * calls whose work overlaps in time (on different streams, or from
+ * different threads) race and give unspecified results; calls on one
+ * stream are ordered by it.  The array keeps the last call's bytes; no
+ * result depends on its earlier contents. */
+#define RL_TRANSFER_NOALLOC_LIMIT (32ull << 20)
+rl_status rl_transfer_noalloc(const rl_view* src, const rl_view* dst, uint64_t n,
+                              void* stream, const rl_xfer_opts* opts);
 
 /* Wait for `stream`, then return (and clear) the device status word of
  * that stream: RL_EOVERFLOW, RL_ECAPACITY or RL_EBOUNDS (in that order of

@@ -19,9 +19,12 @@ LIB_PATH = os.path.join(_HERE, "librelayout.so")
 
 RL_OK, RL_EINVAL, RL_EALIGN, RL_EOVERLAP, RL_ECAPACITY, RL_EOVERFLOW = 0, 1, 2, 3, 4, 5
 RL_ENOMEM, RL_EBUDGET, RL_EUNSUPPORTED, RL_EHIP, RL_EBUSY, RL_EBOUNDS = 6, 7, 8, 9, 10, 11
+RL_ELIMIT = 12
+# staging limit of rl_transfer_noalloc (RL_TRANSFER_NOALLOC_LIMIT in the header)
+TRANSFER_NOALLOC_LIMIT = 32 << 20
 STATUS_NAMES = {0: "RL_OK", 1: "RL_EINVAL", 2: "RL_EALIGN", 3: "RL_EOVERLAP", 4: "RL_ECAPACITY",
                 5: "RL_EOVERFLOW", 6: "RL_ENOMEM", 7: "RL_EBUDGET", 8: "RL_EUNSUPPORTED",
-                9: "RL_EHIP", 10: "RL_EBUSY", 11: "RL_EBOUNDS"}
+                9: "RL_EHIP", 10: "RL_EBUSY", 11: "RL_EBOUNDS", 12: "RL_ELIMIT"}
 TYPES = ["u8", "i8", "u16", "i16", "u32", "i32", "u64", "i64", "f32", "f64"]
 KINDS = {"aos": 0, "soa": 1, "aosoa": 2}
 SPACES = {"device": 0, "host": 1, "pinned": 2}
@@ -108,6 +111,7 @@ SIGNATURES = {
     "rl_convert": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP]),
     "rl_offsets": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint32, ctypes.c_uint64, _P(ctypes.c_uint64), _VP]),
     "rl_transfer": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
+    "rl_transfer_noalloc": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
     "rl_sync": (ctypes.c_int, [_VP]),
     "rl_last_error": (ctypes.c_char_p, []),
     "rl_batch_create": (ctypes.c_int, [_P(rl_batch_opts), _P(_VP)]),
@@ -282,6 +286,13 @@ def sync(stream=None):
 def transfer(src: View, dst: View, n: int, stream=None, mode="auto"):
     o = rl_xfer_opts(XFER_MODES[mode])
     check(lib().rl_transfer(src.ref(), dst.ref(), n, stream_ptr(stream), ctypes.byref(o)), "rl_transfer")
+
+
+def transfer_noalloc(src: View, dst: View, n: int, stream=None, mode="auto"):
+    """rl_transfer_noalloc: rl_transfer without allocation (fixed staging)."""
+    o = rl_xfer_opts(XFER_MODES[mode])
+    check(lib().rl_transfer_noalloc(src.ref(), dst.ref(), n, stream_ptr(stream), ctypes.byref(o)),
+          "rl_transfer_noalloc")
 
 
 class Server:

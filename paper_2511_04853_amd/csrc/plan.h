@@ -79,5 +79,6 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
                         const rl_xfer_opts* opts, uint8_t* stage, uint64_t stage_bytes);
 uint64_t staging_bytes(const rl_view& host_view, uint64_t n);
 bool transfer_is_staged(const rl_view& host_view, const rl_xfer_opts* opts);
+bool is_host(rl_space s);
 
 }  // namespace rl

@@ -26,6 +26,8 @@
 
 namespace rl {
 
+bool is_host(rl_space s) { return s == RL_SPACE_HOST || s == RL_SPACE_HOST_PINNED; }
+
 namespace {
 
 struct StageBuf {
@@ -34,8 +36,6 @@ struct StageBuf {
 };
 std::mutex g_stage_mu;
 std::map<std::pair<int, hipStream_t>, StageBuf> g_stage;   // held until the process ends
-
-bool is_host(rl_space s) { return s == RL_SPACE_HOST || s == RL_SPACE_HOST_PINNED; }
 
 // Device address of pinned host memory (or nullptr if not pinned).
 void* device_alias(void* p) {
@@ -194,4 +194,58 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
 extern "C" rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n, void* stream,
                                  const rl_xfer_opts* opts) {
   return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
+}
+
+// ------------------------------------------------------------------ no-allocation variant
+//
+// Staging memory of rl_transfer_noalloc: a fixed array in the code object.
+// Every device the library is loaded on holds its own copy until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address on the current device comes from hipGetSymbolAddress and is the
+// only form passed to copies and kernels.
+namespace {
+constexpr uint64_t kNoAllocStageBytes = RL_TRANSFER_NOALLOC_LIMIT;
+__device__ __align__(256) uint8_t scratch[kNoAllocStageBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch_ptr;   // device -> address of that device's scratch
+
+rl_status scratch_on_current_device(uint8_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return rl::hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+      return rl::hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return rl::fail(RL_EHIP, "hipGetSymbolAddress(scratch) gave a null address");
+    it = g_scratch_ptr.emplace(dev, (uint8_t*)p).first;
+  }
+  *out = it->second;
+  return RL_OK;
+}
+}  // namespace
+
+extern "C" rl_status rl_transfer_noalloc(const rl_view* src, const rl_view* dst, uint64_t n, void* stream,
+                                         const rl_xfer_opts* opts) {
+  // the staged path is the only one that needs memory of the library; the
+  // limit is checked before anything is enqueued
+  const bool one_host = src && dst && src->layout && dst->layout &&
+                        rl::is_host(src->layout->space) != rl::is_host(dst->layout->space);
+  if (!one_host || n == 0) return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
+  const rl_view& hv = rl::is_host(src->layout->space) ? *src : *dst;
+  if (!rl::transfer_is_staged(hv, opts)) return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
+  if (n > hv.capacity) return rl::fail(RL_EINVAL, "n %llu over the host view's capacity", (unsigned long long)n);
+  if (!hv.layout->schema->members.empty() && !hv.member_capacity)
+    return rl::fail(RL_EINVAL, "member capacities of the host view are NULL");
+  const uint64_t need = rl::staging_bytes(hv, n);
+  if (need > kNoAllocStageBytes)
+    return rl::fail(RL_ELIMIT, "rl_transfer_noalloc stages at most %llu bytes; this transfer needs %llu",
+                    (unsigned long long)kNoAllocStageBytes, (unsigned long long)need);
+  uint8_t* stage = nullptr;
+  rl_status st = scratch_on_current_device(&stage);
+  if (st) return st;
+  return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, stage, kNoAllocStageBytes);
 }

@@ -187,3 +187,14 @@ def test_auto_width_layout_is_batch_only():
     a = _fake_view(sp.layout("aos"), 100, 1 << 40)
     d = _fake_view(auto, 100, 1 << 42)
     assert P.lib().rl_convert(a.ref(), d.ref(), 10, ctypes.c_void_p(0)) == P.RL_EINVAL
+
+
+def test_noalloc_limit_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+RL_TRANSFER_NOALLOC_LIMIT\s+\((\d+)ull\s*<<\s*(\d+)\)", text)
+    assert m, "RL_TRANSFER_NOALLOC_LIMIT not found"
+    assert int(m.group(1)) << int(m.group(2)) == P.TRANSFER_NOALLOC_LIMIT
+    src = open(os.path.join(ROOT, "paper_2511_04853_amd", "csrc", "transfer.cpp")).read()
+    # the staging array is a fixed device array, reached only through hipGetSymbolAddress
+    assert re.search(r"__device__\s+__align__\(256\)\s+uint8_t\s+scratch\[", src)
+    assert "hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))" in src
