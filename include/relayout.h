@@ -208,7 +208,14 @@ typedef struct rl_view {
  * with jagged groups; unsupported storage change).
  * Device errors (rl_sync): RL_EOVERFLOW, RL_ECAPACITY, RL_EBOUNDS; dst is
  * then unspecified but no memory outside the views is touched.
- * n == 0: RL_OK, nothing enqueued. */
+ * n == 0: RL_OK, nothing enqueued.
+ * Records with one jagged group of packed 4-byte member words convert in
+ * one kernel whose work-groups pass running member totals to each other
+ * through a small per-stream device buffer of the library (8 bytes per
+ * tile; allocated on the stream's first such call, grown when needed,
+ * held until the process ends); callers that cannot allocate use
+ * rl_transfer_noalloc.  Under stream capture the multi-kernel path, which
+ * needs no such buffer, is taken. */
 rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t n,
                      void* stream);
 
@@ -263,7 +270,9 @@ rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n,
  * have no limit.  Every call on one device shares that device's array:
  * calls whose work overlaps in time (on different streams, or from
  * different threads) race and give unspecified results; calls on one
- * stream are ordered by it.  The array keeps the last call's bytes; no
+ * stream are ordered by it.  The array
+ * also holds the look-back state of jagged conversions (1 MiB after the
+ * staging bytes).  The array keeps the last call's bytes; no
  * result depends on its earlier contents. */
 #define RL_TRANSFER_NOALLOC_LIMIT (32ull << 20)
 rl_status rl_transfer_noalloc(const rl_view* src, const rl_view* dst, uint64_t n,

@@ -107,6 +107,7 @@ rl_status plan_all(rl_batch* b, const Config& c) {
   shape.tile = c.tile;
   shape.threads = c.threads;
   shape.direct = shape_from_env().direct;
+  shape.fused = 0;   // batches run their jagged items through the table kernels
   for (auto& it : b->items) {
     Plan p;
     if (it.n) {

@@ -455,7 +455,10 @@ rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>&
 
 namespace rl {
 // Tile shape override for experiments and the tile-independence tests:
-// RL_TILE_OBJECTS (objects per tile), RL_BLOCK_THREADS, RL_GRID_BLOCKS.
+// RL_TILE_OBJECTS (objects per tile), RL_BLOCK_THREADS, RL_GRID_BLOCKS;
+// RL_DST_DIRECT, RL_SOURCE_DMA and RL_JAGGED_FUSED (0 turns a path off;
+// RL_JAGGED_FUSED=2 makes a jagged records conversion fail with
+// RL_EUNSUPPORTED where the single-pass kernel does not apply).
 PlanShape shape_from_env() {
   PlanShape s;
   if (const char* v = getenv("RL_TILE_OBJECTS")) s.tile = (uint32_t)strtoul(v, nullptr, 10);
@@ -466,6 +469,7 @@ PlanShape shape_from_env() {
   if (const char* v = getenv("RL_GRID_BLOCKS")) s.grid = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_DST_DIRECT")) s.direct = atoi(v) ? -1 : 0;
   if (const char* v = getenv("RL_SOURCE_DMA")) s.dma = atoi(v) ? -1 : 0;
+  if (const char* v = getenv("RL_JAGGED_FUSED")) s.fused = atoi(v) == 2 ? 2 : atoi(v) ? -1 : 0;
   return s;
 }
 }  // namespace rl
@@ -489,7 +493,9 @@ extern "C" rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t
     return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
   if (n == 0) return RL_OK;
   Plan plan;
-  if ((st = make_plan(*src, *dst, n, shape_from_env(), &plan))) return st;
+  PlanShape shape = shape_from_env();
+  if (stream_capturing((hipStream_t)stream)) shape.fused = 0;
+  if ((st = make_plan(*src, *dst, n, shape, &plan))) return st;
   return enqueue_plan(plan, (hipStream_t)stream);
 }
 

@@ -559,16 +559,17 @@ __device__ __forceinline__ void put(uint8_t* p, T v) {
   else *reinterpret_cast<T*>(p) = v;
 }
 
+// Threads tx of ntx (normally the whole work-group) take part.
 template <uint32_t SK, uint32_t DK, bool FULL, bool DIRECT, class DD>
 __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
-                                               uint32_t o0, uint32_t cnt) {
+                                               uint32_t o0, uint32_t cnt, uint32_t tx, uint32_t ntx) {
   constexpr uint32_t P = kObjPerThread;
-  const uint32_t nt = blockDim.x;
+  const uint32_t nt = ntx;
   uint32_t sa[P], sb[P], da[P], db[P];
   bool ok[P];
 #pragma unroll
   for (uint32_t k = 0; k < P; ++k) {
-    const uint32_t o = o0 + threadIdx.x + k * nt;
+    const uint32_t o = o0 + tx + k * nt;
     ok[k] = FULL || o < cnt;
     obj_terms<SK>(d.src, o, sa[k], sb[k]);
     obj_terms<DK>(d.dst, o, da[k], db[k]);
@@ -684,13 +685,13 @@ __device__ __forceinline__ void check_staged(const DD& d, const uint8_t* run, ui
 // Unused slots of the last AoSoA block of a partial tile, written as zeros
 // in global memory (the image path zero-fills its LDS image instead).
 template <class DD>
-__device__ __forceinline__ void zero_tail_direct(const DD& d, uint64_t i0, uint32_t cnt) {
+__device__ __forceinline__ void zero_tail_direct(const DD& d, uint64_t i0, uint32_t cnt, uint32_t tx, uint32_t ntx) {
   const auto& s = d.dst;
   const uint32_t end = s.width == 1 ? cnt : __umulhi(cnt + s.width - 1, s.width_magic) * s.width;
   uint8_t* const Dtile = s.base + i0 * s.obj_bytes;
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
     const auto& L = d.leaf[c];
-    for (uint32_t o = cnt + threadIdx.x; o < end; o += blockDim.x) {
+    for (uint32_t o = cnt + tx; o < end; o += ntx) {
       uint32_t a, b;
       obj_terms<KIND_AOSOA>(s, o, a, b);
       uint8_t* p = Dtile + a + L.dst_off + b * L.dst_size;
@@ -706,13 +707,13 @@ __device__ __forceinline__ void zero_tail_direct(const DD& d, uint64_t i0, uint3
 
 template <uint32_t SK, uint32_t DK, bool DIRECT, class DD>
 __device__ __forceinline__ void transform_kinds(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
-                                                uint32_t cnt) {
-  const uint32_t per_pass = kObjPerThread * blockDim.x;
+                                                uint32_t cnt, uint32_t tx = threadIdx.x, uint32_t ntx = blockDim.x) {
+  const uint32_t per_pass = kObjPerThread * ntx;
   for (uint32_t o0 = 0; o0 < cnt; o0 += per_pass) {
-    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true, DIRECT>(d, m, lt, i0, o0, cnt);
-    else transform_pass<SK, DK, false, DIRECT>(d, m, lt, i0, o0, cnt);
+    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true, DIRECT>(d, m, lt, i0, o0, cnt, tx, ntx);
+    else transform_pass<SK, DK, false, DIRECT>(d, m, lt, i0, o0, cnt, tx, ntx);
   }
-  if (DIRECT && DK == KIND_AOSOA) zero_tail_direct(d, i0, cnt);
+  if (DIRECT && DK == KIND_AOSOA) zero_tail_direct(d, i0, cnt, tx, ntx);
 }
 
 // Direct destinations (SoA columns, AoSoA blocks): each leaf of a wave's
@@ -1094,6 +1095,389 @@ __global__ void rebase_kernel(const RebaseDesc d) {
   rebase_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x, d.n, d.status);
 }
 
+// ------------------------------------------------------------------ single-pass jagged forward
+//
+// AoS records holding (pointer, count) pairs of one jagged group, member
+// records of NW packed 4-byte words, into an offsets column and member
+// columns, in one kernel (Sec. VI: the prefix sum of the member counts).
+// Work-group b converts tile b.  Per tile:
+//  1. the records arrive in LDS by DMA;
+//  2. their counts are scanned (tile-local exclusive offsets, aggregate A)
+//     and A is published at once in the tile's look-back word;
+//  3. the per-object leaves go straight to their destination;
+//  4. the first staging pass of the tile's members is DMA'd from the pool
+//     into LDS columns by tile-local member index;
+//  5. meanwhile the tile's prefix P (the members of all earlier tiles) is
+//     assembled by a block-wide look-back: in rounds of up to four words
+//     per thread, every earlier tile's word is read at once, back to the
+//     nearest tile that has published its inclusive prefix; a tile whose
+//     word is not there yet is summed from its records in global memory
+//     instead of being waited for.  P + A is published;
+//  6. the offsets (P + local) and the members (at P + local index) are
+//     stored at their final places.
+// No work-group ever waits for another, so no dispatch order or residency
+// is assumed, and no atomic read-modify-write is used (same-address
+// atomics serialise at about 11 ns each on this chip).
+//
+// Look-back words: bits 63..62 state (1: aggregate, 2: inclusive prefix),
+// bits 61..40 the launch epoch (low 22 bits; the host numbers the launches
+// on each look-back buffer), bits 39..0 the value, saturated at 2^40 - 1
+// (any member total that large exceeds every capacity; the plan only uses
+// this kernel for capacities below 2^39).  A word of another launch counts
+// as missing (a buffer would have to see 2^22 launches, all with fewer
+// tiles, for an old word to carry the current epoch).
+
+constexpr uint32_t kLbEpochMask = (1u << 22) - 1;
+
+__device__ __forceinline__ uint64_t sat40(uint64_t v) { return v < kLookbackValueLimit ? v : kLookbackValueLimit; }
+
+__device__ __forceinline__ uint64_t lb_word(uint32_t state, uint32_t epoch, uint64_t v) {
+  return ((uint64_t)state << 62) | ((uint64_t)(epoch & kLbEpochMask) << 40) | sat40(v);
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
+  return __hip_atomic_load(gp(const_cast<uint64_t*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, 64));
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// LDS carve-up of the single-pass jagged kernel.
+struct JagLds {
+  uint8_t* img;        // records of the tile
+  uint64_t* loff;      // tile-local exclusive offsets, T + 1 entries (entry cnt = aggregate)
+  uint64_t* ptrs;      // pool byte offsets of the tile's objects
+  uint32_t* vlen;      // members readable per object (0 for a record outside its pool)
+  uint64_t* wsum;      // block scan: one u64 per wave + 1
+  uint64_t* rsum;      // look-back sums, one per wave
+  uint32_t* rmin;      // look-back minimum, one per wave
+  uint16_t* own;       // tile-local object of each member of a staging pass
+  uint32_t* stage;     // NW columns of (stage + 4) words
+};
+
+// LDS bytes before the staging columns: records, offsets, pointers,
+// counts, scan and look-back sums.
+template <class JD>
+__host__ __device__ __forceinline__ uint32_t jag_head_bytes(const JD& j) {
+  const uint32_t T = j.dense.tile;
+  return round16(j.dense.src.image_bytes) + round16((T + 1) * 8) + round16(T * 8) + round16(T * 4) +
+         round16(18 * 8) + round16(4 * 8) + round16(4 * 4) + round16(j.stage * 2);
+}
+
+template <class JD>
+__host__ __device__ __forceinline__ uint32_t jag_lds_layout(const JD& j) {
+  return jag_head_bytes(j) + j.words * (j.stage + 4) * 4;
+}
+
+template <class JD>
+__device__ __forceinline__ JagLds jag_carve(uint8_t* smem, const JD& j) {
+  const uint32_t T = j.dense.tile;
+  JagLds m;
+  uint8_t* p = smem;
+  m.img = p; p += round16(j.dense.src.image_bytes);
+  m.loff = reinterpret_cast<uint64_t*>(p); p += round16((T + 1) * 8);
+  m.ptrs = reinterpret_cast<uint64_t*>(p); p += round16(T * 8);
+  m.vlen = reinterpret_cast<uint32_t*>(p); p += round16(T * 4);
+  m.wsum = reinterpret_cast<uint64_t*>(p); p += round16(18 * 8);
+  m.rsum = reinterpret_cast<uint64_t*>(p); p += round16(4 * 8);
+  m.rmin = reinterpret_cast<uint32_t*>(p); p += round16(4 * 4);
+  m.own = reinterpret_cast<uint16_t*>(p); p += round16(j.stage * 2);
+  m.stage = reinterpret_cast<uint32_t*>(p);
+  return m;
+}
+
+// Member total of tile `tile` summed from its records in global memory by
+// the whole wave (for a tile whose look-back word did not arrive in time).
+template <class JD>
+__device__ __forceinline__ uint64_t jag_tile_total(const JD& j, uint64_t tile) {
+  const uint32_t T = j.dense.tile, stride = j.dense.src.stride;
+  const uint64_t i0 = tile * T;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(T, j.dense.n - i0);
+  const uint8_t* rec = j.dense.src.base + i0 * stride + j.len_off;
+  uint64_t s = 0;
+  for (uint32_t k = threadIdx.x & 63; k < cnt; k += 64) s += *gp(reinterpret_cast<const uint32_t*>(rec + (uint64_t)k * stride));
+  return wave_sum_u64(s);
+}
+
+// Prefix of tile t (t >= 1): the saturated member total of tiles 0 .. t-1,
+// assembled by one wave (its loads must not queue behind member DMAs of
+// the same wave: a wave's memory counter retires in order).  In rounds of
+// 64 x kLookbackPerLane words, every earlier tile's word is read at once,
+// back to the nearest tile with an inclusive prefix of this launch.  Words
+// that have not arrived are polled again for a bounded time (their tiles
+// are running and publish within microseconds); after that, a missing
+// tile's total is summed from its records, so no tile ever depends on
+// another work-group making progress.
+constexpr uint32_t kLookbackPerLane = 8;
+constexpr uint32_t kLookbackPolls = 256;   // a few hundred microseconds of polling before summing records
+
+template <class JD>
+__device__ uint64_t jag_look_back(const JD& j, const uint64_t* flags, uint64_t t, uint32_t epoch) {
+  constexpr uint32_t K = kLookbackPerLane;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t ep = epoch & kLbEpochMask;
+  auto valid = [&](uint64_t w) { return (w >> 62) != 0 && (uint32_t)((w >> 40) & kLbEpochMask) == ep; };
+  uint64_t prefix = 0;
+  uint64_t hi = t;   // this round: tiles hi - 1 - d for distances d = lane + 64 k
+  while (hi > 0) {
+    uint64_t w[K];
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) {
+      const uint64_t d = lane + 64ull * k;
+      w[k] = d < hi ? lb_load(flags + (hi - 1 - d)) : 0;
+    }
+    uint32_t near, missing;
+    for (uint32_t poll = 0;; ++poll) {
+      near = 0xFFFFFFFFu;   // nearest inclusive prefix of this launch
+#pragma unroll
+      for (uint32_t k = 0; k < K; ++k) {
+        const uint64_t d = lane + 64ull * k;
+        if (d < hi && (w[k] >> 62) == 2 && valid(w[k])) near = min(near, (uint32_t)d);
+      }
+      near = wave_min_u32(near);
+      missing = 0;   // words needed (up to the nearest prefix) and not there
+#pragma unroll
+      for (uint32_t k = 0; k < K; ++k) {
+        const uint64_t d = lane + 64ull * k;
+        if (d < hi && d <= near && !valid(w[k])) missing |= 1u << k;
+      }
+      if (!__any(missing != 0) || poll == kLookbackPolls) break;
+      __builtin_amdgcn_s_sleep(8);
+#pragma unroll
+      for (uint32_t k = 0; k < K; ++k)
+        if (missing & (1u << k)) w[k] = lb_load(flags + (hi - 1 - (lane + 64ull * k)));
+    }
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) {
+      const uint64_t d = lane + 64ull * k;
+      if (d < hi && d <= near && valid(w[k])) sum += w[k] & kLookbackValueLimit;
+    }
+    // still missing after the polls: the whole wave sums those tiles'
+    // records, one tile at a time
+    for (;;) {
+      const uint64_t b = __ballot(missing != 0);
+      if (!b) break;
+      const uint32_t src = (uint32_t)__builtin_ctzll(b);
+      const uint32_t mk = __shfl(missing, src, 64);
+      const uint32_t k = __builtin_ctz(mk);
+      const uint64_t total = jag_tile_total(j, hi - 1 - (src + 64ull * k));
+      if (lane == src) {
+        sum += total;
+        missing &= missing - 1;
+      }
+    }
+    prefix = sat40(prefix + wave_sum_u64(sat40(sum)));
+    if (near != 0xFFFFFFFFu) break;
+    hi = hi > 64ull * K ? hi - 64ull * K : 0;
+  }
+  return prefix;
+}
+
+// Owners (tile-local object index) of tile-local members [p0, p0 + pm)
+// into m.own[0 .. pm): each thread fills a contiguous run, finding the
+// owner of its first member by binary search over the tile-local offsets
+// and then stepping over object boundaries, so the work is spread by
+// members whatever the counts are.  All threads of the work-group take
+// part; a barrier must follow before m.own is read.
+__device__ __forceinline__ void jag_owners(const JagLds& m, uint32_t cnt, uint64_t p0, uint32_t pm) {
+  const uint32_t nt = blockDim.x;
+  const uint32_t R = (pm + nt - 1) / nt;
+  const uint32_t r0 = threadIdx.x * R, r1 = min(pm, r0 + R);
+  if (r0 >= r1) return;
+  const uint64_t k0 = p0 + r0;
+  uint32_t lo = 0, hi = cnt;   // last object whose first member is <= k0
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (m.loff[mid] <= k0) lo = mid; else hi = mid;
+  }
+  uint64_t next = m.loff[lo + 1];   // member k < total = loff[cnt], so lo + 1 <= cnt
+  for (uint32_t r = r0; r < r1; ++r) {
+    const uint64_t k = p0 + r;
+    while (k >= next) next = m.loff[++lo + 1];
+    m.own[r] = (uint16_t)lo;
+  }
+}
+
+// DMA the words of tile-local members [p0, p0 + pm) from the pool into the
+// LDS columns (slot k of a column holds member p0 + k); owners from m.own.
+// Members outside their record's validated block are not loaded (their
+// destination entries are then unspecified and the status says so).
+// Waves w0 .. w0 + nw - 1 of the work-group take part (the calling wave
+// must be one of them).
+template <uint32_t NW, class JD>
+__device__ __forceinline__ void jag_issue(const JD& j, const JagLds& m, uint64_t p0, uint32_t pm,
+                                          uint32_t w0, uint32_t nw) {
+  const uint32_t lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) - w0;
+  for (uint32_t vb = wave * 64; vb < pm; vb += nw * 64) {
+    const uint32_t k = vb + lane;
+    bool ok = k < pm;
+    const uint8_t* src = j.pool;
+    if (ok) {
+      const uint32_t o = m.own[k];
+      const uint64_t jj = p0 + k - m.loff[o];
+      ok = jj < m.vlen[o];
+      src = j.pool + m.ptrs[o] + jj * j.mstride;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < NW; ++q) {
+      uint32_t* col = m.stage + q * (j.stage + 4) + vb;
+      const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr)(uint8_t*)col);
+      if (ok) dma4(src + 4 * q, base);
+    }
+  }
+}
+
+// Store staged members [p0, p0 + pm) at destination index P + p0 + k, up
+// to the capacity: 16-byte vectors where the destination is aligned, words
+// at the ends.
+template <uint32_t NW, class JD>
+__device__ __forceinline__ void jag_store(const JD& j, const JagLds& m, uint64_t P, uint64_t p0, uint32_t pm) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t lo = P + p0;
+  const uint64_t hi = min<uint64_t>(lo + pm, j.capacity);
+  if (hi <= lo) return;
+  const uint64_t a0 = min<uint64_t>((lo + 3) & ~3ull, hi), a1 = max<uint64_t>(a0, hi & ~3ull);
+#pragma unroll
+  for (uint32_t q = 0; q < NW; ++q) {
+    const uint32_t* sq = m.stage + q * (j.stage + 4);   // destination index x at sq[x - lo]
+    RL_G uint32_t* col = gp(reinterpret_cast<uint32_t*>(j.mcol[q]));
+    for (uint32_t i = tid; lo + i < a0; i += nt) col[lo + i] = sq[i];
+    const uint32_t nv = (uint32_t)((a1 - a0) >> 2);
+    const uint32_t* s0 = sq + (a0 - lo);
+    RL_G v4u* cv = reinterpret_cast<RL_G v4u*>(col + a0);
+    for (uint32_t v = tid; v < nv; v += nt) {
+      const uint32_t* x = s0 + 4 * v;
+      cv[v] = v4u{x[0], x[1], x[2], x[3]};
+    }
+    for (uint64_t i = a1 + tid; i < hi; i += nt) col[i] = sq[i - lo];
+  }
+}
+
+template <uint32_t NW>
+__global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
+  extern __shared__ uint4 smem_raw[];
+  uint8_t* smem = reinterpret_cast<uint8_t*>(smem_raw);
+  const RL_C JaggedDesc& j = kernel_arg<JaggedDesc>();
+  const RL_C DenseDesc& d = j.dense;
+  const JagLds m = jag_carve(smem, j);
+  uint64_t* const flags = j.lookback;
+  uint32_t* const status = d.status;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t n = d.n;
+  const uint32_t T = d.tile;
+  const uint64_t t = blockIdx.x;
+  const uint64_t i0 = t * T;
+  if (i0 >= n) return;   // uniform
+  const uint32_t cnt = (uint32_t)min<uint64_t>(T, n - i0);
+  const uint32_t epoch = j.epoch;
+  LeafLanes lt;
+  load_lanes(d, 0, lt);
+  // 1. records
+  issue_source(d, smem, TileJob{1, 0, t, n, 0}, lt, true);
+  dma_wait();
+  __syncthreads();
+  // 2. counts: tile-local exclusive offsets, validated pool blocks
+  const uint32_t stride = d.src.stride;
+  const uint32_t per = (T + nt - 1) / nt;
+  const uint32_t o0 = tid * per;
+  const uint64_t pool_end = j.pool_bytes;
+  uint64_t sum = 0;
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t o = o0 + k;
+    if (o < cnt) sum += *reinterpret_cast<const uint32_t*>(m.img + o * stride + j.len_off);
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(sum, m.wsum, &total);
+  bool bad = false;
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t o = o0 + k;
+    if (o >= cnt) break;
+    const uint8_t* rec = m.img + o * stride;
+    const uint64_t len = *reinterpret_cast<const uint32_t*>(rec + j.len_off);
+    const uint64_t p = *reinterpret_cast<const uint64_t*>(rec + j.ptr_off);
+    const bool good = (p & (uint64_t)(j.malign - 1)) == 0 && p <= pool_end && len <= (pool_end - p) / j.mstride;
+    m.loff[o] = run;
+    m.ptrs[o] = p;
+    m.vlen[o] = good ? (uint32_t)len : 0u;
+    bad |= !good;
+    run += len;
+  }
+  if (bad) flag(status, ST_FLAG_BOUNDS);
+  // published from wave 1 where there is one: wave 0's look-back loads
+  // would otherwise wait for this store
+  if (tid == (nt > 64 ? 64u : 0u)) {
+    m.loff[cnt] = total;
+    lb_store(flags + t, lb_word(t == 0 ? 2u : 1u, epoch, total));
+  }
+  __syncthreads();   // tile-local offsets, pointers and counts in LDS
+  const uint64_t A = m.loff[cnt];
+  const uint32_t S = j.stage;
+  const uint32_t pm0 = (uint32_t)min<uint64_t>(A, S);
+  jag_owners(m, cnt, 0, pm0);
+  __syncthreads();
+  // 3.-5. wave 0 assembles the prefix while the other waves request the
+  // first members and store the per-object leaves (a one-wave work-group
+  // does the three in turn, the look-back first)
+  DenseLds dm;
+  dm.src = smem;
+  dm.dst = smem;
+  dm.wsum = m.wsum;
+  dm.offs = m.wsum;
+  const uint32_t wave = tid >> 6, nwaves = nt >> 6;
+  uint64_t P = 0;
+  if (wave == 0 && t > 0) P = jag_look_back(j, flags, t, epoch);
+  if (nwaves == 1 || wave > 0) {
+    const uint32_t w0 = nwaves == 1 ? 0 : 1;
+    jag_issue<NW>(j, m, 0, pm0, w0, nwaves - w0);
+    const uint32_t tx = tid - 64 * w0, ntx = nt - 64 * w0;
+    if (d.dst.kind == KIND_SOA) transform_kinds<KIND_AOS, KIND_SOA, true>(d, dm, lt, i0, cnt, tx, ntx);
+    else transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, dm, lt, i0, cnt, tx, ntx);
+  }
+  if (tid == 0) m.rsum[0] = P;
+  __syncthreads();
+  P = m.rsum[0];
+  if (tid == 0 && t > 0) lb_store(flags + t, lb_word(2u, epoch, P + A));
+  // 6. offsets, then members that land inside the destination capacity
+  //    (the loop is bounded by a real buffer whatever the counts say)
+  for (uint32_t o = tid; o < cnt; o += nt) store_off(j.offsets, j.off_type, i0 + o, P + m.loff[o]);
+  if (i0 + cnt == n && tid == 0) {
+    const uint64_t all = sat40(P + A);
+    store_off(j.offsets, j.off_type, n, all);
+    if (all > off_limit(j.off_type)) flag(status, ST_FLAG_OVERFLOW);
+    else if (all > j.capacity) flag(status, ST_FLAG_CAPACITY);
+  }
+  const uint64_t stored = min<uint64_t>(A, P < j.capacity ? j.capacity - P : 0);
+  for (uint64_t p0 = 0; p0 < stored; p0 += S) {
+    const uint32_t pm = (uint32_t)min<uint64_t>(S, stored - p0);
+    if (p0 > 0) {
+      jag_owners(m, cnt, p0, pm);
+      __syncthreads();
+      jag_issue<NW>(j, m, p0, pm, 0, nwaves);
+    }
+    dma_wait();
+    __syncthreads();
+    jag_store<NW>(j, m, P, p0, pm);
+    __syncthreads();
+  }
+}
+
+__global__ void zero_kernel(uint32_t* p, uint64_t words) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+    gp(p)[i] = 0u;
+}
+
 // Status words of streams: one per stream that has run a conversion (the
 // host assigns slots), so that reading and clearing one stream's word never
 // races with another stream's kernels.
@@ -1321,6 +1705,34 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+uint32_t jagged_lds_bytes(const JaggedDesc& j) { return jag_lds_layout(j); }
+
+hipError_t launch_jagged(const JaggedDesc& j, uint32_t threads, hipStream_t s) {
+  if (threads == 0 || threads > 256 || threads % 64 || !j.lookback || j.words < 1 || j.words > 4 ||
+      j.dense.tile == 0 || j.stage == 0)
+    return hipErrorInvalidValue;
+  const uint32_t lds = jagged_lds_bytes(j);
+  const uint64_t tiles = (j.dense.n + j.dense.tile - 1) / j.dense.tile;
+  if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
+  const uint64_t grid = tiles ? tiles : 1;
+  switch (j.words) {
+    case 1: hipLaunchKernelGGL(jagged_kernel<1>, dim3((uint32_t)grid), dim3(threads), lds, s, j); break;
+    case 2: hipLaunchKernelGGL(jagged_kernel<2>, dim3((uint32_t)grid), dim3(threads), lds, s, j); break;
+    case 3: hipLaunchKernelGGL(jagged_kernel<3>, dim3((uint32_t)grid), dim3(threads), lds, s, j); break;
+    default: hipLaunchKernelGGL(jagged_kernel<4>, dim3((uint32_t)grid), dim3(threads), lds, s, j); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s) {
+  if (((uintptr_t)p & 3) || (bytes & 3)) return hipErrorInvalidValue;
+  const uint64_t words = bytes / 4;
+  if (!words) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((words + 255) / 256, 1024);
+  hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), words);
+  return hipGetLastError();
 }
 
 hipError_t launch_take_status(uint32_t* status, uint32_t* out, hipStream_t s) {

@@ -3,6 +3,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 #include "plan.h"
@@ -302,6 +304,72 @@ static rl_status push_scan_gather(Plan* plan, const rl_view& src, const rl_view&
   return RL_OK;
 }
 
+// The single-pass jagged kernel: one jagged group read from AoS records
+// (pointer, count) into an offsets destination whose per-object leaves are
+// stored directly, member records of 1..4 packed 4-byte words into 16-byte
+// aligned member columns, a destination capacity below 2^39 (look-back
+// values saturate at 2^40).  Objects per tile are sized so that a tile's
+// members fill about three quarters of one LDS staging pass at the
+// destination's mean members per object.  Returns false (and leaves *out
+// unspecified) where it does not apply.
+static bool build_jagged(const rl_view& src, const rl_view& dst, uint64_t n, const PlanShape& shape,
+                         JaggedDesc* out) {
+  const rl_layout* SL = src.layout;
+  const rl_layout* DL = dst.layout;
+  const rl_schema* sc = SL->schema;
+  if (shape.fused == 0 || shape.direct == 0 || sc->members.size() != 1 || SL->kind != RL_AOS ||
+      DL->kind == RL_AOS || n == 0)
+    return false;
+  const uint64_t cap = dst.member_capacity[0];
+  if (cap >= (1ull << 39) || src.member_capacity[0] >= (1ull << 39)) return false;
+  const uint32_t nw = (uint32_t)sc->members[0].size();
+  if (nw < 1 || nw > 4 || SL->mstride[0] != 4 * nw) return false;
+  const uint32_t mb = group_buffer(DL, 0) + 1;
+  for (uint32_t m = 0; m < nw; ++m)
+    if (sc->members[0][m].size != 4 || SL->moff[0][m] != 4 * m || ((uintptr_t)dst.buffers[mb + m] & 15))
+      return false;
+  if (SL->ptr_off[0] % 8 || SL->len_off[0] % 4 || SL->stride % 8) return false;
+  SideSpec s = object_side(SL, src.buffers, 0);
+  SideSpec d = object_side(DL, dst.buffers, 0);
+  uint32_t unit = 16;
+  if (d.kind == KIND_AOSOA) unit = lcm32(unit, d.width);
+  if (unit > 512) return false;
+  const uint32_t S = jagged_stage_members(nw);
+  const uint64_t mean = std::max<uint64_t>(1, (cap + n - 1) / n);
+  uint32_t target = 512;
+  while (target > 16 && (uint64_t)target * mean > (uint64_t)S * 3 / 4) target /= 2;
+  if (shape.tile) target = std::min<uint32_t>(shape.tile, 512);
+  const uint32_t tile = std::max(unit, target / unit * unit);
+  JaggedDesc& j = *out;
+  memset(&j, 0, sizeof j);
+  if (build_dense(s, d, n, tile, &j.dense) != RL_OK) return false;
+  j.dense.dst_direct = 1;
+  if (!direct_ok(j.dense)) return false;
+  if (shape.dma == 0) j.dense.dma = 0;
+  j.offsets = (uint8_t*)dst.buffers[group_buffer(DL, 0)];
+  j.capacity = cap;
+  j.pool = (const uint8_t*)src.buffers[group_buffer(SL, 0)];
+  j.pool_bytes = src.member_capacity[0] * SL->mstride[0];
+  for (uint32_t m = 0; m < nw; ++m) j.mcol[m] = (uint8_t*)dst.buffers[mb + m];
+  j.ptr_off = SL->ptr_off[0];
+  j.len_off = SL->len_off[0];
+  j.mstride = SL->mstride[0];
+  j.malign = SL->malign[0];
+  j.words = nw;
+  j.off_type = (uint32_t)sc->offset_types[0];
+  j.stage = S;
+  // four work-groups per compute unit: members per staging pass shrink to
+  // fit 40 KB of LDS (a tile then takes more passes)
+  while (jagged_lds_bytes(j) > 40 * 1024 && j.stage > 256) j.stage -= 64;
+  if (jagged_lds_bytes(j) > kLdsBudget) return false;
+  const uint64_t need = lookback_bytes((n + tile - 1) / tile);
+  if (shape.lookback) {
+    if (need > shape.lookback_bytes) return false;
+    j.lookback = shape.lookback;
+  }
+  return true;
+}
+
 rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const PlanShape& shape,
                     Plan* plan) {
   const rl_layout* SL = src.layout;
@@ -311,6 +379,18 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
   uint32_t* const status = nullptr;   // stamped with the stream's word at enqueue
   if (ng && SL->kind == RL_AOS && DL->kind == RL_AOS)
     return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
+
+  {
+    Step js;
+    js.kind = Step::JAGGED;
+    if (build_jagged(src, dst, n, shape, &js.jagged)) {
+      js.threads = shape.threads ? std::min<uint32_t>(shape.threads, 256) : 256;
+      plan->steps.push_back(js);
+      return RL_OK;
+    }
+    if (shape.fused == 2 && ng && SL->kind == RL_AOS && n)
+      return fail(RL_EUNSUPPORTED, "the single-pass jagged kernel does not apply to this conversion");
+  }
 
   SideSpec s = object_side(SL, src.buffers, 0);
   SideSpec d = object_side(DL, dst.buffers, 0);
@@ -415,6 +495,54 @@ rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t g, 
   return RL_OK;
 }
 
+// Look-back memory of single-pass jagged steps, one buffer per (device,
+// stream), zeroed when allocated and reused in stream order; held until
+// the process ends.  Every buffer (these and those callers give) has a
+// launch counter that numbers the launches on it.
+namespace {
+struct LookbackBuf {
+  uint64_t* ptr = nullptr;
+  uint64_t bytes = 0;
+};
+std::mutex g_lb_mu;
+std::map<std::pair<int, hipStream_t>, LookbackBuf> g_lb;
+std::map<const uint64_t*, uint32_t> g_lb_launches;
+}  // namespace
+
+// The stream's look-back buffer with room for `need` bytes (caller holds g_lb_mu).
+static rl_status stream_lookback(hipStream_t s, uint64_t need, uint64_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  LookbackBuf& b = g_lb[{dev, s}];
+  if (b.bytes < need) {
+    if (b.ptr) {
+      // earlier work on this stream may still use the old buffer
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      (void)hipFree(b.ptr);
+      g_lb_launches.erase(b.ptr);
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    const uint64_t want = std::max<uint64_t>((need * 2 + 255) & ~255ull, 64 << 10);
+    if ((e = hipMalloc((void**)&b.ptr, want)) != hipSuccess)
+      return fail(RL_ENOMEM, "look-back buffer of %llu bytes: %s", (unsigned long long)want, hipGetErrorString(e));
+    if ((e = launch_zero(b.ptr, want, s)) != hipSuccess) return hip_fail(e, "zero look-back buffer");
+    b.bytes = want;
+  }
+  *out = b.ptr;
+  return RL_OK;
+}
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus c = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &c) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return c != hipStreamCaptureStatusNone;
+}
+
 rl_status enqueue_plan(const Plan& plan, hipStream_t stream) {
   // device-detected errors go to the status word of the launching stream
   uint32_t* const status = stream_status(stream);
@@ -427,6 +555,20 @@ rl_status enqueue_plan(const Plan& plan, hipStream_t stream) {
       case Step::SCAN_TOTALS: s.totals.status = status; e = launch_scan_totals(s.totals, stream); break;
       case Step::GATHER: s.gather.status = status; e = launch_gather(s.gather, s.threads, stream); break;
       case Step::REBASE: s.rebase.status = status; e = launch_rebase(s.rebase, stream); break;
+      case Step::JAGGED: {
+        s.jagged.dense.status = status;
+        const uint64_t tiles = (s.jagged.dense.n + s.jagged.dense.tile - 1) / s.jagged.dense.tile;
+        // the buffer and its launch counter stay locked until the kernel is
+        // enqueued (another thread may grow the buffer)
+        std::lock_guard<std::mutex> lk(g_lb_mu);
+        if (!s.jagged.lookback) {
+          rl_status st = stream_lookback(stream, lookback_bytes(tiles), &s.jagged.lookback);
+          if (st) return st;
+        }
+        s.jagged.epoch = ++g_lb_launches[s.jagged.lookback];
+        e = launch_jagged(s.jagged, s.threads, stream);
+        break;
+      }
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }

@@ -14,16 +14,25 @@ struct PlanShape {
   int direct = -1;        // destination values stored straight to global memory:
                           // -1 where the destination allows it, 0 never
   int dma = -1;           // source runs DMA'd into LDS: -1 where aligned, 0 never
+  int fused = -1;         // single-pass jagged kernel: -1 where it applies, 0 never,
+                          // 2 required (a jagged records source fails where it does not apply)
+  // Look-back memory of single-pass jagged steps given by the caller
+  // (zeroed before its first use, used by one stream at a time); null:
+  // the library's per-stream buffer.  A step needing more tiles than it
+  // holds takes the multi-kernel path.
+  uint64_t* lookback = nullptr;
+  uint64_t lookback_bytes = 0;
 };
 
 struct Step {
-  enum Kind { DENSE, SCAN_TOTALS, GATHER, REBASE } kind;
+  enum Kind { DENSE, SCAN_TOTALS, GATHER, REBASE, JAGGED } kind;
   uint32_t threads = 256;
   uint32_t grid = 0;
   DenseDesc dense;
   ScanTotalsDesc totals;
   GatherDesc gather;
   RebaseDesc rebase;
+  JaggedDesc jagged;
 };
 
 struct Plan {
@@ -70,13 +79,17 @@ rl_status make_offsets_plan(const rl_view& src, const rl_view& dst, uint32_t gro
                             const PlanShape& shape, Plan* plan);
 rl_status enqueue_plan(const Plan& plan, hipStream_t stream);
 PlanShape shape_from_env();
+// Whether `s` is being captured into a graph (single-pass jagged steps
+// number their launches on the host, so they are not captured).
+bool stream_capturing(hipStream_t s);
 bool auto_width(const rl_view* v);
 
 // Host <-> device transfer (rl_transfer) with an optional staging block
 // owned by the caller (device memory of at least staging_bytes(host view)
 // bytes; nullptr: the library's per-stream staging buffer).
 rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipStream_t stream,
-                        const rl_xfer_opts* opts, uint8_t* stage, uint64_t stage_bytes);
+                        const rl_xfer_opts* opts, uint8_t* stage, uint64_t stage_bytes,
+                        uint64_t* lookback = nullptr, uint64_t lookback_bytes = 0);
 uint64_t staging_bytes(const rl_view& host_view, uint64_t n);
 bool transfer_is_staged(const rl_view& host_view, const rl_xfer_opts* opts);
 bool is_host(rl_space s);

@@ -165,6 +165,35 @@ struct RebaseDesc {
   uint32_t* status;
 };
 
+// Single-pass conversion of AoS records holding one jagged group's
+// (pointer, count) pairs into an offsets column and member columns, for
+// member records of 1..4 packed 4-byte words: one work-group per tile does
+// the per-object leaves (as a dense step), the scan of the counts, a
+// look-back over the tiles before it for the tile's prefix, the offsets
+// and the members.
+struct JaggedDesc {
+  DenseDesc dense;         // per-object leaves of the records: source records, tile, direct stores
+  uint8_t* offsets;        // destination offsets column (n + 1 entries)
+  uint64_t capacity;       // destination member capacity
+  const uint8_t* pool;     // source member pool
+  uint64_t pool_bytes;
+  uint64_t* lookback;      // one 64-bit word per tile
+  uint8_t* mcol[4];        // destination member columns (16-byte aligned)
+  uint32_t ptr_off;        // u64 byte offset into the pool, in a record
+  uint32_t len_off;        // u32 member count, in a record
+  uint32_t mstride;        // member record bytes (4 * words)
+  uint32_t malign;         // member record alignment
+  uint32_t words;          // 1..4
+  uint32_t off_type;       // rl_type of the offsets
+  uint32_t stage;          // members per LDS staging pass
+  uint32_t epoch;          // launch number on this look-back buffer (set at enqueue)
+};
+// Look-back memory: one word per tile, zero before its first use; launches
+// on one buffer must be ordered (one stream) and numbered by the host.
+inline uint64_t lookback_bytes(uint64_t tiles) { return tiles * 8; }
+// Counts and prefixes in look-back words are kept below 2^40 (saturating).
+constexpr uint64_t kLookbackValueLimit = (1ull << 40) - 1;
+
 // Device-resident tables of a batch: every step of every item, grouped by
 // the kernel that runs it.  Prefix arrays have one entry per item plus one.
 struct BatchTables {
@@ -198,6 +227,13 @@ hipError_t launch_scan_totals(const ScanTotalsDesc& d, hipStream_t s);
 hipError_t launch_gather(const GatherDesc& d, uint32_t threads, hipStream_t s);
 hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s);
 hipError_t launch_take_status(uint32_t* status, uint32_t* out, hipStream_t s);
+// One work-group per tile.
+hipError_t launch_jagged(const JaggedDesc& j, uint32_t threads, hipStream_t s);
+uint32_t jagged_lds_bytes(const JaggedDesc& j);
+// Members per staging pass of the single-pass jagged kernel (32 KB of words).
+constexpr uint32_t jagged_stage_members(uint32_t words) { return (8192 / words) / 64 * 64; }
+// Zero `bytes` of device memory with a kernel (usable where a memset node is not).
+hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
 // Device address of the status words of the current device.
 hipError_t status_words(uint32_t** out);
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,

@@ -61,10 +61,17 @@ struct Event {
 
 }  // namespace
 
+// Look-back bytes per server stream: single-pass jagged conversions of up
+// to 32,768 tiles; larger collections take the multi-kernel path.
+constexpr uint64_t kServerLookbackBytes = 256 << 10;
+
 struct rl_server {
   rl_server_opts opts{};
   int device = 0;
   std::vector<hipStream_t> streams;
+  // per stream: look-back state of single-pass jagged conversions, carved
+  // from the slab at creation and zeroed once (reused in stream order)
+  std::vector<uint64_t*> lookback;
   uint8_t* slab = nullptr;
   SlabAllocator pool;
   // one pinned word per in-flight slot: the device status flags of the
@@ -148,7 +155,8 @@ uint64_t launch(rl_server* s, Event& e) {
     rl_xfer_opts o{RL_XFER_AUTO};
     // items of an event run one after another on its stream, so they share
     // the event's staging block
-    const rl_status r = transfer_impl(&sv, &dv, it.n, st, &o, stage, e.stage_need);
+    const rl_status r = transfer_impl(&sv, &dv, it.n, st, &o, stage, e.stage_need, s->lookback[e.stream],
+                                      kServerLookbackBytes);
     if (r != RL_OK && e.status == RL_OK) e.status = r;
     std::vector<uint64_t> hb(layout_n_buffers(it.src_layout));
     layout_buffer_bytes(it.src_layout, it.n, it.src_mcap.empty() ? nullptr : it.src_mcap.data(), hb.data());
@@ -255,6 +263,19 @@ extern "C" rl_status rl_server_create(const rl_server_opts* opts, rl_server** ou
     }
     s->streams.push_back(st);
   }
+  for (uint32_t k = 0; k < opts->n_streams; ++k) {
+    const uint64_t off = s->pool.alloc(kServerLookbackBytes);
+    uint64_t* lb = off == UINT64_MAX ? nullptr : reinterpret_cast<uint64_t*>(s->slab + off);
+    if (lb && (e = launch_zero(lb, kServerLookbackBytes, s->streams[k])) != hipSuccess) lb = nullptr;
+    s->lookback.push_back(lb);   // null (budget too small): the library's per-stream buffer
+  }
+  for (auto x : s->streams)
+    if ((e = hipStreamSynchronize(x)) != hipSuccess) {
+      for (auto y : s->streams) (void)hipStreamDestroy(y);
+      (void)hipHostFree(s->slot_words);
+      (void)hipFree(s->slab);
+      return hip_fail(e, "hipStreamSynchronize");
+    }
   rl_server* raw = s.release();
   raw->scheduler = std::thread(scheduler_loop, raw);
   *out = raw;
@@ -297,9 +318,13 @@ extern "C" rl_status rl_server_submit(rl_server* s, const rl_event* ev, uint64_t
   }
   e->bytes = event_bytes(*e);
   const uint64_t need = e->bytes + (e->stage_need + 255) / 256 * 256;
-  if (need > s->pool.capacity())
-    return fail(RL_EBUDGET, "event needs %llu bytes (results and staging), budget is %llu",
-                (unsigned long long)need, (unsigned long long)s->pool.capacity());
+  // the slab less the look-back regions is what events can ever use
+  uint64_t usable = s->pool.capacity();
+  for (auto* lb : s->lookback)
+    if (lb) usable -= kServerLookbackBytes;
+  if (need > usable)
+    return fail(RL_EBUDGET, "event needs %llu bytes (results and staging), %llu of the budget hold events",
+                (unsigned long long)need, (unsigned long long)usable);
   hipError_t he = hipEventCreateWithFlags(&e->done, hipEventDisableTiming);
   if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
   std::lock_guard<std::mutex> lk(s->mu);

@@ -55,7 +55,7 @@ void* device_alias(void* p) {
 // at least staging_bytes(), owned by the caller) or else in the staging
 // buffer of (device, stream).
 rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t stream, bool h2d,
-                 uint8_t* given, uint64_t given_bytes) {
+                 uint8_t* given, uint64_t given_bytes, const PlanShape& shape) {
   const rl_view& hv = h2d ? src : dst;
   const rl_layout* HL = hv.layout;
   const uint32_t nb = layout_n_buffers(HL);
@@ -104,11 +104,11 @@ rl_status staged(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t
       if (bytes[b] && (e = hipMemcpyAsync(sb[b], hv.buffers[b], bytes[b], hipMemcpyHostToDevice, stream)) != hipSuccess)
         st = hip_fail(e, "hipMemcpyAsync H2D");
     Plan plan;
-    if (!st) st = make_plan(staged, dst, n, PlanShape{}, &plan);
+    if (!st) st = make_plan(staged, dst, n, shape, &plan);
     if (!st) st = enqueue_plan(plan, stream);
   } else {
     Plan plan;
-    st = make_plan(src, staged, n, PlanShape{}, &plan);
+    st = make_plan(src, staged, n, shape, &plan);
     if (!st) st = enqueue_plan(plan, stream);
     for (uint32_t b = 0; b < nb && !st; ++b)
       if (bytes[b] && (e = hipMemcpyAsync(hv.buffers[b], sb[b], bytes[b], hipMemcpyDeviceToHost, stream)) != hipSuccess)
@@ -136,7 +136,8 @@ bool transfer_is_staged(const rl_view& hv, const rl_xfer_opts* opts) {
 }
 
 rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipStream_t stream,
-                        const rl_xfer_opts* opts, uint8_t* stage, uint64_t stage_bytes) {
+                        const rl_xfer_opts* opts, uint8_t* stage, uint64_t stage_bytes,
+                        uint64_t* lookback, uint64_t lookback_bytes) {
   std::vector<Range> rs, rd;
   rl_status st = validate_view(src, n, "src", &rs, false);
   if (st) return st;
@@ -182,11 +183,18 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
     PlanShape to_host, from_host;
     to_host.direct = 0;
     from_host.dma = 0;
+    to_host.lookback = from_host.lookback = lookback;
+    to_host.lookback_bytes = from_host.lookback_bytes = lookback_bytes;
+    if (stream_capturing(stream)) to_host.fused = from_host.fused = 0;
     st = h2d ? make_plan(hv2, *dst, n, from_host, &plan) : make_plan(*src, hv2, n, to_host, &plan);
     if (st) return st;
     return enqueue_plan(plan, stream);
   }
-  return staged(*src, *dst, n, stream, h2d, stage, stage_bytes);
+  PlanShape shape;
+  shape.lookback = lookback;
+  shape.lookback_bytes = lookback_bytes;
+  if (stream_capturing(stream)) shape.fused = 0;
+  return staged(*src, *dst, n, stream, h2d, stage, stage_bytes, shape);
 }
 
 }  // namespace rl
@@ -205,7 +213,10 @@ extern "C" rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_
 // only form passed to copies and kernels.
 namespace {
 constexpr uint64_t kNoAllocStageBytes = RL_TRANSFER_NOALLOC_LIMIT;
-__device__ __align__(256) uint8_t scratch[kNoAllocStageBytes];
+// after the staging bytes: look-back words of single-pass jagged
+// conversions (zero at load)
+constexpr uint64_t kNoAllocLookbackBytes = 1ull << 20;
+__device__ __align__(256) uint8_t scratch[kNoAllocStageBytes + kNoAllocLookbackBytes];
 
 std::mutex g_scratch_mu;
 std::map<int, uint8_t*> g_scratch_ptr;   // device -> address of that device's scratch
@@ -230,13 +241,20 @@ rl_status scratch_on_current_device(uint8_t** out) {
 
 extern "C" rl_status rl_transfer_noalloc(const rl_view* src, const rl_view* dst, uint64_t n, void* stream,
                                          const rl_xfer_opts* opts) {
-  // the staged path is the only one that needs memory of the library; the
-  // limit is checked before anything is enqueued
+  // staging and the look-back state of jagged conversions are the memory
+  // the library would otherwise allocate; the staging limit is checked
+  // before anything is enqueued
   const bool one_host = src && dst && src->layout && dst->layout &&
                         rl::is_host(src->layout->space) != rl::is_host(dst->layout->space);
   if (!one_host || n == 0) return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
   const rl_view& hv = rl::is_host(src->layout->space) ? *src : *dst;
-  if (!rl::transfer_is_staged(hv, opts)) return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
+  uint8_t* base = nullptr;
+  if (!rl::transfer_is_staged(hv, opts)) {
+    rl_status st = scratch_on_current_device(&base);
+    if (st) return st;
+    return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0,
+                             reinterpret_cast<uint64_t*>(base + kNoAllocStageBytes), kNoAllocLookbackBytes);
+  }
   if (n > hv.capacity) return rl::fail(RL_EINVAL, "n %llu over the host view's capacity", (unsigned long long)n);
   if (!hv.layout->schema->members.empty() && !hv.member_capacity)
     return rl::fail(RL_EINVAL, "member capacities of the host view are NULL");
@@ -244,8 +262,8 @@ extern "C" rl_status rl_transfer_noalloc(const rl_view* src, const rl_view* dst,
   if (need > kNoAllocStageBytes)
     return rl::fail(RL_ELIMIT, "rl_transfer_noalloc stages at most %llu bytes; this transfer needs %llu",
                     (unsigned long long)kNoAllocStageBytes, (unsigned long long)need);
-  uint8_t* stage = nullptr;
-  rl_status st = scratch_on_current_device(&stage);
+  rl_status st = scratch_on_current_device(&base);
   if (st) return st;
-  return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, stage, kNoAllocStageBytes);
+  return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, base, kNoAllocStageBytes,
+                           reinterpret_cast<uint64_t*>(base + kNoAllocStageBytes), kNoAllocLookbackBytes);
 }
