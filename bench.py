@@ -6,11 +6,14 @@ resident in HBM as AoS records, converted into the four device layouts the
 workload asks for: SoA (energy_d narrowed to f32) and AoSoA with block
 widths 32, 64 and 128 (same narrowing).  Each step uses its own copy of the
 source and destinations, rotating over enough copies that the working set
-is several times the 256 MB Infinity Cache, so every step reads and writes
-HBM.
+is several times the 256 MB Infinity Cache; the timed steps use copies the
+warm-up did not touch.
 
 Value: algorithmic bytes (source footprint read + destination footprint
-written, per conversion) per second of the timed region.
+written, per conversion) per second of the timed region.  The four
+conversions share their source, so the HBM traffic of a step is lower
+(three of the four source reads are served by L2); roofline.frac_hbm gives
+the fraction from the measured HBM counters beside the algorithmic one.
 
 The four conversions of a step run as one launch of the batch engine
 (persistent kernels over a device table; tile shape, work-group count and
@@ -18,13 +21,17 @@ graph replay vs direct launch autotuned once, cached); the same
 conversions as a per-conversion launch loop are timed beside it.  The
 timed region is K steps back to back between two events; each step is one
 launch of the batch dense kernel, so the region's mean step time is that
-kernel's mean launch duration (the roofline); a second pass with an event
-pair around every launch reports the duration of an isolated launch.
+kernel's mean launch duration (the roofline).  A second pass with an event
+pair around each of 50 launches gives the paper's statistic (mean of the
+10 fastest, and the median).
 
-Extra legs, outside the timed region: 512 heterogeneous collections in one
-graph launch against the launch loop, a sweep at larger object counts, the
-host -> device transfer + conversion rate (PCIe included), and the oracle
-timed on the host cores (cpu_baseline).
+Extra legs, outside the timed region: a single conversion per launch
+(cold), the attainable HBM rate of a plain 16-byte copy kernel and the
+launch floor, the plain round trip, jagged conversions, 512 heterogeneous
+collections in one graph launch against the launch loop, a sweep at larger
+object counts, host <-> device transfers with conversion (PCIe included),
+the serving loop against a synchronous per-event loop, and the oracle timed
+on one and on all host cores (cpu_baseline).
 """
 import argparse
 import ctypes
@@ -52,7 +59,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--leg", choices=["round_trip", "jagged", "serving", "batched", "sweep", "h2d"],
+    ap.add_argument("--leg", choices=sorted(LEGS),
                     help="run only this extra leg and print its JSON (for profiling one leg)")
     return ap.parse_args()
 
@@ -65,7 +72,7 @@ def main():
         sys.exit(2)
     import torch
     import paper_2511_04853_amd as P
-    import workloads as W
+    import workloads as Wk
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -73,7 +80,7 @@ def main():
     stream = torch.cuda.current_stream()
     sp = P.stream_ptr(stream)
     if args.leg:
-        print(json.dumps(run_leg(args.leg, P, W, torch, stream)), flush=True)
+        print(json.dumps(LEGS[args.leg](P, Wk, torch, stream)), flush=True)
         return
 
     # calibration copy of known size for the HBM byte counters (untimed)
@@ -83,18 +90,18 @@ def main():
     torch.cuda.synchronize()
     del calib, calib2
 
-    S = P.Schema(W.CELL)
-    narrowed = ["f32" if f.type == "f64" else f.type for f in W.CELL.fields]
+    S = P.Schema(Wk.CELL)
+    narrowed = ["f32" if f.type == "f64" else f.type for f in Wk.CELL.fields]
     aos = P.Layout(S, "aos")
     dsts = [P.Layout(S, "soa", storage=narrowed)] + [P.Layout(S, "aosoa", width=w, storage=narrowed)
                                                      for w in WIDTHS]
     n = N_CELLS
-    v = W.cell_values(n)
+    v = Wk.cell_values(n)
 
     # source records built on the device from the generated columns
     def device_aos(values):
         cols = []
-        for f in W.CELL.fields:
+        for f in Wk.CELL.fields:
             cols.append(torch.from_numpy(np.ascontiguousarray(values.fields[f.name]).view(np.uint8)).cuda())
         soa64 = P.Layout(S, "soa")
         rec = torch.empty(aos.buffer_bytes(values.n)[0], dtype=torch.uint8, device="cuda")
@@ -129,17 +136,20 @@ def main():
         b = sets[k % len(sets)][2]
         b.loop(sp) if loop else b.launch(sp)
 
-    for k in range(args.warmup):
+    W = args.warmup
+    for k in range(W):
         run(k)
     assert P.sync(stream) == 0, P.rl_last_error()
 
-    # timed region: K steps back to back, bracketed by two events
+    # timed region: K steps back to back, bracketed by two events; the
+    # steps use copies W, W + 1, ... (not touched by the warm-up while
+    # W + K <= the number of copies)
     K = args.steps
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
     for k in range(K):
-        run(k)
+        run(W + k)
     t1.record(stream)
     torch.cuda.synchronize()
     ms_total = t0.elapsed_time(t1)
@@ -149,19 +159,13 @@ def main():
 
     # A step is one launch of the batch dense kernel (the only kernel of a
     # step whose counts are host-known), so its mean launch duration in the
-    # timed region is ms_per_step.  An event pair around each launch of a
-    # second pass adds each launch's dispatch latency (reported beside it).
+    # timed region is ms_per_step.  An event pair around each of 50 launches
+    # of a second pass gives the paper's statistic for isolated launches
+    # (each includes its dispatch latency).
     mean_launch_ms = ms_per_step
     achieved = step_bytes / (mean_launch_ms * 1e-3) / 1e9
-    evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(K)]
-    torch.cuda.synchronize()
-    for k in range(K):
-        evs[k][0].record(stream)
-        run(k)
-        evs[k][1].record(stream)
-    torch.cuda.synchronize()
+    iso = event_times(lambda k: run(W + K + k), stream, torch, 50)
     assert P.sync(stream) == 0, P.rl_last_error()
-    isolated_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
 
     # the same conversions as a launch loop (one kernel launch per conversion)
     for k in range(args.warmup):
@@ -185,7 +189,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": "u8 moves + f64->f32 RNE",
         "data": "synthetic",
         "config": {
             "workload": "cell collection, 190,000 objects, device AoS (32 B records) -> SoA with "
@@ -206,8 +210,9 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
             "kernel": "rl::batch_dense_kernel",
+            "bytes_basis": "algorithmic: per conversion, source footprint read + destination footprint written",
             "mean_launch_us": round(mean_launch_ms * 1e3, 3),
-            "isolated_launch_us": round(isolated_ms * 1e3, 3),
+            "isolated_launch_us": iso,
             "bytes_per_launch": int(step_bytes),
         },
         "step_launch_loop": {"ms_per_step": round(ms_loop, 5),
@@ -215,16 +220,20 @@ def main():
                              "batch_speedup": round(ms_loop / ms_per_step, 3)},
     }
 
-    out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"], n)
+    traffic = measured_traffic(out["roofline"]["kernel"], n)
+    out["roofline"]["traffic"] = traffic
+    if traffic:
+        # the same launch time against the HBM bytes the counters saw
+        out["roofline"]["frac_hbm"] = round(traffic / (mean_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    del sets
+    torch.cuda.empty_cache()
     if not args.no_extras:
-        out["plain_round_trip"] = plain_round_trip(P, W, torch, stream)
-        out["jagged"] = jagged(P, W, torch, stream)
-        out["serving"] = serving(P, W, torch, stream)
-        out["batched"] = batched(P, W, torch, stream, tune_cache)
-        out["sweep"] = sweep(P, W, torch, stream)
-        out["h2d"] = h2d_rate(P, W, torch, stream, S, aos, dsts[0], v)
+        for name in EXTRA_ORDER:
+            print(f"# leg {name}", file=sys.stderr, flush=True)
+            out[name] = LEGS[name](P, Wk, torch, stream)
+            torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(W, v, args.cpu_seconds, step_bytes)
+        out["cpu_baseline"] = cpu_baseline(Wk, v, args.cpu_seconds, step_bytes)
     print(json.dumps(out), flush=True)
 
 
@@ -355,25 +364,6 @@ def batched(P, W, torch, stream, tune_cache):
     return res
 
 
-def run_leg(name, P, W, torch, stream):
-    """One extra leg on its own (same code as in the full run)."""
-    if name == "round_trip":
-        return plain_round_trip(P, W, torch, stream)
-    if name == "jagged":
-        return jagged(P, W, torch, stream)
-    if name == "serving":
-        return serving(P, W, torch, stream)
-    if name == "batched":
-        return batched(P, W, torch, stream, os.path.join(os.environ.get("TMPDIR", "/tmp"),
-                                                         f"rl_tune_{os.getpid()}.json"))
-    if name == "sweep":
-        return sweep(P, W, torch, stream)
-    S = P.Schema(W.CELL)
-    aos = P.Layout(S, "aos")
-    soa = P.Layout(S, "soa", storage=["f32" if f.type == "f64" else f.type for f in W.CELL.fields])
-    return h2d_rate(P, W, torch, stream, S, aos, soa, W.cell_values(N_CELLS))
-
-
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -397,6 +387,7 @@ def measured_traffic(kernel, n):
 
 
 def _time(fn, stream, torch, reps=50, warm=5):
+    """Mean ms of `reps` back-to-back calls fn(k) between two events."""
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
@@ -407,6 +398,78 @@ def _time(fn, stream, torch, reps=50, warm=5):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def event_times(fn, stream, torch, count):
+    """fn(k) for k < count, an event pair around each call: the paper's
+    statistic over the durations (mean of the 10 fastest, median), in us."""
+    evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(count)]
+    torch.cuda.synchronize()
+    for k in range(count):
+        evs[k][0].record(stream)
+        fn(k)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    return paper_stat([e[0].elapsed_time(e[1]) * 1e3 for e in evs])
+
+
+def paper_stat(us):
+    """Mean of the 10 fastest of the runs, and the median (the case study's
+    statistic: mean of the 10 fastest of 50 executions)."""
+    a = sorted(us)
+    return {"runs": len(a), "mean10_fastest_us": round(float(np.mean(a[:10])), 3),
+            "median_us": round(float(np.median(a)), 3)}
+
+
+def single_conversion(P, W, torch, stream, sets=32):
+    """One conversion per launch: the cell collection (190,000 objects) from
+    AoS records into SoA (energy_d narrowed) and into AoSoA(64), rotating 32
+    copies (334 MB per kind, beyond the Infinity Cache)."""
+    S = P.Schema(W.CELL)
+    narrowed = ["f32" if f.type == "f64" else f.type for f in W.CELL.fields]
+    aos = P.Layout(S, "aos")
+    n = 190_000
+    lib, sp = P.lib(), P.stream_ptr(stream)
+    res = {"objects": n, "copies": sets}
+    for name, L in (("soa", P.Layout(S, "soa", storage=narrowed)),
+                    ("aosoa64", P.Layout(S, "aosoa", width=64, storage=narrowed))):
+        pairs = []
+        for _ in range(sets):
+            src = torch.randint(0, 255, (aos.buffer_bytes(n)[0],), dtype=torch.uint8, device="cuda")
+            dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in L.buffer_bytes(n)]
+            pairs.append((P.View(aos, n, [src]), P.View(L, n, dst)))
+        nbytes = aos.buffer_bytes(n)[0] + sum(L.buffer_bytes(n))
+        fn = lambda k=0: lib.rl_convert(pairs[k % sets][0].ref(), pairs[k % sets][1].ref(), n, sp)
+        ms = _time(fn, stream, torch, reps=64, warm=4)
+        iso = event_times(fn, stream, torch, 50)
+        assert P.sync(stream) == 0, P.rl_last_error()
+        res[name] = {"bytes": nbytes, "us_back_to_back": round(ms * 1e3, 3),
+                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm_algorithmic": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "isolated": iso}
+        del pairs
+    return res
+
+
+def copy_peak(P, W, torch, stream):
+    """The attainable HBM rate: the library's plain 16-byte vector copy
+    kernel (rl_memcopy, device to device) over 1 GiB buffers, three pairs
+    rotating (cold); and the launch floor (back-to-back copies of 16 bytes)."""
+    size = 1 << 30
+    a = [torch.empty(size, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    b = [torch.empty(size, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    for t in a:
+        t.fill_(7)
+    fn = lambda k=0: P.memcopy(b[k % 3], "device", a[k % 3], "device", size, stream)
+    ms = _time(fn, stream, torch, reps=12, warm=3)
+    res = {"bytes_per_copy": 2 * size, "us": round(ms * 1e3, 1),
+           "GBps_read_plus_write": round(2 * size / (ms * 1e-3) / 1e9, 1),
+           "frac_of_spec": round(2 * size / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    assert torch.equal(b[0][:4096], a[0][:4096])
+    small = lambda k=0: P.memcopy(b[0], "device", a[0], "device", 16, stream)
+    res["launch_floor_us"] = round(_time(small, stream, torch, reps=200, warm=10) * 1e3, 3)
+    del a, b
+    return res
 
 
 def plain_round_trip(P, W, torch, stream, sets=64):
@@ -499,10 +562,15 @@ def jagged(P, W, torch, stream, sets=8):
     fwd_s = _time(lambda k=0: lib.rl_convert(vals[k % sets][3].ref(), vals[k % sets][1].ref(), n, sp), stream, torch)
     fwd = _time(lambda k=0: lib.rl_convert(vals[k % sets][0].ref(), vals[k % sets][1].ref(), n, sp), stream, torch)
     rev = _time(lambda k=0: lib.rl_convert(vals[k % sets][1].ref(), vals[k % sets][0].ref(), n, sp), stream, torch)
+    fwd_iso = event_times(lambda k=0: lib.rl_convert(vals[k % sets][3].ref(), vals[k % sets][1].ref(), n, sp),
+                          stream, torch, 50)
+    rev_iso = event_times(lambda k=0: lib.rl_convert(vals[k % sets][1].ref(), vals[k % sets][0].ref(), n, sp),
+                          stream, torch, 50)
     assert P.sync(stream) == 0
     tot = int(np.mean([v[2] for v in vals]))
     by = sum(aos.buffer_bytes(n, [tot])) + sum(soa.buffer_bytes(n, [tot]))
     return {"objects": n, "members": tot, "bytes_each_way": by,
+            "forward_isolated": fwd_iso, "reverse_isolated": rev_iso,
             "forward_shuffled_pool_us": round(fwd_s * 1e3, 2),
             "forward_shuffled_pool_GBps": round(by / (fwd_s * 1e-3) / 1e9, 1),
             "forward_us": round(fwd * 1e3, 2), "forward_GBps": round(by / (fwd * 1e-3) / 1e9, 1),
@@ -625,93 +693,272 @@ def serving(P, W, torch, stream, rates=(1000, 3000), n_events=10_000, hold=512, 
     st = srv.stats()
     res["peak_resident_GB"] = round(st["peak_bytes"] / 1e9, 3)
     srv.close()
+    del srv
+    torch.cuda.synchronize()
+
+    # the baseline: a synchronous per-event loop on one stream, each event's
+    # transfers enqueued and waited for before the next event starts (same
+    # events, same arrival processes; results into preallocated buffers)
+    loop_dst = []
+    for items in events:
+        outs = []
+        for view, layout, n in items:
+            mem = list(view._mcap)[:1] if view.layout.schema.n_groups else []
+            outs.append(P.View(layout, n, [torch.empty(x, dtype=torch.uint8, device="cuda")
+                                           for x in layout.buffer_bytes(n, mem)], mem))
+        loop_dst.append(outs)
+
+    def serve_one(k):
+        for (view, layout, n), dv in zip(events[k % pool_events], loop_dst[k % pool_events]):
+            P.transfer(view, dv, n, stream)
+        assert P.sync(stream) == 0, P.rl_last_error()
+
+    def loop_run(rate, count, seed):
+        arrivals = W.poisson_arrivals(count, rate, seed=seed)
+        lat_ms = np.zeros(count)
+        t0 = time.perf_counter()
+        for k in range(count):
+            while True:
+                dt = arrivals[k] - (time.perf_counter() - t0)
+                if dt <= 0:
+                    break
+                if dt > 3e-4:
+                    time.sleep(dt - 2e-4)
+            serve_one(k)
+            lat_ms[k] = ((time.perf_counter() - t0) - arrivals[k]) * 1e3
+        span = (time.perf_counter() - t0) - arrivals[0]
+        return {"events": count, "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                "events_per_s": round(count / span, 1)}
+
+    for k in range(200):   # warm-up
+        serve_one(k)
+    loop = {}
+    for rate in rates:
+        loop[f"{rate}/s"] = loop_run(rate, 3000, seed=3004 + rate)
+    t = time.perf_counter()
+    for k in range(3000):
+        serve_one(k)
+    loop["back_to_back"] = {"events": 3000, "events_per_s": round(3000 / (time.perf_counter() - t), 1)}
+    res["per_event_loop"] = loop
+    res["server_over_loop_throughput"] = round(res["saturation_offered_6000/s"]["events_per_s"] /
+                                               loop["back_to_back"]["events_per_s"], 3)
+    del loop_dst
     return res
 
 
-def sweep(P, W, torch, stream):
-    """AoS -> SoA (narrowed) at larger object counts, 2 copies rotating."""
+def _cluster_device_collection(P, W, torch, n, g, aos, soa):
+    """A cluster collection built on the device: Poisson(40) member counts,
+    random field and member bits, as AoS records + canonical pool (returns
+    the records view and the member total)."""
+    lens = torch.poisson(torch.full((n,), 40.0, device="cuda"), generator=g).to(torch.int64)
+    offs = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    offs[1:] = torch.cumsum(lens, 0)
+    tot = int(offs[-1].item())
+    bufs = [torch.randint(0, 256, (4 * n,), dtype=torch.uint8, device="cuda", generator=g) for _ in range(6)]
+    bufs.append(offs.to(torch.int32).view(torch.uint8))
+    bufs += [torch.randint(0, 256, (4 * tot,), dtype=torch.uint8, device="cuda", generator=g) for _ in range(2)]
+    av = P.View(aos, n, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in aos.buffer_bytes(n, [tot])], [tot])
+    P.convert(P.View(soa, n, bufs, [tot]), av, n)
+    return av, tot
+
+
+def sweep(P, W, torch, stream, copies=4):
+    """AoS records -> SoA at larger object counts, `copies` copies rotating
+    (cold at every size): the plain schema (8 scalars) and the cell schema
+    (energy_d narrowed) at 2^20 .. 2^25 objects, the cluster schema (jagged,
+    Poisson(40) members) at 2^21; the library's plain copy kernel over the
+    same bytes (half read, half written) beside each row."""
+    res = {}
+    lib, sp = P.lib(), P.stream_ptr(stream)
+
+    def copy_rate(nbytes):
+        half = nbytes // 2 // 16 * 16
+        a = [torch.empty(half, dtype=torch.uint8, device="cuda") for _ in range(copies)]
+        b = [torch.empty(half, dtype=torch.uint8, device="cuda") for _ in range(copies)]
+        ms = _time(lambda k=0: P.memcopy(b[k % copies], "device", a[k % copies], "device", half, stream),
+                   stream, torch, reps=12, warm=copies)
+        return round(2 * half / (ms * 1e-3) / 1e9, 1)
+
+    for sname, decl in (("plain8", W.PLAIN8), ("cell", W.CELL)):
+        S = P.Schema(decl)
+        narrowed = ["f32" if f.type == "f64" else f.type for f in decl.fields] if decl is W.CELL else None
+        aos = P.Layout(S, "aos")
+        soa = P.Layout(S, "soa", storage=narrowed)
+        for n in (1 << 20, 1 << 22, 1 << 24, 1 << 25):
+            pairs = []
+            for _ in range(copies):
+                src = torch.randint(0, 255, (aos.buffer_bytes(n)[0],), dtype=torch.uint8, device="cuda")
+                dst = [torch.empty(x, dtype=torch.uint8, device="cuda") for x in soa.buffer_bytes(n)]
+                pairs.append((P.View(aos, n, [src]), P.View(soa, n, dst)))
+            nbytes = aos.buffer_bytes(n)[0] + sum(soa.buffer_bytes(n))
+            ms = _time(lambda k=0: lib.rl_convert(pairs[k % copies][0].ref(), pairs[k % copies][1].ref(), n, sp),
+                       stream, torch, reps=12, warm=copies)
+            assert P.sync(stream) == 0, P.rl_last_error()
+            del pairs
+            torch.cuda.empty_cache()
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            cp = copy_rate(nbytes)
+            res[f"{sname}/{n}"] = {"us": round(ms * 1e3, 2), "GBps": round(gbs, 1),
+                                   "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "copy_kernel_GBps": cp,
+                                   "frac_of_copy": round(gbs / cp, 4)}
+            torch.cuda.empty_cache()
+    # jagged: cluster records + pool -> SoA + offsets + member columns
+    S = P.Schema(W.CLUSTER)
+    aos, soa = P.Layout(S, "aos"), P.Layout(S, "soa")
+    n = 1 << 21
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1002)
+    sets = []
+    for _ in range(copies):
+        av, tot = _cluster_device_collection(P, W, torch, n, g, aos, soa)
+        dv = P.View(soa, n, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in soa.buffer_bytes(n, [tot])],
+                    [tot])
+        sets.append((av, dv, tot))
+    assert P.sync(stream) == 0
+    ms = _time(lambda k=0: lib.rl_convert(sets[k % copies][0].ref(), sets[k % copies][1].ref(), n, sp),
+               stream, torch, reps=12, warm=copies)
+    assert P.sync(stream) == 0, P.rl_last_error()
+    tot = int(np.mean([x[2] for x in sets]))
+    nbytes = sum(aos.buffer_bytes(n, [tot])) + sum(soa.buffer_bytes(n, [tot]))
+    del sets
+    torch.cuda.empty_cache()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    cp = copy_rate(nbytes)
+    res[f"cluster/{n}"] = {"members": tot, "us": round(ms * 1e3, 2), "GBps": round(gbs, 1),
+                           "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "copy_kernel_GBps": cp,
+                           "frac_of_copy": round(gbs / cp, 4)}
+    torch.cuda.empty_cache()
+    return res
+
+
+def _wall(fn, torch, reps=20, warm=3):
+    """Mean wall seconds of fn() with the device drained before and after."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def h2d(P, W, torch, stream):
+    """Pinned host collections -> device layouts with conversion, PCIe
+    included (never the headline): the cell collection (190,000 objects,
+    6.08 MB of records) into SoA and AoSoA 32/64/128 (energy_d narrowed),
+    staged (DMA copy + conversion) and zero-copy (the kernel reads host
+    memory); the jagged cluster collection (50,000 records + pool); a plain
+    pinned copy of the same bytes for the link rate."""
     res = {}
     S = P.Schema(W.CELL)
     narrowed = ["f32" if f.type == "f64" else f.type for f in W.CELL.fields]
-    aos = P.Layout(S, "aos")
-    soa = P.Layout(S, "soa", storage=narrowed)
-    lib = P.lib()
-    sp = P.stream_ptr(stream)
-    for n in (1 << 20, 1 << 22, 1 << 24):
-        pairs = []
-        for r in range(2):
-            src = torch.randint(0, 255, (aos.buffer_bytes(n)[0],), dtype=torch.uint8, device="cuda")
-            dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in soa.buffer_bytes(n)]
-            pairs.append((P.View(aos, n, [src]), P.View(soa, n, dst)))
-        nbytes = aos.buffer_bytes(n)[0] + sum(soa.buffer_bytes(n))
-        reps = 10
-        for k in range(3):
-            lib.rl_convert(pairs[k % 2][0].ref(), pairs[k % 2][1].ref(), n, sp)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for k in range(reps):
-            lib.rl_convert(pairs[k % 2][0].ref(), pairs[k % 2][1].ref(), n, sp)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        del pairs
-        # a plain device copy moving the same bytes (half read, half written)
-        a = [torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda") for _ in range(2)]
-        b = [torch.empty_like(a[0]) for _ in range(2)]
-        for k in range(3):
-            b[k % 2].copy_(a[k % 2])
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for k in range(reps):
-            b[k % 2].copy_(a[k % 2])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_copy = e0.elapsed_time(e1) / reps
-        del a, b
-        res[str(n)] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
-                       "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                       "plain_copy_GBps": round(nbytes / (ms_copy * 1e-3) / 1e9, 1)}
-    assert P.sync(stream) == 0
-    return res
-
-
-def h2d_rate(P, W, torch, stream, S, aos_dev, soa, v):
-    """Pinned host AoS -> device SoA, staged over PCIe (not the headline value)."""
     aos_h = P.Layout(S, "aos", space="pinned")
-    n = v.n
-    host = torch.empty(aos_dev.buffer_bytes(n)[0], dtype=torch.uint8, pin_memory=True)
-    dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in soa.buffer_bytes(n)]
-    sv, dv = P.View(aos_h, n, [host]), P.View(soa, n, dst)
-    res = {}
-    # the plain pinned -> device copy of the same bytes, for reference
+    n = 190_000
+    host = torch.randint(0, 255, (aos_h.buffer_bytes(n)[0],), dtype=torch.uint8).pin_memory()
     raw = torch.empty(host.numel(), dtype=torch.uint8, device="cuda")
-    for _ in range(3):
-        raw.copy_(host, non_blocking=True)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(20):
-        raw.copy_(host, non_blocking=True)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / 20
-    res["plain_copy"] = {"us": round(dt * 1e6, 1), "link_GBps": round(host.numel() / dt / 1e9, 2)}
-    for mode in ("staged", "zero_copy"):
-        for _ in range(3):
-            P.transfer(sv, dv, n, mode=mode)
-        torch.cuda.synchronize()
-        reps = 20
-        t = time.perf_counter()
-        for _ in range(reps):
-            P.transfer(sv, dv, n, mode=mode)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / reps
-        res[mode] = {"us": round(dt * 1e6, 1), "link_GBps": round(host.numel() / dt / 1e9, 2)}
+    dt = _wall(lambda: raw.copy_(host, non_blocking=True), torch)
+    res["cell_plain_copy"] = {"bytes": host.numel(), "us": round(dt * 1e6, 1),
+                              "link_GBps": round(host.numel() / dt / 1e9, 2)}
+    for name, L in (("soa", P.Layout(S, "soa", storage=narrowed)),) + tuple(
+            (f"aosoa{w}", P.Layout(S, "aosoa", width=w, storage=narrowed)) for w in (32, 64, 128)):
+        dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in L.buffer_bytes(n)]
+        sv, dv = P.View(aos_h, n, [host]), P.View(L, n, dst)
+        for mode in ("staged", "zero_copy"):
+            dt = _wall(lambda: P.transfer(sv, dv, n, stream, mode=mode), torch)
+            res[f"cell_{name}_{mode}"] = {"us": round(dt * 1e6, 1), "link_GBps": round(host.numel() / dt / 1e9, 2)}
+    assert P.sync(stream) == 0, P.rl_last_error()
+    # jagged
+    S = P.Schema(W.CLUSTER)
+    aos, soa, aos_hj = P.Layout(S, "aos"), P.Layout(S, "soa"), P.Layout(S, "aos", space="pinned")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1002)
+    m = 50_000
+    av, tot = _cluster_device_collection(P, W, torch, m, g, aos, soa)
     assert P.sync(stream) == 0
+    hbufs = [t.cpu().pin_memory() for t in av.tensors]
+    hv = P.View(aos_hj, m, hbufs, [tot])
+    dv = P.View(soa, m, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in soa.buffer_bytes(m, [tot])], [tot])
+    hb = sum(t.numel() for t in hbufs)
+    for mode in ("staged", "zero_copy"):
+        dt = _wall(lambda: P.transfer(hv, dv, m, stream, mode=mode), torch)
+        res[f"cluster_soa_{mode}"] = {"host_bytes": hb, "us": round(dt * 1e6, 1), "link_GBps": round(hb / dt / 1e9, 2)}
+    assert P.sync(stream) == 0, P.rl_last_error()
     return res
+
+
+def d2h(P, W, torch, stream):
+    """Device collections -> pinned host records with conversion, PCIe
+    included: the cell collection from SoA (energy_d narrowed) back into
+    the original AoS records (energy_d widened to f64), and the cluster
+    collection from SoA + offsets into records + a canonical pool; staged
+    (conversion into device staging + DMA copy) and zero-copy (the kernel
+    writes host memory); a plain device -> pinned copy for the link rate."""
+    res = {}
+    S = P.Schema(W.CELL)
+    narrowed = ["f32" if f.type == "f64" else f.type for f in W.CELL.fields]
+    soa = P.Layout(S, "soa", storage=narrowed)
+    aos_h = P.Layout(S, "aos", space="pinned")
+    n = 190_000
+    src = [torch.randint(0, 255, (b,), dtype=torch.uint8, device="cuda") for b in soa.buffer_bytes(n)]
+    src[6] = (torch.rand(n, device="cuda") * 1e3).view(torch.uint8)   # valid floats to widen
+    host = torch.empty(aos_h.buffer_bytes(n)[0], dtype=torch.uint8).pin_memory()
+    raw = torch.empty(host.numel(), dtype=torch.uint8, device="cuda")
+    dt = _wall(lambda: host.copy_(raw, non_blocking=True), torch)
+    res["cell_plain_copy"] = {"bytes": host.numel(), "us": round(dt * 1e6, 1),
+                              "link_GBps": round(host.numel() / dt / 1e9, 2)}
+    sv, hv = P.View(soa, n, src), P.View(aos_h, n, [host])
+    for mode in ("staged", "zero_copy"):
+        dt = _wall(lambda: P.transfer(sv, hv, n, stream, mode=mode), torch)
+        res[f"cell_aos_{mode}"] = {"us": round(dt * 1e6, 1), "link_GBps": round(host.numel() / dt / 1e9, 2)}
+    assert P.sync(stream) == 0, P.rl_last_error()
+    S = P.Schema(W.CLUSTER)
+    aos, soa, aos_hj = P.Layout(S, "aos"), P.Layout(S, "soa"), P.Layout(S, "aos", space="pinned")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1002)
+    m = 50_000
+    av, tot = _cluster_device_collection(P, W, torch, m, g, aos, soa)
+    dv = P.View(soa, m, [torch.empty(x, dtype=torch.uint8, device="cuda") for x in soa.buffer_bytes(m, [tot])], [tot])
+    P.convert(av, dv, m)
+    assert P.sync(stream) == 0
+    hbufs = [torch.empty(x, dtype=torch.uint8).pin_memory() for x in aos_hj.buffer_bytes(m, [tot])]
+    hv = P.View(aos_hj, m, hbufs, [tot])
+    hb = sum(t.numel() for t in hbufs)
+    for mode in ("staged", "zero_copy"):
+        dt = _wall(lambda: P.transfer(dv, hv, m, stream, mode=mode), torch)
+        res[f"cluster_aos_{mode}"] = {"host_bytes": hb, "us": round(dt * 1e6, 1), "link_GBps": round(hb / dt / 1e9, 2)}
+    assert P.sync(stream) == 0, P.rl_last_error()
+    return res
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Host threads to time the oracle on: the CPUs this process may use,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def cpu_baseline(W, v, seconds, step_bytes):
-    """The oracle (plain C per-object loop, single thread) on the same step."""
+    """The oracle (plain C per-object loop) on the benchmark step (the four
+    conversions of the cell collection), buffers prepared once: on one host
+    thread, and split into contiguous object ranges on all host threads
+    (same loop body).  50 runs each (fewer if a run is long), the paper's
+    statistic over them; value = algorithmic bytes / mean of the 10 fastest."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     S = oracle.Schema(W.CELL)
     narrowed = ["f32" if t == "f64" else t for t in S.leaf_types()]
@@ -719,19 +966,87 @@ def cpu_baseline(W, v, seconds, step_bytes):
     dsts = [oracle.make_layout(S, "soa", storage=narrowed)] + [
         oracle.make_layout(S, "aosoa", width=w, storage=narrowed) for w in WIDTHS]
     src = oracle.pack(S, v, aos)
-    reps = 0
-    t = time.perf_counter()
-    while True:
-        for d in dsts:
-            st, _, _ = oracle.convert(aos, src, d, v.n)
+    preps = [oracle.Prepared(aos, src, d, v.n) for d in dsts]
+    threads = host_threads()
+    pool = ThreadPoolExecutor(threads)
+    out = {}
+    for label, th in (("one_thread", 1), ("all_threads", threads)):
+        times = []
+        t_end = time.perf_counter() + seconds / 2
+        while len(times) < 50 and (len(times) < 10 or time.perf_counter() < t_end):
+            t = time.perf_counter()
+            for p_ in preps:
+                assert p_.run(th, pool) == 0
+            times.append((time.perf_counter() - t) * 1e6)
+        st = paper_stat(times)
+        out[label] = {"threads": th, **st, "GBps": round(step_bytes / (st["mean10_fastest_us"] * 1e-6) / 1e9, 3)}
+    pool.shutdown()
+    best = out["all_threads"]
+    return {"value": best["GBps"], "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"the benchmark step (190,000 cell objects into SoA and AoSoA 32/64/128, energy_d narrowed), "
+                      f"{best['runs']} runs on {threads} host threads (contiguous object ranges), "
+                      f"mean of the 10 fastest {best['mean10_fastest_us'] / 1e3:.2f} ms per step; "
+                      f"one thread: {out['one_thread']['GBps']} GB/s",
+            "detail": out}
+
+
+def cpu_events(P, W, torch, stream, seconds=8.0):
+    """Serving workload on the host cores: the oracle converts whole events
+    (one plain, one cell and one cluster collection of log-normal sizes,
+    records -> SoA, energy_d narrowed), one event per host thread at a time,
+    no transfer; events per second."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    decls = [W.PLAIN8, W.CELL, W.CLUSTER]
+    schemas = [oracle.Schema(d) for d in decls]
+    srcs = [oracle.make_layout(S, "aos") for S in schemas]
+    dsts = [oracle.make_layout(S, "soa", storage=(["f32" if t == "f64" else t for t in S.leaf_types()]
+                                                  if d is W.CELL else None)) for S, d in zip(schemas, decls)]
+    sizes = W.serving_events(16)
+    events = []
+    for k, row in enumerate(sizes):
+        items = []
+        for j, (S, d) in enumerate(zip(schemas, decls)):
+            n = int(row[j])
+            vals = (W.plain_values(n, seed=5000 + k) if d is W.PLAIN8 else
+                    W.cell_values(n, seed=5000 + k) if d is W.CELL else W.cluster_values(n, seed=5000 + k))
+            items.append((srcs[j], oracle.pack(S, vals, srcs[j]), dsts[j], n,
+                          [vals.total(0)] if d.offset_types else []))
+        events.append(items)
+
+    def convert_event(items):
+        for sl, sb, dl, n, mem in items:
+            st, _, _ = oracle.convert(sl, sb, dl, n, mem, mem)
             assert st == 0
-        reps += 1
-        if time.perf_counter() - t >= seconds:
-            break
-    dt = (time.perf_counter() - t) / reps
-    return {"value": round(step_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full steps (190,000 objects x 4 conversions), single thread, "
-                      f"{dt * 1e3:.1f} ms per step"}
+
+    threads = host_threads()
+    with ThreadPoolExecutor(threads) as pool:
+        list(pool.map(convert_event, events[:threads]))   # warm-up
+        done = 0
+        t = time.perf_counter()
+        while time.perf_counter() - t < seconds:
+            list(pool.map(convert_event, [events[(done + i) % len(events)] for i in range(threads * 4)]))
+            done += threads * 4
+        dt = time.perf_counter() - t
+    return {"events_per_s": round(done / dt, 1), "threads": threads, "cpu_model": cpu_model(), "events": done}
+
+
+LEGS = {
+    "single_conversion": single_conversion,
+    "copy_peak": copy_peak,
+    "round_trip": lambda P, W, torch, stream: plain_round_trip(P, W, torch, stream),
+    "jagged": jagged,
+    "batched": lambda P, W, torch, stream: batched(
+        P, W, torch, stream, os.path.join(os.environ.get("TMPDIR", "/tmp"), f"rl_tune_{os.getpid()}.json")),
+    "sweep": sweep,
+    "h2d": h2d,
+    "d2h": d2h,
+    "serving": lambda P, W, torch, stream: serving(P, W, torch, stream),
+    "cpu_events": cpu_events,
+}
+EXTRA_ORDER = ["single_conversion", "copy_peak", "round_trip", "jagged", "batched", "sweep", "h2d", "d2h",
+               "serving", "cpu_events"]
 
 
 if __name__ == "__main__":

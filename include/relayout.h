@@ -230,8 +230,8 @@ rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t group,
 
 /* Options of rl_transfer. */
 typedef enum rl_xfer_mode {
-  RL_XFER_AUTO = 0,      /* zero-copy for pinned collections without jagged
-                            groups, staged otherwise */
+  RL_XFER_AUTO = 0,      /* zero-copy for pinned collections, staged for
+                            pageable ones */
   RL_XFER_STAGED = 1,    /* DMA copies of the host buffers into a device
                             staging buffer of the library (one per stream,
                             grown on demand, kept until the process ends),
@@ -256,6 +256,24 @@ typedef struct rl_xfer_opts {
  * Zero-copy needs pinned host memory.  Errors as rl_convert. */
 rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n,
                       void* stream, const rl_xfer_opts* opts);
+
+/* Copy `bytes` from src, in memory context src_space, to dst, in dst_space
+ * (Sec. VII-A: copies between memory contexts, with the variants for
+ * partially overlapping arrays that insertion and deletion use).
+ *  - device -> device: a copy kernel; the ranges may overlap (the result
+ *    is as if the source went through a separate buffer first).  Moves of
+ *    overlapping ranges by less than 64 MiB go through a 64 MiB per-stream
+ *    scratch buffer of the library (allocated on first use, held until the
+ *    process ends), band by band.
+ *  - host <-> device: a DMA-engine copy; host memory that is pageable is
+ *    copied synchronously by the runtime.
+ *  - host -> host: memmove, once the stream has finished its earlier work
+ *    (synchronous).
+ * Asynchronous on `stream` otherwise.  Errors: RL_EINVAL (bad context,
+ * NULL pointer with bytes > 0), RL_ENOMEM (scratch), RL_EHIP.
+ * bytes == 0: RL_OK, nothing enqueued. */
+rl_status rl_memcopy(void* dst, rl_space dst_space, const void* src,
+                     rl_space src_space, uint64_t bytes, void* stream);
 
 /* rl_transfer for callers that cannot allocate memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation.
@@ -378,7 +396,7 @@ typedef struct rl_server_stats {
 
 /* A serving loop: events are admitted in arrival order while their result
  * bytes (plus, while converting, the device staging of collections that
- * are copied before conversion: jagged or pageable ones) fit the budget
+ * are copied before conversion: pageable ones) fit the budget
  * and a slot is free; admitted events convert concurrently on the server's
  * streams; results stay resident until released.  All of it is carved
  * from one device allocation of budget_bytes made at creation.  The caller

@@ -73,6 +73,7 @@ def _load():
             build()
         _lib = ctypes.CDLL(_LIB)
         _lib.or_convert_objects.restype = ctypes.c_int
+        _lib.or_convert_objects_range.restype = ctypes.c_int
         _lib.or_convert_group.restype = ctypes.c_int
         _lib.or_exclusive_scan.restype = ctypes.c_int
         _lib.or_rounding_is_nearest.restype = ctypes.c_int
@@ -405,6 +406,35 @@ def convert(src: Layout, src_bufs, dst: Layout, n: int, src_members=(),
         if st != ST_OK:
             return st, dst_bufs, totals
     return ST_OK, dst_bufs, totals
+
+
+class Prepared:
+    """One dense conversion with its buffers set up once, for timing the
+    oracle's loop alone (no allocation or packing per run): ``run(threads)``
+    converts objects 0..n-1 split into ``threads`` contiguous ranges, one
+    host thread each (ctypes releases the GIL during the C call)."""
+
+    def __init__(self, src: Layout, src_bufs, dst: Layout, n: int):
+        self.n = n
+        self.src_bufs = [np.ascontiguousarray(b).view(np.uint8).reshape(-1) for b in src_bufs]
+        self.dst_bufs = zeros_like_layout(dst, n, [0] * dst.schema.n_groups)
+        self.keep = []
+        self.so = _objects_struct(src, self.src_bufs, self.keep)
+        self.do = _objects_struct(dst, self.dst_bufs, self.keep)
+        self.n_leaves = len(src.schema.leaves)
+
+    def _range(self, i0, i1):
+        return _load().or_convert_objects_range(ctypes.byref(self.so), ctypes.byref(self.do),
+                                                ctypes.c_uint32(self.n_leaves), ctypes.c_uint64(i0),
+                                                ctypes.c_uint64(i1))
+
+    def run(self, threads=1, pool=None):
+        if threads <= 1:
+            return self._range(0, self.n)
+        step = (self.n + threads - 1) // threads
+        futs = [pool.submit(self._range, k * step, min(self.n, (k + 1) * step)) for k in range(threads)]
+        sts = [f.result() for f in futs]
+        return max(sts)
 
 
 def _count_members(L: Layout, bufs, g, n):

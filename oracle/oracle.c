@@ -121,17 +121,25 @@ int or_rounding_is_nearest(void) { return fegetround() == FE_TONEAREST; }
 
 /* For every object in order, for every leaf in schema order, move the value.
    The destination is expected zero-filled by the caller, so padding bytes
-   and the unused slots of a last partial AoSoA block stay zero. */
-int or_convert_objects(const or_objects* src, const or_objects* dst,
-                       uint32_t n_leaves, uint64_t n) {
+   and the unused slots of a last partial AoSoA block stay zero.
+   or_convert_objects_range does objects i0 .. i1-1 only; contiguous ranges
+   on several threads (for timing on all host cores) give the same bytes,
+   since every object's values land at addresses of that object alone. */
+int or_convert_objects_range(const or_objects* src, const or_objects* dst,
+                             uint32_t n_leaves, uint64_t i0, uint64_t i1) {
   if (!or_rounding_is_nearest()) return ST_UNSUPPORTED;
-  for (uint64_t i = 0; i < n; ++i)
+  for (uint64_t i = i0; i < i1; ++i)
     for (uint32_t c = 0; c < n_leaves; ++c) {
       int st = move_value(src->type[c], leaf_addr(src, c, i),
                           dst->type[c], leaf_addr(dst, c, i));
       if (st != ST_OK) return st;
     }
   return ST_OK;
+}
+
+int or_convert_objects(const or_objects* src, const or_objects* dst,
+                       uint32_t n_leaves, uint64_t n) {
+  return or_convert_objects_range(src, dst, n_leaves, 0, n);
 }
 
 /* ---- jagged groups ---------------------------------------------------- */

@@ -112,6 +112,7 @@ SIGNATURES = {
     "rl_offsets": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint32, ctypes.c_uint64, _P(ctypes.c_uint64), _VP]),
     "rl_transfer": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
     "rl_transfer_noalloc": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
+    "rl_memcopy": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_uint64, _VP]),
     "rl_sync": (ctypes.c_int, [_VP]),
     "rl_last_error": (ctypes.c_char_p, []),
     "rl_batch_create": (ctypes.c_int, [_P(rl_batch_opts), _P(_VP)]),
@@ -286,6 +287,13 @@ def sync(stream=None):
 def transfer(src: View, dst: View, n: int, stream=None, mode="auto"):
     o = rl_xfer_opts(XFER_MODES[mode])
     check(lib().rl_transfer(src.ref(), dst.ref(), n, stream_ptr(stream), ctypes.byref(o)), "rl_transfer")
+
+
+def memcopy(dst, dst_space, src, src_space, nbytes, stream=None):
+    """rl_memcopy: copy between memory contexts ("device", "host", "pinned");
+    overlapping device ranges move with memmove semantics."""
+    check(lib().rl_memcopy(_ptr(dst), SPACES[dst_space], _ptr(src), SPACES[src_space], nbytes,
+                           stream_ptr(stream)), "rl_memcopy")
 
 
 def transfer_noalloc(src: View, dst: View, n: int, stream=None, mode="auto"):

@@ -234,6 +234,8 @@ uint32_t jagged_lds_bytes(const JaggedDesc& j);
 constexpr uint32_t jagged_stage_members(uint32_t words) { return (8192 / words) / 64 * 64; }
 // Zero `bytes` of device memory with a kernel (usable where a memset node is not).
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
+// Plain copy between disjoint ranges reachable from the device.
+hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s);
 // Device address of the status words of the current device.
 hipError_t status_words(uint32_t** out);
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,

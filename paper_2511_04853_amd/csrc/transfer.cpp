@@ -132,7 +132,7 @@ bool transfer_is_staged(const rl_view& hv, const rl_xfer_opts* opts) {
   const rl_xfer_mode m = opts ? opts->mode : RL_XFER_AUTO;
   if (m == RL_XFER_STAGED) return true;
   if (m == RL_XFER_ZERO_COPY) return false;
-  return !hv.layout->schema->members.empty() || hv.layout->space != RL_SPACE_HOST_PINNED;
+  return hv.layout->space != RL_SPACE_HOST_PINNED;
 }
 
 rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipStream_t stream,
@@ -158,9 +158,10 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
   if (o.mode < RL_XFER_AUTO || o.mode > RL_XFER_ZERO_COPY) return fail(RL_EINVAL, "bad transfer mode");
   const rl_layout* HL = h2d ? SL : DL;
   const rl_view& hv = h2d ? *src : *dst;
-  // auto: dense collections in pinned memory are read (or written) in place
-  // by the conversion kernels; others go through device staging
-  if (o.mode == RL_XFER_AUTO) o.mode = (!jagged && HL->space == RL_SPACE_HOST_PINNED) ? RL_XFER_ZERO_COPY : RL_XFER_STAGED;
+  // auto: collections in pinned memory are read (or written) in place by
+  // the conversion kernels (measured at the link rate, jagged ones too);
+  // pageable ones go through device staging
+  if (o.mode == RL_XFER_AUTO) o.mode = transfer_is_staged(hv, &o) ? RL_XFER_STAGED : RL_XFER_ZERO_COPY;
   if (o.mode == RL_XFER_ZERO_COPY) {
     if (HL->space != RL_SPACE_HOST_PINNED) return fail(RL_EUNSUPPORTED, "zero-copy needs pinned host memory");
     const uint32_t nb = layout_n_buffers(HL);
