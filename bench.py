@@ -59,13 +59,19 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-events", type=int, default=10_000,
+                    help="events per rate in the serving leg (fewer for a traced run)")
     ap.add_argument("--leg", choices=sorted(LEGS),
                     help="run only this extra leg and print its JSON (for profiling one leg)")
     return ap.parse_args()
 
 
+SERVING_EVENTS = [10_000]
+
+
 def main():
     args = parse()
+    SERVING_EVENTS[0] = args.serving_events
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               "(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
@@ -79,16 +85,16 @@ def main():
     P.lib()
     stream = torch.cuda.current_stream()
     sp = P.stream_ptr(stream)
+    # calibration: one dispatch of the library's copy kernel moving 64 MiB
+    # (untimed), for scaling the HBM byte counters of a profiled run
+    calib = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
+    calib2 = torch.empty_like(calib)
+    P.memcopy(calib2, "device", calib, "device", 64 << 20, stream)
+    torch.cuda.synchronize()
+    del calib, calib2
     if args.leg:
         print(json.dumps(LEGS[args.leg](P, Wk, torch, stream)), flush=True)
         return
-
-    # calibration copy of known size for the HBM byte counters (untimed)
-    calib = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
-    calib2 = torch.empty_like(calib)
-    calib2.copy_(calib)
-    torch.cuda.synchronize()
-    del calib, calib2
 
     S = P.Schema(Wk.CELL)
     narrowed = ["f32" if f.type == "f64" else f.type for f in Wk.CELL.fields]
@@ -454,7 +460,7 @@ def single_conversion(P, W, torch, stream, sets=32):
 def copy_peak(P, W, torch, stream):
     """The attainable HBM rate: the library's plain 16-byte vector copy
     kernel (rl_memcopy, device to device) over 1 GiB buffers, three pairs
-    rotating (cold); and the launch floor (back-to-back copies of 16 bytes)."""
+    rotating (cold); and back-to-back copies of 16 bytes from Python."""
     size = 1 << 30
     a = [torch.empty(size, dtype=torch.uint8, device="cuda") for _ in range(3)]
     b = [torch.empty(size, dtype=torch.uint8, device="cuda") for _ in range(3)]
@@ -466,8 +472,10 @@ def copy_peak(P, W, torch, stream):
            "GBps_read_plus_write": round(2 * size / (ms * 1e-3) / 1e9, 1),
            "frac_of_spec": round(2 * size / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     assert torch.equal(b[0][:4096], a[0][:4096])
+    # back-to-back 16-byte copies issued from Python: bound by the host's
+    # submission rate (ctypes call + launch), an upper bound of the floor
     small = lambda k=0: P.memcopy(b[0], "device", a[0], "device", 16, stream)
-    res["launch_floor_us"] = round(_time(small, stream, torch, reps=200, warm=10) * 1e3, 3)
+    res["submit_floor_us"] = round(_time(small, stream, torch, reps=200, warm=10) * 1e3, 3)
     del a, b
     return res
 
@@ -731,15 +739,16 @@ def serving(P, W, torch, stream, rates=(1000, 3000), n_events=10_000, hold=512, 
                 "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
                 "events_per_s": round(count / span, 1)}
 
-    for k in range(200):   # warm-up
+    for k in range(min(200, n_events)):   # warm-up
         serve_one(k)
     loop = {}
     for rate in rates:
-        loop[f"{rate}/s"] = loop_run(rate, 3000, seed=3004 + rate)
+        loop[f"{rate}/s"] = loop_run(rate, min(3000, n_events), seed=3004 + rate)
+    nb = min(3000, n_events)
     t = time.perf_counter()
-    for k in range(3000):
+    for k in range(nb):
         serve_one(k)
-    loop["back_to_back"] = {"events": 3000, "events_per_s": round(3000 / (time.perf_counter() - t), 1)}
+    loop["back_to_back"] = {"events": nb, "events_per_s": round(nb / (time.perf_counter() - t), 1)}
     res["per_event_loop"] = loop
     res["server_over_loop_throughput"] = round(res["saturation_offered_6000/s"]["events_per_s"] /
                                                loop["back_to_back"]["events_per_s"], 3)
@@ -1042,7 +1051,8 @@ LEGS = {
     "sweep": sweep,
     "h2d": h2d,
     "d2h": d2h,
-    "serving": lambda P, W, torch, stream: serving(P, W, torch, stream),
+    "serving": lambda P, W, torch, stream: serving(P, W, torch, stream, n_events=SERVING_EVENTS[0],
+                                                   warmup=min(1000, SERVING_EVENTS[0])),
     "cpu_events": cpu_events,
 }
 EXTRA_ORDER = ["single_conversion", "copy_peak", "round_trip", "jagged", "batched", "sweep", "h2d", "d2h",
