@@ -74,6 +74,8 @@ def _load():
         _lib = ctypes.CDLL(_LIB)
         _lib.or_convert_objects.restype = ctypes.c_int
         _lib.or_convert_objects_range.restype = ctypes.c_int
+        _lib.or_gather_objects.restype = ctypes.c_int
+        _lib.or_gather_group.restype = ctypes.c_int
         _lib.or_convert_group.restype = ctypes.c_int
         _lib.or_exclusive_scan.restype = ctypes.c_int
         _lib.or_rounding_is_nearest.restype = ctypes.c_int
@@ -406,6 +408,99 @@ def convert(src: Layout, src_bufs, dst: Layout, n: int, src_members=(),
         if st != ST_OK:
             return st, dst_bufs, totals
     return ST_OK, dst_bufs, totals
+
+
+def gather_into(src: Layout, src_bufs, dst: Layout, dst_bufs, idx, k0=0, base=(), src_members=(),
+                dst_capacity=()):
+    """Gather (the plain definition behind insertion, deletion and
+    compaction, Sec. VII-B): destination object k0 + k takes every value of
+    source object idx[k]; per jagged group g the members of the gathered
+    objects are placed one object after the other from destination member
+    base[g] on.  dst_bufs (numpy uint8 arrays of the destination layout) are
+    modified in place.  Returns (status, ends) with ends[g] the member index
+    after the last one placed."""
+    lib = _load()
+    S = src.schema
+    src_bufs = [np.ascontiguousarray(b).view(np.uint8).reshape(-1) for b in src_bufs]
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+    m = len(idx)
+    keep = [idx]
+    so = _objects_struct(src, src_bufs, keep)
+    do = _objects_struct(dst, dst_bufs, keep)
+    ip = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    st = lib.or_gather_objects(ctypes.byref(so), ctypes.byref(do), ctypes.c_uint32(len(S.leaves)), ip,
+                               ctypes.c_uint64(m), ctypes.c_uint64(k0))
+    ends = []
+    if st != ST_OK:
+        return st, ends
+    for g in range(S.n_groups):
+        sg = _group_struct(src, g, src_bufs, src_members[g], keep)
+        dg = _group_struct(dst, g, dst_bufs, dst_capacity[g], keep)
+        end = ctypes.c_uint64(0)
+        st = lib.or_gather_group(ctypes.byref(sg), ctypes.byref(dg), ip, ctypes.c_uint64(m), ctypes.c_uint64(k0),
+                                 ctypes.c_uint64(base[g] if base else 0), ctypes.byref(end))
+        ends.append(end.value)
+        if st != ST_OK:
+            return st, ends
+    return ST_OK, ends
+
+
+def _lengths(L: Layout, bufs, g, n):
+    """Member counts of objects 0..n-1 of group g (records' counts, or
+    differences of the offsets)."""
+    S = L.schema
+    if L.kind == "aos":
+        off = L.slot_offsets[S.slots.index(("len", g))]
+        rec = np.ascontiguousarray(bufs[0]).view(np.uint8)[:n * L.stride].reshape(n, L.stride)
+        return rec[:, off:off + 4].copy().view(np.uint32).reshape(-1).astype(np.uint64)
+    o = np.ascontiguousarray(bufs[_group_buffers(L, g, bufs)]).view(NP_DTYPE[S.decl.offset_types[g]])
+    return (o[1:n + 1].astype(np.int64) - o[:n].astype(np.int64)).astype(np.uint64)
+
+
+def select(src: Layout, src_bufs, dst: Layout, n: int, keep_flags, src_members=()):
+    """Compaction after a filter: the objects i < n with keep_flags[i] != 0,
+    in order, into fresh zero-filled buffers of layout dst (members of each
+    group packed from 0).  Returns (status, dst_bufs, count, totals)."""
+    idx = np.nonzero(np.asarray(keep_flags)[:n])[0].astype(np.uint64)
+    S = src.schema
+    tots = [int(_lengths(src, src_bufs, g, n)[idx].sum()) for g in range(S.n_groups)]
+    out = zeros_like_layout(dst, len(idx), tots)
+    st, _ = gather_into(src, src_bufs, dst, out, idx, 0, [0] * S.n_groups, src_members, tots)
+    return st, out, len(idx), tots
+
+
+def erase(L: Layout, bufs, n: int, at: int, count: int, members=()):
+    """Objects [at, at + count) removed from a collection of n objects: the
+    objects before and after them, in order, in fresh buffers of the same
+    layout.  Returns (status, bufs, totals)."""
+    idx = np.concatenate([np.arange(at, dtype=np.uint64), np.arange(at + count, n, dtype=np.uint64)])
+    S = L.schema
+    tots = [int(_lengths(L, bufs, g, n)[idx].sum()) for g in range(S.n_groups)]
+    out = zeros_like_layout(L, len(idx), tots)
+    st, _ = gather_into(L, bufs, L, out, idx, 0, [0] * S.n_groups, members, tots)
+    return st, out, tots
+
+
+def insert(L: Layout, bufs, n: int, at: int, new_L: Layout, new_bufs, count: int, members=(), new_members=()):
+    """`count` objects of a second collection (layout new_L) inserted before
+    object `at` of a collection of n objects (at == n appends): objects
+    0..at-1, then the new ones, then objects at..n-1, in fresh buffers of
+    layout L; members follow their objects.  Returns (status, bufs, totals)."""
+    S = L.schema
+    old_len = [_lengths(L, bufs, g, n) for g in range(S.n_groups)]
+    new_len = [_lengths(new_L, new_bufs, g, count) for g in range(S.n_groups)]
+    tots = [int(old_len[g].sum() + new_len[g].sum()) for g in range(S.n_groups)]
+    out = zeros_like_layout(L, n + count, tots)
+    base = [0] * S.n_groups
+    parts = [(L, bufs, np.arange(at, dtype=np.uint64), 0, members),
+             (new_L, new_bufs, np.arange(count, dtype=np.uint64), at, new_members),
+             (L, bufs, np.arange(at, n, dtype=np.uint64), at + count, members)]
+    for sl, sb, idx, k0, mem in parts:
+        st, ends = gather_into(sl, sb, L, out, idx, k0, base, mem, tots)
+        if st != ST_OK:
+            return st, out, tots
+        base = ends if ends else base
+    return ST_OK, out, tots
 
 
 class Prepared:

@@ -293,3 +293,97 @@ int or_exclusive_scan(const uint32_t* lengths, uint64_t n, unsigned char* offset
   if (total_out) *total_out = run;
   return overflow ? ST_OVERFLOW : ST_OK;
 }
+
+/* ---- gathers: insertion, deletion and compaction ------------------------- */
+
+/*
+ * Insertion and deletion on the arrays of a collection (Sec. VII-B) and the
+ * compaction of a filtered collection all give a collection whose objects
+ * are existing objects in a chosen order.  The plain definition: a gather.
+ * Destination object k0 + k takes every per-object value of source object
+ * idx[k], for k = 0 .. m-1 (moved as in or_convert_objects).
+ */
+int or_gather_objects(const or_objects* src, const or_objects* dst, uint32_t n_leaves,
+                      const uint64_t* idx, uint64_t m, uint64_t k0) {
+  if (!or_rounding_is_nearest()) return ST_UNSUPPORTED;
+  for (uint64_t k = 0; k < m; ++k)
+    for (uint32_t c = 0; c < n_leaves; ++c) {
+      int st = move_value(src->type[c], leaf_addr(src, c, idx[k]),
+                          dst->type[c], leaf_addr(dst, c, k0 + k));
+      if (st != ST_OK) return st;
+    }
+  return ST_OK;
+}
+
+/*
+ * The members of one jagged group in a gather: destination object k0 + k
+ * receives the members of source object idx[k], placed one object after
+ * the other from destination member `base` on.  The destination's offsets
+ * entries k0 .. k0 + m are written (entry k0 = base), or its records'
+ * (ptr, len) pairs with ptr = member index times the member stride.  The
+ * status reports, in this order of precedence: an end beyond the offset
+ * type, an end beyond the destination capacity, a gathered source member
+ * block outside its storage (or misaligned).  *end_out receives the member
+ * index after the last one placed.
+ */
+int or_gather_group(const or_group* src, const or_group* dst, const uint64_t* idx,
+                    uint64_t m, uint64_t k0, uint64_t base, uint64_t* end_out) {
+  uint64_t run = base;
+  int overflow = 0, bounds = 0;
+  uint64_t limit = dst->form == 1 ? offset_type_max(dst->off_type) : UINT64_MAX;
+  if (!or_rounding_is_nearest()) return ST_UNSUPPORTED;
+  for (uint64_t k = 0; k < m; ++k) {
+    uint64_t len = src_length(src, idx[k]);
+    if (dst->form == 1) store_uint(dst->offsets + (k0 + k) * type_size(dst->off_type),
+                                   dst->off_type, run);
+    if (run + len < run || run + len > limit) overflow = 1;
+    run += len;
+  }
+  if (dst->form == 1) store_uint(dst->offsets + (k0 + m) * type_size(dst->off_type),
+                                 dst->off_type, run);
+  if (end_out) *end_out = run;
+  if (overflow || run > limit) return ST_OVERFLOW;
+  if (run > dst->capacity) return ST_CAPACITY;
+
+  for (uint64_t k = 0; k < m; ++k) {
+    uint64_t i = idx[k], len = src_length(src, i);
+    if (src->form == 0) {
+      uint64_t ptr;
+      memcpy(&ptr, src->records + i * src->rec_stride + src->ptr_off, 8);
+      if (ptr % src->malign != 0) { bounds = 1; continue; }
+      if (ptr > src->capacity * src->mstride ||
+          len > (src->capacity * src->mstride - ptr) / src->mstride) bounds = 1;
+    } else {
+      uint64_t first = src_first(src, i);
+      if (first > src->capacity || len > src->capacity - first) bounds = 1;
+    }
+  }
+  if (bounds) return ST_BOUNDS;
+
+  run = base;
+  for (uint64_t k = 0; k < m; ++k) {
+    uint64_t i = idx[k], len = src_length(src, i);
+    uint64_t sptr = 0, sfirst = 0;
+    if (src->form == 0) memcpy(&sptr, src->records + i * src->rec_stride + src->ptr_off, 8);
+    else sfirst = src_first(src, i);
+    if (dst->form == 0) {
+      uint64_t dptr = run * dst->mstride;
+      uint32_t dlen = (uint32_t)len;
+      memcpy(dst->records + (k0 + k) * dst->rec_stride + dst->ptr_off, &dptr, 8);
+      memcpy(dst->records + (k0 + k) * dst->rec_stride + dst->len_off, &dlen, 4);
+    }
+    for (uint64_t j = 0; j < len; ++j)
+      for (uint32_t mm = 0; mm < src->n_members; ++mm) {
+        const unsigned char* s = src->form == 0
+            ? member_addr_ptr(src, sptr, j, mm)
+            : src->mcol[mm] + (sfirst + j) * type_size(src->type[mm]);
+        unsigned char* d = dst->form == 0
+            ? dst->pool + (run + j) * dst->mstride + dst->moff[mm]
+            : dst->mcol[mm] + (run + j) * type_size(dst->type[mm]);
+        int st = move_value(src->type[mm], s, dst->type[mm], d);
+        if (st != ST_OK) return st;
+      }
+    run += len;
+  }
+  return ST_OK;
+}
