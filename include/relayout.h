@@ -228,6 +228,58 @@ rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t n,
 rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t group,
                      uint64_t n, uint64_t* total_host, void* stream);
 
+/* ------------------------------------------------------------------ insertion, deletion, compaction */
+
+/* Compaction after a filter (Sec. VII-B: operations on every property's
+ * array of a collection): dst receives, in order, the objects i < n of src
+ * whose keep[i] != 0; every value moves as rl_convert moves it, and each
+ * jagged group's members follow their objects, packed from member 0 in
+ * dst (offsets rebuilt, or record pointers = first member index * member
+ * record size).  keep: n bytes of device memory.  n_kept: NULL, or device
+ * memory receiving the kept count (u64).  dst must hold n objects (the
+ * count is only known on the device); dst's slots past the kept objects
+ * are left zero in AoSoA blocks and record padding.  Any layout kinds on
+ * either side; the schemas must be the same object.
+ * Host errors: as rl_convert (RL_EINVAL also for keep == NULL with n > 0).
+ * Device errors (rl_sync): RL_EOVERFLOW (member total beyond dst's offset
+ * type), RL_ECAPACITY (beyond dst's member capacity: members that do not
+ * fit are not written), RL_EBOUNDS (a kept object's member block outside
+ * src's storage: its members are not copied).  Uses a per-stream scratch
+ * buffer of the library (about 16 bytes per object; allocated on first
+ * use, grown when needed, held until the process ends). */
+rl_status rl_select(const rl_view* src, const rl_view* dst, uint64_t n,
+                    const uint8_t* keep, uint64_t* n_kept, void* stream);
+
+/* Erase objects [at, at + count) of a view holding n objects, in place
+ * (Sec. VII-B: the layout holder's erase on every array): objects
+ * [at + count, n) move to [at, n - count), as if through a separate buffer;
+ * the view then holds n - count objects and the unused slots of its last
+ * AoSoA block are zero.  Collections with jagged groups: only the last
+ * objects (at + count == n; nothing moves), else RL_EUNSUPPORTED.
+ * Errors: RL_EINVAL (range outside n objects), as rl_convert for the view.
+ * AoSoA views move through a per-stream scratch buffer of the library
+ * (at most 64 MiB, allocated on first use). */
+rl_status rl_erase(const rl_view* view, uint64_t n, uint64_t at, uint64_t count,
+                   void* stream);
+
+/* Insert objects 0 .. count-1 of src before object `at` of a view holding
+ * n objects, in place (Sec. VII-B: the layout holder's insert; at == n
+ * appends): objects [at, n) move to [at + count, n + count) as if through a
+ * separate buffer, then src's objects are converted into [at, at + count)
+ * (copy / narrowing / widening as the storage types say).  The view's
+ * capacity must hold n + count objects; src must not overlap it.  Jagged
+ * groups: appends only (at == n), between offsets layouts (SoA / AoSoA on
+ * both sides): src's members follow the view's, offsets entries
+ * n .. n + count continue from the view's total.
+ * Host errors: RL_EINVAL (position or capacity), RL_EUNSUPPORTED (jagged
+ * other than an append between offsets layouts), as rl_convert otherwise.
+ * Device errors (rl_sync, appends): RL_ECAPACITY (members beyond the view's
+ * member capacity: nothing appended to that group), RL_EOVERFLOW (total
+ * beyond the offset type, or decreasing src offsets), RL_EBOUNDS (src
+ * offsets beyond src's member capacity). */
+rl_status rl_insert(const rl_view* view, uint64_t n, uint64_t at,
+                    const rl_view* src, uint64_t count, void* stream);
+
 /* Options of rl_transfer. */
 typedef enum rl_xfer_mode {
   RL_XFER_AUTO = 0,      /* zero-copy for pinned collections, staged for

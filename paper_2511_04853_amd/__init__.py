@@ -113,6 +113,9 @@ SIGNATURES = {
     "rl_transfer": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
     "rl_transfer_noalloc": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
     "rl_memcopy": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_uint64, _VP]),
+    "rl_select": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _VP, _VP]),
+    "rl_erase": (ctypes.c_int, [_P(rl_view), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _VP]),
+    "rl_insert": (ctypes.c_int, [_P(rl_view), ctypes.c_uint64, ctypes.c_uint64, _P(rl_view), ctypes.c_uint64, _VP]),
     "rl_sync": (ctypes.c_int, [_VP]),
     "rl_last_error": (ctypes.c_char_p, []),
     "rl_batch_create": (ctypes.c_int, [_P(rl_batch_opts), _P(_VP)]),
@@ -294,6 +297,22 @@ def memcopy(dst, dst_space, src, src_space, nbytes, stream=None):
     overlapping device ranges move with memmove semantics."""
     check(lib().rl_memcopy(_ptr(dst), SPACES[dst_space], _ptr(src), SPACES[src_space], nbytes,
                            stream_ptr(stream)), "rl_memcopy")
+
+
+def select(src: View, dst: View, n: int, keep, n_kept=None, stream=None):
+    """rl_select: the objects i < n of src with keep[i] != 0 (device bytes),
+    in order, into dst; n_kept: optional device u64 receiving the count."""
+    check(lib().rl_select(src.ref(), dst.ref(), n, _ptr(keep), _ptr(n_kept), stream_ptr(stream)), "rl_select")
+
+
+def erase(view: View, n: int, at: int, count: int, stream=None):
+    """rl_erase: objects [at, at + count) of a view of n objects removed in place."""
+    check(lib().rl_erase(view.ref(), n, at, count, stream_ptr(stream)), "rl_erase")
+
+
+def insert(view: View, n: int, at: int, src: View, count: int, stream=None):
+    """rl_insert: src's objects 0..count-1 inserted before object `at` in place."""
+    check(lib().rl_insert(view.ref(), n, at, src.ref(), count, stream_ptr(stream)), "rl_insert")
 
 
 def transfer_noalloc(src: View, dst: View, n: int, stream=None, mode="auto"):

@@ -1504,6 +1504,287 @@ __global__ void __launch_bounds__(256) copy_kernel(uint8_t* dst, const uint8_t* 
   for (uint64_t b = head + (nv << 4) + tid; b < bytes; b += nt) gp(dst)[b] = gp(src)[b];
 }
 
+// ------------------------------------------------------------------ insertion, deletion, compaction
+//
+// Insertion and deletion on a collection's arrays and the compaction of a
+// filtered collection (Sec. VII-B) are gathers: destination object k takes
+// every value of a chosen source object.  The mover below handles any pair
+// of layout kinds at any object index, one thread per object (simple and
+// general: these are not the bandwidth-critical path); members of jagged
+// groups move with a wave per object.
+
+template <class GS>
+__device__ __forceinline__ uint8_t* gen_addr(const GS& s, uint32_t c, uint32_t size, uint64_t i) {
+  if (s.kind == KIND_AOS) return s.base + i * s.stride + s.off[c];
+  if (s.kind == KIND_SOA) return s.col[c] + i * size;
+  const uint64_t blk = i / s.width;
+  return s.base + blk * s.width * s.obj_bytes + (uint64_t)s.width * s.off[c] + (i - blk * s.width) * size;
+}
+
+// A value of 1, 2, 4 or 8 bytes at any address (little-endian).
+__device__ __forceinline__ uint64_t gload(const uint8_t* p, uint32_t size) {
+  if (((uintptr_t)p & (size - 1)) == 0) {
+    switch (size) {
+      case 1: return *gp(p);
+      case 2: return *gp(reinterpret_cast<const uint16_t*>(p));
+      case 4: return *gp(reinterpret_cast<const uint32_t*>(p));
+      default: return *gp(reinterpret_cast<const uint64_t*>(p));
+    }
+  }
+  uint64_t v = 0;
+  for (uint32_t k = 0; k < size; ++k) v |= (uint64_t)gp(p)[k] << (8 * k);
+  return v;
+}
+
+__device__ __forceinline__ void gstore(uint8_t* p, uint32_t size, uint64_t v) {
+  if (((uintptr_t)p & (size - 1)) == 0) {
+    switch (size) {
+      case 1: *gp(p) = (uint8_t)v; return;
+      case 2: *gp(reinterpret_cast<uint16_t*>(p)) = (uint16_t)v; return;
+      case 4: *gp(reinterpret_cast<uint32_t*>(p)) = (uint32_t)v; return;
+      default: *gp(reinterpret_cast<uint64_t*>(p)) = v; return;
+    }
+  }
+  for (uint32_t k = 0; k < size; ++k) gp(p)[k] = (uint8_t)(v >> (8 * k));
+}
+
+__device__ __forceinline__ uint64_t gop(uint64_t v, uint32_t op) {
+  if (op == OP_NARROW) return __float_as_uint(narrow_value(__longlong_as_double((long long)v)));
+  if (op == OP_WIDEN) return (uint64_t)__double_as_longlong(widen_value(__uint_as_float((uint32_t)v)));
+  return v;
+}
+
+__global__ void __launch_bounds__(256) move_kernel(const MoveDesc) {
+  const RL_C MoveDesc& d = kernel_arg<MoveDesc>();
+  const uint64_t count = d.count_dev ? *gp(d.count_dev) : d.count;
+  const uint64_t nt = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count; k += nt) {
+    const uint64_t i = d.map ? gp(d.map)[k] : d.src0 + k;
+    const uint64_t o = d.dst0 + k;
+    for (uint32_t c = 0; c < d.n_leaves; ++c) {
+      uint8_t* dp = gen_addr(d.dst, c, d.dst_size[c], o);
+      if (d.zero_only) {
+        gstore(dp, d.dst_size[c], 0);
+        continue;
+      }
+      gstore(dp, d.dst_size[c], gop(gload(gen_addr(d.src, c, d.src_size[c], i), d.src_size[c]), d.op[c]));
+    }
+  }
+}
+
+// Member count and first member index of object i of a group (form 0:
+// validated against the pool; form 1: against the member storage).  *ok
+// false for a block outside its storage.
+template <class GG>
+__device__ __forceinline__ void gen_block(const GG& g, uint64_t i, uint64_t* len, uint64_t* first, bool* ok) {
+  if (g.form == 0) {
+    const uint8_t* rec = g.records + i * g.rec_stride;
+    const uint64_t l = gload(rec + g.len_off, 4);
+    const uint64_t p = gload(rec + g.ptr_off, 8);
+    const uint64_t pool_end = g.capacity * g.mstride;
+    *ok = (p & (uint64_t)(g.malign - 1)) == 0 && p <= pool_end && l <= (pool_end - p) / g.mstride;
+    *len = l;
+    *first = p / g.mstride;
+  } else {
+    const uint64_t a = load_off(g.offsets, g.off_type, i), b = load_off(g.offsets, g.off_type, i + 1);
+    *ok = b >= a && a <= g.capacity && b - a <= g.capacity - a;
+    *len = b >= a ? b - a : 0;
+    *first = a;
+  }
+}
+
+template <class GG>
+__device__ __forceinline__ uint8_t* gen_member(const GG& g, uint64_t first, uint64_t j, uint32_t q) {
+  if (g.form == 0) return g.pool + (first + j) * g.mstride + g.moff[q];
+  return g.mcol[q] + (first + j) * g.msize[q];
+}
+
+// Block-wide sum of one u64 per thread (result valid in every thread).
+__device__ __forceinline__ uint64_t block_sum(uint64_t v, uint64_t* wsum) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum_u64(v);
+  if (lane == 0) wsum[wave] = v;
+  __syncthreads();
+  uint64_t s = 0;
+  for (uint32_t w = 0; w < nw; ++w) s += wsum[w];
+  __syncthreads();
+  return s;
+}
+
+// Compaction, pass 1: kept flags per tile.
+__global__ void __launch_bounds__(256) select_count_kernel(const SelectDesc d) {
+  __shared__ uint64_t wsum[8];
+  const uint64_t i0 = (uint64_t)blockIdx.x * kSelectTile;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(kSelectTile, d.n - i0);
+  uint64_t c = 0;
+  for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) c += gp(d.keep)[i0 + k] != 0;
+  c = block_sum(c, wsum);
+  if (threadIdx.x == 0) gp(d.tile_tot)[blockIdx.x] = c;
+}
+
+// Exclusive scan of `ntiles` per-tile totals in place (one work-group);
+// the grand total goes to *total (and *total2 when set).
+__device__ void scan_tiles_body(uint64_t* tot, uint64_t ntiles, uint64_t* total, uint64_t* total2, uint64_t* wsum) {
+  uint64_t carry = 0;
+  for (uint64_t c0 = 0; c0 < ntiles; c0 += blockDim.x) {
+    const uint64_t k = c0 + threadIdx.x;
+    const uint64_t v = k < ntiles ? gp(tot)[k] : 0;
+    uint64_t all;
+    const uint64_t ex = block_exclusive_scan(v, wsum, &all);
+    if (k < ntiles) gp(tot)[k] = carry + ex;
+    carry += all;
+  }
+  if (threadIdx.x == 0) {
+    *gp(total) = carry;
+    if (total2) *gp(total2) = carry;
+  }
+}
+
+__global__ void __launch_bounds__(1024) select_scan_kernel(const SelectDesc d) {
+  __shared__ uint64_t wsum[17];
+  scan_tiles_body(d.tile_tot, (d.n + kSelectTile - 1) / kSelectTile, d.count, d.count_out, wsum);
+}
+
+// Compaction, pass 3: kept object indices at their places (each thread
+// takes four consecutive flags of its tile).
+__global__ void __launch_bounds__(256) select_map_kernel(const SelectDesc d) {
+  __shared__ uint64_t wsum[17];
+  const uint64_t i0 = (uint64_t)blockIdx.x * kSelectTile;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(kSelectTile, d.n - i0);
+  const uint32_t per = kSelectTile / blockDim.x;
+  const uint32_t o0 = threadIdx.x * per;
+  uint64_t c = 0;
+  for (uint32_t k = 0; k < per; ++k)
+    if (o0 + k < cnt) c += gp(d.keep)[i0 + o0 + k] != 0;
+  uint64_t all;
+  uint64_t pos = gp(d.tile_tot)[blockIdx.x] + block_exclusive_scan(c, wsum, &all);
+  for (uint32_t k = 0; k < per; ++k)
+    if (o0 + k < cnt && gp(d.keep)[i0 + o0 + k] != 0) gp(d.map)[pos++] = i0 + o0 + k;
+}
+
+// Members of the kept objects, pass 1: each kept object's member count
+// (lens[k]) and the per-tile sums (over kept-object tiles).
+__global__ void __launch_bounds__(256) select_lens_kernel(const SelectDesc d) {
+  __shared__ uint64_t wsum[8];
+  const uint64_t count = *gp(d.count);
+  const uint64_t k0 = (uint64_t)blockIdx.x * kSelectTile;
+  uint64_t c = 0;
+  for (uint32_t k = threadIdx.x; k < kSelectTile; k += blockDim.x) {
+    const uint64_t kk = k0 + k;
+    if (kk >= count) break;
+    uint64_t len, first;
+    bool ok;
+    gen_block(d.src, gp(d.map)[kk], &len, &first, &ok);
+    gp(d.lens)[kk] = len;
+    c += len;
+  }
+  c = block_sum(c, wsum);
+  if (threadIdx.x == 0) gp(d.tile_tot)[blockIdx.x] = c;
+}
+
+__global__ void __launch_bounds__(1024) select_lens_scan_kernel(const SelectDesc d) {
+  __shared__ uint64_t wsum[17];
+  // the total lands at lens[count]: the entry after the last kept object
+  scan_tiles_body(d.tile_tot, (d.n + kSelectTile - 1) / kSelectTile, d.lens + *gp(d.count), nullptr, wsum);
+}
+
+// Pass 3: lens[k] becomes the first member index of kept object k.
+__global__ void __launch_bounds__(256) select_offsets_kernel(const SelectDesc d) {
+  __shared__ uint64_t wsum[17];
+  const uint64_t count = *gp(d.count);
+  const uint64_t k0 = (uint64_t)blockIdx.x * kSelectTile;
+  const uint32_t per = kSelectTile / blockDim.x;
+  const uint64_t o0 = k0 + threadIdx.x * per;
+  uint64_t c = 0;
+  for (uint32_t k = 0; k < per; ++k)
+    if (o0 + k < count) c += gp(d.lens)[o0 + k];
+  uint64_t all;
+  uint64_t run = gp(d.tile_tot)[blockIdx.x] + block_exclusive_scan(c, wsum, &all);
+  for (uint32_t k = 0; k < per; ++k)
+    if (o0 + k < count) {
+      const uint64_t l = gp(d.lens)[o0 + k];
+      gp(d.lens)[o0 + k] = run;
+      run += l;
+    }
+}
+
+// Members of gathered objects: a wave per destination object.  Writes the
+// destination's offsets entries (form 1) or records' (pointer, count)
+// (form 0), checks the total against the offset type and the capacity,
+// and copies the members that fit.
+__global__ void __launch_bounds__(256) member_move_kernel(const MemberMoveDesc) {
+  const RL_C MemberMoveDesc& d = kernel_arg<MemberMoveDesc>();
+  const uint64_t count = *gp(d.count_dev);
+  const uint64_t total = gp(d.out_off)[count];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t limit = d.dst.form == 1 ? off_limit(d.dst.off_type) : ~0ull;
+  if (wave == 0 && lane == 0) {
+    if (total > limit) flag(d.status, ST_FLAG_OVERFLOW);
+    else if (total > d.dst.capacity) flag(d.status, ST_FLAG_CAPACITY);
+    if (d.dst.form == 1) store_off(d.dst.offsets, d.dst.off_type, count, total);
+  }
+  for (uint64_t k = wave; k < count; k += nwaves) {
+    const uint64_t i = gp(d.map)[k];
+    uint64_t len, first;
+    bool ok;
+    gen_block(d.src, i, &len, &first, &ok);
+    const uint64_t at = gp(d.out_off)[k];
+    if (lane == 0) {
+      if (!ok) flag(d.status, ST_FLAG_BOUNDS);
+      if (d.dst.form == 1) {
+        store_off(d.dst.offsets, d.dst.off_type, k, at);
+      } else {
+        uint8_t* rec = d.dst.records + k * d.dst.rec_stride;
+        gstore(rec + d.dst.ptr_off, 8, at * d.dst.mstride);
+        gstore(rec + d.dst.len_off, 4, len);
+      }
+    }
+    if (!ok || at > d.dst.capacity || len > d.dst.capacity - at) continue;   // wave-uniform
+    for (uint64_t j = lane; j < len; j += 64)
+      for (uint32_t q = 0; q < d.src.n_members; ++q)
+        gstore(gen_member(d.dst, at, j, q), d.dst.msize[q], gload(gen_member(d.src, first, j, q), d.src.msize[q]));
+  }
+}
+
+// Append to a resident jagged group (both sides offsets + member columns):
+// the destination's member count so far is its offsets entry `at`.
+__global__ void __launch_bounds__(256) append_kernel(const AppendDesc d) {
+  const uint64_t base = load_off(d.dst.offsets, d.dst.off_type, d.at);
+  const uint64_t s0 = load_off(d.src.offsets, d.src.off_type, 0);
+  const uint64_t s1 = load_off(d.src.offsets, d.src.off_type, d.count);
+  const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t nt = (uint64_t)gridDim.x * blockDim.x;
+  // checks every thread makes alike (uniform early exit)
+  uint32_t bad = 0;
+  if (s1 < s0) bad = ST_FLAG_OVERFLOW;
+  else if (s1 > d.src.capacity) bad = ST_FLAG_BOUNDS;
+  else if (base + (s1 - s0) < base || base + (s1 - s0) > off_limit(d.dst.off_type)) bad = ST_FLAG_OVERFLOW;
+  else if (base + (s1 - s0) > d.dst.capacity) bad = ST_FLAG_CAPACITY;
+  if (bad) {
+    if (tid == 0) flag(d.status, bad);
+    return;
+  }
+  bool decreasing = false;
+  for (uint64_t k = 1 + tid; k <= d.count; k += nt) {
+    const uint64_t v = load_off(d.src.offsets, d.src.off_type, k);
+    if (v < load_off(d.src.offsets, d.src.off_type, k - 1)) decreasing = true;
+    store_off(d.dst.offsets, d.dst.off_type, d.at + k, base + (v - s0));
+  }
+  if (decreasing) flag(d.status, ST_FLAG_OVERFLOW);
+  const uint64_t len = s1 - s0;
+  for (uint32_t q = 0; q < d.src.n_members; ++q)
+    for (uint64_t m = tid; m < len; m += nt)
+      gstore(d.dst.mcol[q] + (base + m) * d.dst.msize[q], d.dst.msize[q],
+             gload(d.src.mcol[q] + (s0 + m) * d.src.msize[q], d.src.msize[q]));
+}
+
+__global__ void zero_bytes_kernel(uint8_t* p, uint64_t bytes) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < bytes; i += (uint64_t)gridDim.x * blockDim.x)
+    gp(p)[i] = 0;
+}
+
 __global__ void zero_kernel(uint32_t* p, uint64_t words) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
     gp(p)[i] = 0u;
@@ -1768,6 +2049,48 @@ hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s
   const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 4ull * (uint32_t)cus));
   hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<uint8_t*>(dst),
                      reinterpret_cast<const uint8_t*>(src), bytes);
+  return hipGetLastError();
+}
+
+hipError_t launch_move(const MoveDesc& d, uint64_t grid_objects, hipStream_t s) {
+  if (!grid_objects) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((grid_objects + 255) / 256, 4096);
+  hipLaunchKernelGGL(move_kernel, dim3(grid), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectDesc& d, hipStream_t s) {
+  const uint64_t tiles = (d.n + kSelectTile - 1) / kSelectTile;
+  if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
+  if (tiles) hipLaunchKernelGGL(select_count_kernel, dim3((uint32_t)tiles), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(1024), 0, s, d);
+  if (tiles) hipLaunchKernelGGL(select_map_kernel, dim3((uint32_t)tiles), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_members(const SelectDesc& d, hipStream_t s) {
+  const uint64_t tiles = std::max<uint64_t>(1, (d.n + kSelectTile - 1) / kSelectTile);
+  hipLaunchKernelGGL(select_lens_kernel, dim3((uint32_t)tiles), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(select_lens_scan_kernel, dim3(1), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(select_offsets_kernel, dim3((uint32_t)tiles), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_member_move(const MemberMoveDesc& d, hipStream_t s) {
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((d.n_max + 3) / 4, 4096));
+  hipLaunchKernelGGL(member_move_kernel, dim3(grid), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_append(const AppendDesc& d, hipStream_t s) {
+  hipLaunchKernelGGL(append_kernel, dim3(1024), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(void* p, uint64_t bytes, hipStream_t s) {
+  if (!bytes) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((bytes + 255) / 256, 2048);
+  hipLaunchKernelGGL(zero_bytes_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<uint8_t*>(p), bytes);
   return hipGetLastError();
 }
 

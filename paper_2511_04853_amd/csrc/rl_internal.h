@@ -194,6 +194,88 @@ inline uint64_t lookback_bytes(uint64_t tiles) { return tiles * 8; }
 // Counts and prefixes in look-back words are kept below 2^40 (saturating).
 constexpr uint64_t kLookbackValueLimit = (1ull << 40) - 1;
 
+// One side of the generic object mover: any layout kind, any object index.
+// Address of leaf c of object i: AoS base + i * stride + off[c]; SoA
+// col[c] + i * size; AoSoA base + (i / W) * W * obj_bytes + W * off[c] +
+// (i % W) * size (off[c] = prefix of the leaf sizes).
+struct GenSide {
+  uint8_t* base;
+  uint32_t kind, stride, width, obj_bytes;
+  uint32_t off[kMaxLeaves];
+  uint8_t* col[kMaxLeaves];
+};
+
+// Objects moved one thread per object: destination object dst0 + k takes
+// source object map[k] (or src0 + k) for k < count (host count, or *count_dev
+// when set); zero_only: the destination objects' slots are zeroed instead.
+struct MoveDesc {
+  GenSide src, dst;
+  uint8_t src_size[kMaxLeaves];
+  uint8_t dst_size[kMaxLeaves];
+  uint8_t op[kMaxLeaves];   // LeafOp: copy, narrow, widen
+  uint32_t n_leaves;
+  uint32_t zero_only;
+  uint64_t count;
+  const uint64_t* count_dev;
+  const uint64_t* map;
+  uint64_t src0, dst0;
+};
+
+// Member storage of one jagged group for the member mover: records with
+// (pointer, count) pairs and a pool (form 0), or an offsets column and
+// member columns (form 1).
+struct GenGroup {
+  uint32_t form;
+  uint32_t n_members;
+  uint64_t capacity;        // members the storage holds
+  uint8_t* records;         // form 0
+  uint32_t rec_stride, ptr_off, len_off, mstride, malign;
+  uint8_t* pool;
+  uint8_t* offsets;         // form 1: n + 1 entries
+  uint32_t off_type;
+  uint32_t moff[kMaxMembers];     // form 0: member leaf offsets in a member record
+  uint8_t* mcol[kMaxMembers];     // form 1: member columns
+  uint8_t msize[kMaxMembers];
+};
+
+// Members of gathered objects: destination object k (k < *count_dev) takes
+// the members of source object map[k], placed from member index out_off[k]
+// (exclusive scan of the gathered counts, out_off[*count_dev] = total).
+struct MemberMoveDesc {
+  GenGroup src, dst;
+  const uint64_t* map;
+  const uint64_t* count_dev;
+  const uint64_t* out_off;
+  uint64_t n_max;           // host bound of *count_dev
+  uint32_t* status;
+};
+
+// Scans over a device-side count of entries (compaction).  Tiles of
+// kSelectTile entries.
+constexpr uint32_t kSelectTile = 1024;
+struct SelectDesc {
+  const uint8_t* keep;      // n flags (0 = drop)
+  uint64_t n;
+  uint64_t* tile_tot;       // per tile: count, then exclusive prefix
+  uint64_t* map;            // kept object indices, in order
+  uint64_t* count;          // kept objects (device)
+  uint64_t* count_out;      // optional second copy for the caller (device)
+  // counts of gathered objects, for their member offsets
+  GenGroup src;             // source group (counts read from it)
+  uint64_t* lens;           // per kept object: its member count, then exclusive offsets (n + 1)
+  uint32_t* status;
+};
+
+// Device-side (index, count) copy of jagged member columns for appends:
+// members [src_off[0], src_off[count]) of the source go to member index
+// dst_off[at] on of the destination; the offsets entries at+1 .. at+count
+// become dst_off[at] + (src_off[k] - src_off[0]).
+struct AppendDesc {
+  GenGroup src, dst;        // both form 1
+  uint64_t at, count;
+  uint32_t* status;
+};
+
 // Device-resident tables of a batch: every step of every item, grouped by
 // the kernel that runs it.  Prefix arrays have one entry per item plus one.
 struct BatchTables {
@@ -236,6 +318,13 @@ constexpr uint32_t jagged_stage_members(uint32_t words) { return (8192 / words) 
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
 // Plain copy between disjoint ranges reachable from the device.
 hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s);
+// Generic object and member movers, compaction scans, appends.
+hipError_t launch_move(const MoveDesc& d, uint64_t grid_objects, hipStream_t s);
+hipError_t launch_select(const SelectDesc& d, hipStream_t s);
+hipError_t launch_select_members(const SelectDesc& d, hipStream_t s);
+hipError_t launch_member_move(const MemberMoveDesc& d, hipStream_t s);
+hipError_t launch_append(const AppendDesc& d, hipStream_t s);
+hipError_t launch_zero_bytes(void* p, uint64_t bytes, hipStream_t s);
 // Device address of the status words of the current device.
 hipError_t status_words(uint32_t** out);
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
