@@ -1041,6 +1041,37 @@ def cpu_events(P, W, torch, stream, seconds=8.0):
     return {"events_per_s": round(done / dt, 1), "threads": threads, "cpu_model": cpu_model(), "events": done}
 
 
+def pipeline(P, W, torch, stream):
+    """The case study's two pipelines (stand-in arithmetic, the paper's
+    statistic over the runs): sensors filled on the host, transferred into
+    device SoA with the conversion and calibrated, against the grid size;
+    particles reconstructed on a 5,000 x 5,000 grid and transferred back
+    into the original records + member pool, against the particle count.
+    Reported: each stage's time and the share of transfer + conversion."""
+    import workloads.case_study as C
+    res = {"sensors": {}, "particles": {}}
+    for side in (100, 300, 1000, 3000, 5000):
+        v = C.sensor_grid(side, seed=side)
+        reps = 10 if side <= 1000 else 4
+        runs, host, cols, typed = C.sensor_pipeline(P, torch, side, v, stream, reps=reps)
+        row = {k: paper_stat([r[k] * 1e3 for r in runs])["mean10_fastest_us"] for k in ("fill", "h2d_convert", "energy")}
+        tot = sum(row.values())
+        res["sensors"][f"{side}x{side}"] = {**{k + "_us": v_ for k, v_ in row.items()},
+                                            "transfer_convert_share": round(row["h2d_convert"] / tot, 3)}
+        if side != 5000:
+            del host, cols, typed
+            torch.cuda.empty_cache()
+    for npart in (100, 1_000, 10_000, 100_000):
+        seeds = C.seed_sensors(5000, npart, seed=npart)
+        runs, dbufs, hbufs = C.particle_pipeline(P, torch, 5000, seeds, typed, stream, reps=6)
+        row = {k: paper_stat([r[k] * 1e3 for r in runs])["mean10_fastest_us"] for k in ("reconstruct", "d2h_convert")}
+        res["particles"][str(npart)] = {**{k + "_us": v_ for k, v_ in row.items()},
+                                        "members": runs[-1]["members"],
+                                        "transfer_convert_share": round(row["d2h_convert"] / sum(row.values()), 3)}
+    assert P.sync(stream) == 0, P.rl_last_error()
+    return res
+
+
 LEGS = {
     "single_conversion": single_conversion,
     "copy_peak": copy_peak,
@@ -1054,9 +1085,10 @@ LEGS = {
     "serving": lambda P, W, torch, stream: serving(P, W, torch, stream, n_events=SERVING_EVENTS[0],
                                                    warmup=min(1000, SERVING_EVENTS[0])),
     "cpu_events": cpu_events,
+    "pipeline": pipeline,
 }
 EXTRA_ORDER = ["single_conversion", "copy_peak", "round_trip", "jagged", "batched", "sweep", "h2d", "d2h",
-               "serving", "cpu_events"]
+               "pipeline", "serving", "cpu_events"]
 
 
 if __name__ == "__main__":
