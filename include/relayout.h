@@ -228,6 +228,67 @@ rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t n,
 rl_status rl_offsets(const rl_view* src, const rl_view* dst, uint32_t group,
                      uint64_t n, uint64_t* total_host, void* stream);
 
+/* ------------------------------------------------------------------ collections with a memory context */
+
+typedef struct rl_collection rl_collection;
+
+/* A collection owning its buffers in its layout's memory context (Sec.
+ * VII-A: every collection has a memory context that says how memory is
+ * allocated, deallocated and set): buffers for `capacity` objects and
+ * member_capacity[g] members per group (NULL without groups), allocated in
+ * the layout's space (device: hipMalloc; pinned host: hipHostMalloc;
+ * pageable host: malloc) and zero-filled (device memory by a kernel on
+ * `stream`).  The layout must outlive the collection.
+ * Errors: RL_EINVAL, RL_ENOMEM (nothing is kept). */
+rl_status rl_collection_create(const rl_layout* layout, uint64_t capacity,
+                               const uint64_t* member_capacity, void* stream,
+                               rl_collection** out);
+/* The collection's view; its pointers stay valid until the next
+ * rl_collection_rehome or rl_collection_destroy. */
+rl_status rl_collection_view(const rl_collection* c, rl_view* out);
+/* Move the collection to another memory context and, optionally, another
+ * layout (Sec. VII-A: updating a collection's memory context information
+ * allocates with the new information, copies from the old memory and frees
+ * it): new buffers for the same capacities in `layout` (same schema, any
+ * space and kind), objects 0..n-1 and their members converted into them
+ * (rl_convert between device layouts, rl_transfer across host and device,
+ * through a temporary device copy between host layouts), then the old
+ * buffers freed; the call synchronises `stream`.  On an error the
+ * collection keeps its old memory.  Errors: as rl_convert / rl_transfer,
+ * RL_EINVAL (another schema, n over the capacity), RL_ENOMEM.  Device
+ * errors found by the conversion are returned by rl_sync on `stream`. */
+rl_status rl_collection_rehome(rl_collection* c, const rl_layout* layout, uint64_t n,
+                               void* stream);
+/* Free the collection's buffers (waits for the device first). */
+void rl_collection_destroy(rl_collection* c);
+
+/* ------------------------------------------------------------------ user transfers */
+
+/* A user implementation of a transfer between two layouts (Sec. VII-B:
+ * transfers may be given more optimal implementations, or read
+ * pre-existing structures defined outside the library, through
+ * specialisations with a priority that falls back to more general
+ * implementations).  Called by rl_convert and rl_transfer, after their
+ * argument validation, with the caller's arguments.  Returns RL_OK once it
+ * has enqueued the whole transfer on `stream`; RL_EUNSUPPORTED to decline
+ * (the next matching specialisation is tried, then the library's own
+ * implementation); any other status fails the call with that status. */
+typedef rl_status (*rl_transfer_fn)(const rl_view* src, const rl_view* dst,
+                                    uint64_t n, void* stream, void* user);
+
+/* Register fn for transfers from layout src to layout dst; either may be
+ * NULL (any layout of the other's schema), not both.  Higher priorities
+ * are tried first, equal ones in registration order.  *id (may be NULL)
+ * receives the handle for rl_unregister_transfer.  The layouts must
+ * outlive the registration; registration is thread-safe, and a call in
+ * progress keeps using the list it started with.
+ * Errors: RL_EINVAL (NULL fn, both layouts NULL, different schemas). */
+rl_status rl_register_transfer(const rl_layout* src, const rl_layout* dst,
+                               int32_t priority, rl_transfer_fn fn, void* user,
+                               uint64_t* id);
+/* Errors: RL_EINVAL (unknown id). */
+rl_status rl_unregister_transfer(uint64_t id);
+
 /* ------------------------------------------------------------------ insertion, deletion, compaction */
 
 /* Compaction after a filter (Sec. VII-B: operations on every property's

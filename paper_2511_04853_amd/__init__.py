@@ -100,6 +100,8 @@ class rl_server_stats(ctypes.Structure):
 # Every symbol the header declares, with its ctypes signature.
 _VP = ctypes.c_void_p
 _P = ctypes.POINTER
+# rl_transfer_fn: (const rl_view* src, const rl_view* dst, uint64_t n, void* stream, void* user) -> rl_status
+TRANSFER_FN = ctypes.CFUNCTYPE(ctypes.c_int, _P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _VP)
 SIGNATURES = {
     "rl_schema_create": (ctypes.c_int, [_P(rl_field), ctypes.c_uint32, _P(rl_jagged), ctypes.c_uint32, _P(_VP)]),
     "rl_schema_destroy": (None, [_VP]),
@@ -113,6 +115,12 @@ SIGNATURES = {
     "rl_transfer": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
     "rl_transfer_noalloc": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _P(rl_xfer_opts)]),
     "rl_memcopy": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_uint64, _VP]),
+    "rl_collection_create": (ctypes.c_int, [_VP, ctypes.c_uint64, _P(ctypes.c_uint64), _VP, _P(_VP)]),
+    "rl_collection_view": (ctypes.c_int, [_VP, _P(rl_view)]),
+    "rl_collection_rehome": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, _VP]),
+    "rl_collection_destroy": (None, [_VP]),
+    "rl_register_transfer": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, TRANSFER_FN, _VP, _P(ctypes.c_uint64)]),
+    "rl_unregister_transfer": (ctypes.c_int, [ctypes.c_uint64]),
     "rl_select": (ctypes.c_int, [_P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _VP, _VP]),
     "rl_erase": (ctypes.c_int, [_P(rl_view), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _VP]),
     "rl_insert": (ctypes.c_int, [_P(rl_view), ctypes.c_uint64, ctypes.c_uint64, _P(rl_view), ctypes.c_uint64, _VP]),
@@ -297,6 +305,55 @@ def memcopy(dst, dst_space, src, src_space, nbytes, stream=None):
     overlapping device ranges move with memmove semantics."""
     check(lib().rl_memcopy(_ptr(dst), SPACES[dst_space], _ptr(src), SPACES[src_space], nbytes,
                            stream_ptr(stream)), "rl_memcopy")
+
+
+class Collection:
+    """An rl_collection: buffers owned by the library in the layout's
+    memory context; rehome() moves it to another context / layout."""
+
+    def __init__(self, layout, capacity, member_capacity=(), stream=None):
+        self.layout = layout
+        h = ctypes.c_void_p()
+        mem = (ctypes.c_uint64 * max(1, len(member_capacity)))(*member_capacity)
+        check(lib().rl_collection_create(layout.handle, capacity, mem if len(member_capacity) else None,
+                                         stream_ptr(stream), ctypes.byref(h)), "rl_collection_create")
+        self.h = h
+
+    def view(self):
+        """(rl_view, [buffer addresses], [buffer bytes]) of the collection now."""
+        v = rl_view()
+        check(lib().rl_collection_view(self.h, ctypes.byref(v)), "rl_collection_view")
+        nb = self.layout.max_buffers
+        mem = [v.member_capacity[g] for g in range(self.layout.schema.n_groups)] if v.member_capacity else []
+        sizes = self.layout.buffer_bytes(v.capacity, mem)
+        return v, [v.buffers[b] for b in range(nb)], sizes
+
+    def rehome(self, layout, n, stream=None):
+        check(lib().rl_collection_rehome(self.h, layout.handle, n, stream_ptr(stream)), "rl_collection_rehome")
+        self.layout = layout
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rl_collection_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+
+def register_transfer(src_layout, dst_layout, priority, fn):
+    """rl_register_transfer with a Python callable fn(src_view_ptr,
+    dst_view_ptr, n, stream, user) -> status; returns (id, keepalive) --
+    keep the second value alive while registered."""
+    cb = TRANSFER_FN(fn)
+    i = ctypes.c_uint64()
+    check(lib().rl_register_transfer(src_layout.handle if src_layout is not None else None,
+                                     dst_layout.handle if dst_layout is not None else None,
+                                     priority, cb, None, ctypes.byref(i)), "rl_register_transfer")
+    return i.value, cb
+
+
+def unregister_transfer(i):
+    check(lib().rl_unregister_transfer(i), "rl_unregister_transfer")
 
 
 def select(src: View, dst: View, n: int, keep, n_kept=None, stream=None):

@@ -492,6 +492,9 @@ extern "C" rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t
   if (!src->layout->schema->members.empty() && src->layout->kind == RL_AOS && dst->layout->kind == RL_AOS)
     return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
   if (n == 0) return RL_OK;
+  bool handled = false;
+  st = run_specialisations(src, dst, n, stream, &handled);
+  if (handled) return st;
   Plan plan;
   PlanShape shape = shape_from_env();
   if (stream_capturing((hipStream_t)stream)) shape.fused = 0;

@@ -93,6 +93,9 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
 uint64_t staging_bytes(const rl_view& host_view, uint64_t n);
 bool transfer_is_staged(const rl_view& host_view, const rl_xfer_opts* opts);
 bool is_host(rl_space s);
+// User transfer specialisations matching (src, dst), in priority order;
+// *handled when one took the call.
+rl_status run_specialisations(const rl_view* src, const rl_view* dst, uint64_t n, void* stream, bool* handled);
 // Device-to-device copy with memmove semantics (overlap allowed).
 rl_status device_move(uint8_t* dst, const uint8_t* src, uint64_t bytes, hipStream_t s);
 

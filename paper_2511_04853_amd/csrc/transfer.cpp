@@ -202,6 +202,15 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
 
 extern "C" rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n, void* stream,
                                  const rl_xfer_opts* opts) {
+  if (n && src && dst && src->layout && dst->layout && src->layout->schema == dst->layout->schema) {
+    std::vector<rl::Range> rs, rd;
+    rl_status st = rl::validate_view(src, n, "src", &rs, false);
+    if (st) return st;
+    if ((st = rl::validate_view(dst, n, "dst", &rd, false))) return st;
+    bool handled = false;
+    st = rl::run_specialisations(src, dst, n, stream, &handled);
+    if (handled) return st;
+  }
   return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
 }
 

@@ -21,6 +21,7 @@ HEADER = os.path.join(ROOT, "include", "relayout.h")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"typedef[^;]*;", "", text, flags=re.S)   # types, including function pointer types
     return sorted(set(re.findall(r"\b(rl_[a-z_0-9]+)\s*\(", text)))
 
 
