@@ -89,7 +89,9 @@ class _Objects(ctypes.Structure):
                 ("width", ctypes.c_uint64), ("obj_bytes", ctypes.c_uint64),
                 ("offset", ctypes.POINTER(ctypes.c_uint64)),
                 ("type", ctypes.POINTER(ctypes.c_int32)),
-                ("base", ctypes.POINTER(ctypes.c_void_p))]
+                ("base", ctypes.POINTER(ctypes.c_void_p)),
+                ("index", ctypes.POINTER(ctypes.c_uint64)),
+                ("elements", ctypes.c_uint64)]
 
 
 class _Group(ctypes.Structure):
@@ -252,10 +254,18 @@ class Layout:
     member_offsets: list = None    # aos: per group, offsets in member record
     member_stride: list = None     # aos: per group
     member_align: list = None      # aos: per group
+    leaf_strides: list = None      # strided: bytes between elements, per leaf
+    indexed: bool = False          # strided: objects reach elements through an index table
 
 
 def make_layout(schema: Schema, kind: str, width: int = 0, storage=None,
-                slot_offsets=None, stride=None, member_storage=None) -> Layout:
+                slot_offsets=None, stride=None, member_storage=None,
+                leaf_strides=None, indexed=False) -> Layout:
+    """kind: "aos", "soa", "aosoa" or "strided" (Sec. VII-B: a layout whose
+    arrays map an object index to a value anywhere: leaf c of object i at
+    byte e * leaf_strides[c] of buffer c, e = i, or e = index[i] from an
+    index table, the buffer after the leaves, when indexed).  Strided
+    layouts hold per-object leaves only."""
     storage = list(storage) if storage is not None else schema.leaf_types()
     mstor = (list(member_storage) if member_storage is not None
              else [schema.member_types(g) for g in range(schema.n_groups)])
@@ -272,6 +282,11 @@ def make_layout(schema: Schema, kind: str, width: int = 0, storage=None,
             L.member_align.append(ma)
     elif kind == "aosoa":
         assert width >= 1
+    elif kind == "strided":
+        assert schema.n_groups == 0, "strided layouts hold per-object leaves only"
+        L.leaf_strides = (list(leaf_strides) if leaf_strides is not None
+                          else [TYPE_SIZE[t] for t in storage])
+        L.indexed = bool(indexed)
     return L
 
 
@@ -292,9 +307,17 @@ def buffer_sizes(L: Layout, n: int, members=()):
     members per group, in the buffer order of the layout:
     aos: records, then a pool per group; soa: one column per leaf, then per
     group the offsets column and one column per member leaf; aosoa: the
-    blocks, then per group as soa."""
+    blocks, then per group as soa; strided: one buffer per leaf reaching n
+    elements (the last element's end), then the index table (n entries)
+    when indexed."""
     S = L.schema
     out = []
+    if L.kind == "strided":
+        out += [(n - 1) * st + TYPE_SIZE[t] if n else 0
+                for st, t in zip(L.leaf_strides, L.storage)]
+        if L.indexed:
+            out.append(8 * n)
+        return out
     if L.kind == "aos":
         out.append(n * L.stride)
         for g in range(S.n_groups):
@@ -315,10 +338,23 @@ def zeros_like_layout(L: Layout, n: int, members=()):
     return [np.zeros(s, dtype=np.uint8) for s in buffer_sizes(L, n, members)]
 
 
-def _objects_struct(L: Layout, bufs, keep):
+def _objects_struct(L: Layout, bufs, keep, elements=0):
+    """The C description of a layout's per-object leaves.  ``elements``:
+    for an indexed strided layout, the elements each leaf holds."""
     S = L.schema
     types = [TYPE_CODES.index(t) for t in L.storage]
-    if L.kind == "aos":
+    if L.kind == "strided":
+        nl = len(S.leaves)
+        o = _Objects(3, 0, 0, 0, _u64s(L.leaf_strides), _i32s(types), _ptrs(bufs[:nl]))
+        if L.indexed:
+            idx = bufs[nl].view(np.uint64)
+            keep.append(idx)
+            o.index = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+            if not elements:   # the whole elements every leaf buffer holds
+                elements = min(((len(b) - TYPE_SIZE[t]) // st + 1 if len(b) >= TYPE_SIZE[t] else 0)
+                               for b, st, t in zip(bufs[:nl], L.leaf_strides, L.storage))
+            o.elements = elements
+    elif L.kind == "aos":
         offs = [L.slot_offsets[S.slots.index(("leaf", k))] for k in range(len(S.leaves))]
         base = [bufs[0]]
         o = _Objects(0, L.stride, 0, 0, _u64s(offs), _i32s(types), _ptrs(base))
@@ -410,8 +446,26 @@ def convert(src: Layout, src_bufs, dst: Layout, n: int, src_members=(),
     return ST_OK, dst_bufs, totals
 
 
+def convert_into(src: Layout, src_bufs, dst: Layout, dst_bufs, n: int, src_elements=0,
+                 dst_elements=0):
+    """Per-object leaves of objects 0..n-1 from src_bufs into dst_bufs
+    (numpy uint8 arrays, modified in place; what the conversion does not
+    address is left as it is).  ``*_elements``: the elements each leaf of an
+    indexed strided side holds.  For schemas without jagged groups.
+    Returns the status."""
+    lib = _load()
+    S = src.schema
+    assert S.n_groups == 0
+    src_bufs = [np.ascontiguousarray(b).view(np.uint8).reshape(-1) for b in src_bufs]
+    keep = []
+    so = _objects_struct(src, src_bufs, keep, src_elements)
+    do = _objects_struct(dst, dst_bufs, keep, dst_elements)
+    return lib.or_convert_objects(ctypes.byref(so), ctypes.byref(do),
+                                  ctypes.c_uint32(len(S.leaves)), ctypes.c_uint64(n))
+
+
 def gather_into(src: Layout, src_bufs, dst: Layout, dst_bufs, idx, k0=0, base=(), src_members=(),
-                dst_capacity=()):
+                dst_capacity=(), src_elements=0, dst_elements=0):
     """Gather (the plain definition behind insertion, deletion and
     compaction, Sec. VII-B): destination object k0 + k takes every value of
     source object idx[k]; per jagged group g the members of the gathered
@@ -425,8 +479,8 @@ def gather_into(src: Layout, src_bufs, dst: Layout, dst_bufs, idx, k0=0, base=()
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
     m = len(idx)
     keep = [idx]
-    so = _objects_struct(src, src_bufs, keep)
-    do = _objects_struct(dst, dst_bufs, keep)
+    so = _objects_struct(src, src_bufs, keep, src_elements)
+    do = _objects_struct(dst, dst_bufs, keep, dst_elements)
     ip = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     st = lib.or_gather_objects(ctypes.byref(so), ctypes.byref(do), ctypes.c_uint32(len(S.leaves)), ip,
                                ctypes.c_uint64(m), ctypes.c_uint64(k0))

@@ -26,7 +26,7 @@
 enum { T_U8, T_I8, T_U16, T_I16, T_U32, T_I32, T_U64, T_I64, T_F32, T_F64 };
 enum { ST_OK = 0, ST_ALIGN = 2, ST_CAPACITY = 4, ST_OVERFLOW = 5,
        ST_UNSUPPORTED = 8, ST_BOUNDS = 11 };
-enum { K_AOS = 0, K_SOA = 1, K_AOSOA = 2 };
+enum { K_AOS = 0, K_SOA = 1, K_AOSOA = 2, K_STRIDED = 3 };
 
 static uint64_t type_size(int32_t t) {
   switch (t) {
@@ -40,19 +40,39 @@ static uint64_t type_size(int32_t t) {
 /* ---- per-object leaves ------------------------------------------------ */
 
 typedef struct {
-  int32_t kind;                 /* K_AOS, K_SOA or K_AOSOA */
+  int32_t kind;                 /* K_AOS, K_SOA, K_AOSOA or K_STRIDED */
   uint64_t stride;              /* AoS: bytes per record */
   uint64_t width;               /* AoSoA: objects per block (W) */
   uint64_t obj_bytes;           /* AoSoA: sum of the leaf sizes (B) */
   const uint64_t* offset;       /* AoS: offset of leaf c in a record;
-                                   AoSoA: sum of the sizes of leaves < c */
+                                   AoSoA: sum of the sizes of leaves < c;
+                                   strided: bytes from one element of leaf c
+                                   to the next */
   const int32_t* type;          /* storage type of each leaf */
-  unsigned char* const* base;   /* AoS/AoSoA: base[0]; SoA: base[c] */
+  unsigned char* const* base;   /* AoS/AoSoA: base[0]; SoA, strided: base[c] */
+  const uint64_t* index;        /* strided: NULL (object i is element i) or
+                                   the element of each object */
+  uint64_t elements;            /* strided with an index: elements each leaf
+                                   holds (an index must be below it) */
 } or_objects;
+
+/* Element that object i of a strided layout maps to (Sec. VII-B: a layout's
+   arrays need only map an index to a value, not be contiguous). */
+static uint64_t element_of(const or_objects* L, uint64_t i) {
+  return L->index ? L->index[i] : i;
+}
+
+/* Whether object i has an address: always, except in an indexed strided
+   layout whose index points past its elements. */
+static int object_in_range(const or_objects* L, uint64_t i) {
+  return L->kind != K_STRIDED || !L->index || L->index[i] < L->elements;
+}
 
 /* Address of leaf c of object i. */
 static unsigned char* leaf_addr(const or_objects* L, uint32_t c, uint64_t i) {
   uint64_t size = type_size(L->type[c]);
+  if (L->kind == K_STRIDED)
+    return L->base[c] + element_of(L, i) * L->offset[c];
   if (L->kind == K_AOS)
     return L->base[0] + i * L->stride + L->offset[c];
   if (L->kind == K_SOA)
@@ -128,12 +148,14 @@ int or_rounding_is_nearest(void) { return fegetround() == FE_TONEAREST; }
 int or_convert_objects_range(const or_objects* src, const or_objects* dst,
                              uint32_t n_leaves, uint64_t i0, uint64_t i1) {
   if (!or_rounding_is_nearest()) return ST_UNSUPPORTED;
-  for (uint64_t i = i0; i < i1; ++i)
+  for (uint64_t i = i0; i < i1; ++i) {
+    if (!object_in_range(src, i) || !object_in_range(dst, i)) return ST_BOUNDS;
     for (uint32_t c = 0; c < n_leaves; ++c) {
       int st = move_value(src->type[c], leaf_addr(src, c, i),
                           dst->type[c], leaf_addr(dst, c, i));
       if (st != ST_OK) return st;
     }
+  }
   return ST_OK;
 }
 
@@ -306,12 +328,14 @@ int or_exclusive_scan(const uint32_t* lengths, uint64_t n, unsigned char* offset
 int or_gather_objects(const or_objects* src, const or_objects* dst, uint32_t n_leaves,
                       const uint64_t* idx, uint64_t m, uint64_t k0) {
   if (!or_rounding_is_nearest()) return ST_UNSUPPORTED;
-  for (uint64_t k = 0; k < m; ++k)
+  for (uint64_t k = 0; k < m; ++k) {
+    if (!object_in_range(src, idx[k]) || !object_in_range(dst, k0 + k)) return ST_BOUNDS;
     for (uint32_t c = 0; c < n_leaves; ++c) {
       int st = move_value(src->type[c], leaf_addr(src, c, idx[k]),
                           dst->type[c], leaf_addr(dst, c, k0 + k));
       if (st != ST_OK) return st;
     }
+  }
   return ST_OK;
 }
 
