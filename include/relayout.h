@@ -117,10 +117,22 @@ typedef enum rl_kind {
   RL_SOA = 1,    /* one column per leaf; each jagged group as an offsets
                     column (n + 1 entries, exclusive prefix sum) and one
                     column per member leaf */
-  RL_AOSOA = 2   /* blocks of W objects; inside a block each leaf is a run
+  RL_AOSOA = 2,  /* blocks of W objects; inside a block each leaf is a run
                     of W values, runs in leaf order; the block stride is
                     W * (sum of leaf sizes); the unused slots of a last
                     partial block are zero.  Jagged groups as in RL_SOA. */
+  RL_STRIDED = 3 /* a user's map from object index to address (Sec. VII-B:
+                    a layout's arrays need not be contiguous, only map an
+                    index to a value): leaf c of object i is element e of
+                    buffer c, at byte e * leaf_strides[c], with e = i, or
+                    e = index[i] read from a u64 index table (the buffer
+                    after the leaves) when the layout is indexed.  Several
+                    leaves may share memory (the fields of an existing
+                    record array: buffer c at the field's offset, every
+                    stride the record size); the caller keeps the elements
+                    of different leaves, and the index table, apart.  Bytes
+                    no object addresses are never written.  Per-object
+                    leaves only (no jagged groups). */
 } rl_kind;
 
 typedef enum rl_space {
@@ -144,7 +156,14 @@ typedef enum rl_space {
  *    narrowed (round to nearest even; overflow to infinity; subnormals
  *    kept); RL_F64 for an RL_F32 leaf widens it (exact).  No other change.
  *  - member pools (RL_AOS with jagged groups) use natural alignment of the
- *    group's member leaves. */
+ *    group's member leaves.
+ *  - leaf_strides / indexed: RL_STRIDED only.  leaf_strides: per per-object
+ *    leaf, the bytes from one element to the next, a non-zero multiple of
+ *    the leaf's storage size below 2^31; NULL = the storage size (packed
+ *    columns).  indexed != 0: objects reach their elements through the
+ *    index table; a view of capacity C then has C elements per leaf and C
+ *    index entries, and an index >= C is a device error (RL_EBOUNDS, the
+ *    object is skipped).  Without an index table object i is element i. */
 typedef struct rl_layout_desc {
   rl_kind kind;
   rl_space space;
@@ -152,12 +171,16 @@ typedef struct rl_layout_desc {
   uint64_t record_stride;
   const uint64_t* slot_offsets;
   const rl_type* storage_type;
+  const uint64_t* leaf_strides;
+  uint32_t indexed;
 } rl_layout_desc;
 
 typedef struct rl_layout rl_layout;
 
 /* Errors: RL_EINVAL (bad kind/space, W == 0 for AoSoA, overlapping or
- * out-of-stride slots, an unsupported storage change, a stride over 2^31). */
+ * out-of-stride slots, an unsupported storage change, a stride over 2^31,
+ * a leaf stride that is zero or not a multiple of the leaf's size);
+ * RL_EUNSUPPORTED (RL_STRIDED for a schema with jagged groups). */
 rl_status rl_layout_create(const rl_schema* schema, const rl_layout_desc* desc,
                            rl_layout** out);
 void rl_layout_destroy(rl_layout* layout);
@@ -167,7 +190,10 @@ void rl_layout_destroy(rl_layout* layout);
  *   RL_AOS:   records, then one member pool per group;
  *   RL_SOA:   one column per per-object leaf, then per group the offsets
  *             column and one column per member leaf;
- *   RL_AOSOA: the blocks, then per group as RL_SOA.
+ *   RL_AOSOA: the blocks, then per group as RL_SOA;
+ *   RL_STRIDED: one buffer per leaf, reaching the end of its last element
+ *             ((n_objects - 1) * stride + size bytes), then, when indexed,
+ *             the index table (8 * n_objects bytes).
  * *n_buffers receives the count; bytes (may be NULL) receives each buffer's
  * byte size and must have room for rl_layout_info's max_buffers entries. */
 rl_status rl_layout_buffers(const rl_layout* layout, uint64_t n_objects,
@@ -209,6 +235,9 @@ typedef struct rl_view {
  * Device errors (rl_sync): RL_EOVERFLOW, RL_ECAPACITY, RL_EBOUNDS; dst is
  * then unspecified but no memory outside the views is touched.
  * n == 0: RL_OK, nothing enqueued.
+ * A strided side (RL_STRIDED) is converted by a general kernel, one thread
+ * per object, reading and writing each leaf at its element; the other
+ * side may be of any kind.
  * Records with one jagged group of packed 4-byte member words convert in
  * one kernel whose work-groups pass running member totals to each other
  * through a small per-stream device buffer of the library (8 bytes per
@@ -239,7 +268,8 @@ typedef struct rl_collection rl_collection;
  * the layout's space (device: hipMalloc; pinned host: hipHostMalloc;
  * pageable host: malloc) and zero-filled (device memory by a kernel on
  * `stream`).  The layout must outlive the collection.
- * Errors: RL_EINVAL, RL_ENOMEM (nothing is kept). */
+ * Errors: RL_EINVAL, RL_ENOMEM (nothing is kept), RL_EUNSUPPORTED (an
+ * RL_STRIDED layout: its memory belongs to someone else). */
 rl_status rl_collection_create(const rl_layout* layout, uint64_t capacity,
                                const uint64_t* member_capacity, void* stream,
                                rl_collection** out);
@@ -300,7 +330,8 @@ rl_status rl_unregister_transfer(uint64_t id);
  * memory receiving the kept count (u64).  dst must hold n objects (the
  * count is only known on the device); dst's slots past the kept objects
  * are left zero in AoSoA blocks and record padding.  Any layout kinds on
- * either side; the schemas must be the same object.
+ * either side (an RL_STRIDED object whose index is past its elements is
+ * skipped and reported as RL_EBOUNDS); the schemas must be the same object.
  * Host errors: as rl_convert (RL_EINVAL also for keep == NULL with n > 0).
  * Device errors (rl_sync): RL_EOVERFLOW (member total beyond dst's offset
  * type), RL_ECAPACITY (beyond dst's member capacity: members that do not
@@ -317,7 +348,8 @@ rl_status rl_select(const rl_view* src, const rl_view* dst, uint64_t n,
  * the view then holds n - count objects and the unused slots of its last
  * AoSoA block are zero.  Collections with jagged groups: only the last
  * objects (at + count == n; nothing moves), else RL_EUNSUPPORTED.
- * Errors: RL_EINVAL (range outside n objects), as rl_convert for the view.
+ * Errors: RL_EINVAL (range outside n objects), RL_EUNSUPPORTED (an
+ * RL_STRIDED view), as rl_convert for the view.
  * AoSoA views move through a per-stream scratch buffer of the library
  * (at most 64 MiB, allocated on first use). */
 rl_status rl_erase(const rl_view* view, uint64_t n, uint64_t at, uint64_t count,
@@ -333,7 +365,8 @@ rl_status rl_erase(const rl_view* view, uint64_t n, uint64_t at, uint64_t count,
  * both sides): src's members follow the view's, offsets entries
  * n .. n + count continue from the view's total.
  * Host errors: RL_EINVAL (position or capacity), RL_EUNSUPPORTED (jagged
- * other than an append between offsets layouts), as rl_convert otherwise.
+ * other than an append between offsets layouts; an RL_STRIDED view; src
+ * may be strided), as rl_convert otherwise.
  * Device errors (rl_sync, appends): RL_ECAPACITY (members beyond the view's
  * member capacity: nothing appended to that group), RL_EOVERFLOW (total
  * beyond the offset type, or decreasing src offsets), RL_EBOUNDS (src
@@ -366,7 +399,9 @@ typedef struct rl_xfer_opts {
  * enqueued; `stream` is ordered with it: work enqueued earlier on `stream`
  * happens before the transfer, later work after it.  Host buffers must
  * stay alive until then.  opts may be NULL (RL_XFER_AUTO).
- * Zero-copy needs pinned host memory.  Errors as rl_convert. */
+ * Zero-copy needs pinned host memory.  Errors as rl_convert;
+ * RL_EUNSUPPORTED for an RL_STRIDED side unless a user transfer
+ * (rl_register_transfer) takes the pair. */
 rl_status rl_transfer(const rl_view* src, const rl_view* dst, uint64_t n,
                       void* stream, const rl_xfer_opts* opts);
 
@@ -441,7 +476,10 @@ typedef struct rl_batch_opts {
  * The items of one launch run concurrently: rl_batch_finalize returns
  * RL_EOVERLAP if a destination of one item overlaps a buffer (source or
  * destination) of another; sources may be shared.  Device-detected errors
- * go to the status word of the stream the batch is launched on. */
+ * go to the status word of the stream the batch is launched on.
+ * rl_batch_add returns RL_EUNSUPPORTED for an RL_STRIDED side (batches
+ * walk their items with the tiled kernels; convert such items with
+ * rl_convert). */
 rl_status rl_batch_create(const rl_batch_opts* opts, rl_batch** out);
 rl_status rl_batch_add(rl_batch* batch, const rl_view* src, const rl_view* dst,
                        uint64_t n);

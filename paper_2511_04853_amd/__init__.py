@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "RL_OK", 1: "RL_EINVAL", 2: "RL_EALIGN", 3: "RL_EOVERLAP", 4:
                 5: "RL_EOVERFLOW", 6: "RL_ENOMEM", 7: "RL_EBUDGET", 8: "RL_EUNSUPPORTED",
                 9: "RL_EHIP", 10: "RL_EBUSY", 11: "RL_EBOUNDS", 12: "RL_ELIMIT"}
 TYPES = ["u8", "i8", "u16", "i16", "u32", "i32", "u64", "i64", "f32", "f64"]
-KINDS = {"aos": 0, "soa": 1, "aosoa": 2}
+KINDS = {"aos": 0, "soa": 1, "aosoa": 2, "strided": 3}
 SPACES = {"device": 0, "host": 1, "pinned": 2}
 XFER_MODES = {"auto": 0, "staged": 1, "zero_copy": 2}
 
@@ -52,7 +52,9 @@ class rl_layout_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("space", ctypes.c_int), ("block_width", ctypes.c_uint32),
                 ("record_stride", ctypes.c_uint64),
                 ("slot_offsets", ctypes.POINTER(ctypes.c_uint64)),
-                ("storage_type", ctypes.POINTER(ctypes.c_int))]
+                ("storage_type", ctypes.POINTER(ctypes.c_int)),
+                ("leaf_strides", ctypes.POINTER(ctypes.c_uint64)),
+                ("indexed", ctypes.c_uint32)]
 
 
 class rl_view(ctypes.Structure):
@@ -213,7 +215,8 @@ class Layout:
     """An rl_layout of a Schema."""
 
     def __init__(self, schema: Schema, kind: str, space: str = "device", width: int = 0,
-                 storage=None, slot_offsets=None, stride: int = 0):
+                 storage=None, slot_offsets=None, stride: int = 0, leaf_strides=None,
+                 indexed: bool = False):
         self.schema, self.kind, self.space, self.width = schema, kind, space, width
         self.storage = list(storage) if storage is not None else None
         d = rl_layout_desc()
@@ -230,6 +233,11 @@ class Layout:
             arr = (ctypes.c_int * len(storage))(*[TYPES.index(t) for t in storage])
             self._keep.append(arr)
             d.storage_type = arr
+        if leaf_strides is not None:
+            arr = (ctypes.c_uint64 * len(leaf_strides))(*leaf_strides)
+            self._keep.append(arr)
+            d.leaf_strides = arr
+        d.indexed = 1 if indexed else 0
         h = ctypes.c_void_p()
         check(lib().rl_layout_create(schema.handle, ctypes.byref(d), ctypes.byref(h)), "rl_layout_create")
         self.handle = h

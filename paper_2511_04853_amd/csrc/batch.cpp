@@ -564,6 +564,8 @@ extern "C" rl_status rl_batch_add(rl_batch* b, const rl_view* src, const rl_view
   if (st) return st;
   if ((st = validate_view(dst, n, "dst", &rd, true))) return st;
   if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
+  if (src->layout->kind == RL_STRIDED || dst->layout->kind == RL_STRIDED)
+    return fail(RL_EUNSUPPORTED, "batches do not take strided layouts (use rl_convert)");
   if ((st = check_overlap(rs, rd))) return st;
   if (src->layout->kind == RL_AOSOA && src->layout->width == 0)
     return fail(RL_EINVAL, "a source block width cannot be auto");

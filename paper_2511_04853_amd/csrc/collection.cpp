@@ -84,6 +84,7 @@ extern "C" rl_status rl_collection_create(const rl_layout* layout, uint64_t capa
   *out = nullptr;
   if (layout->kind == RL_AOSOA && layout->width == 0)
     return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
+  if (layout->kind == RL_STRIDED) return fail(RL_EUNSUPPORTED, "a strided layout's memory belongs to its user");
   const size_t ng = layout->schema->members.size();
   if (ng && !member_capacity) return fail(RL_EINVAL, "member capacities needed");
   auto c = new rl_collection();
@@ -110,6 +111,7 @@ extern "C" rl_status rl_collection_rehome(rl_collection* c, const rl_layout* lay
   if (!c || !layout) return fail(RL_EINVAL, "rl_collection_rehome: NULL argument");
   if (layout->schema != c->layout->schema) return fail(RL_EINVAL, "a layout of another schema");
   if (layout->kind == RL_AOSOA && layout->width == 0) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
+  if (layout->kind == RL_STRIDED) return fail(RL_EUNSUPPORTED, "a strided layout's memory belongs to its user");
   if (n > c->capacity) return fail(RL_EINVAL, "n %llu over the capacity %llu", (unsigned long long)n,
                                    (unsigned long long)c->capacity);
   if (!c->layout->schema->members.empty() && c->layout->kind == RL_AOS && layout->kind == RL_AOS)

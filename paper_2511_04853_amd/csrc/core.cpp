@@ -232,7 +232,7 @@ extern "C" rl_status rl_layout_create(const rl_schema* schema, const rl_layout_d
                                       rl_layout** out) {
   if (!schema || !desc || !out) return fail(RL_EINVAL, "rl_layout_create: NULL argument");
   *out = nullptr;
-  if (desc->kind < RL_AOS || desc->kind > RL_AOSOA) return fail(RL_EINVAL, "bad layout kind %d", (int)desc->kind);
+  if (desc->kind < RL_AOS || desc->kind > RL_STRIDED) return fail(RL_EINVAL, "bad layout kind %d", (int)desc->kind);
   if (desc->space < RL_SPACE_DEVICE || desc->space > RL_SPACE_HOST_PINNED)
     return fail(RL_EINVAL, "bad memory space %d", (int)desc->space);
   auto* L = new rl_layout();
@@ -243,6 +243,7 @@ extern "C" rl_status rl_layout_create(const rl_schema* schema, const rl_layout_d
   L->stride = 0;
   L->record_align = 1;
   L->has_gaps = false;
+  L->indexed = false;
   const size_t nl = schema->leaves.size();
   for (size_t c = 0; c < nl; ++c) {
     const rl_type st = desc->storage_type ? desc->storage_type[c] : schema->leaves[c].type;
@@ -260,6 +261,23 @@ extern "C" rl_status rl_layout_create(const rl_schema* schema, const rl_layout_d
   }
   L->obj_bytes = acc;
   if (acc > (uint32_t)kMaxObjBytes) { delete L; return fail(RL_EINVAL, "more than %d bytes per object", kMaxObjBytes); }
+  if (L->kind == RL_STRIDED) {
+    if (!schema->members.empty()) {
+      delete L;
+      return fail(RL_EUNSUPPORTED, "strided layouts hold per-object leaves only (the schema has jagged groups)");
+    }
+    for (size_t c = 0; c < nl; ++c) {
+      const uint64_t sz = type_size(L->storage[c]);
+      const uint64_t st = desc->leaf_strides ? desc->leaf_strides[c] : sz;
+      if (st == 0 || st % sz || st >= (1ull << 31)) {
+        delete L;
+        return fail(RL_EINVAL, "leaf %zu: stride %llu is not a non-zero multiple of %llu below 2^31", c,
+                    (unsigned long long)st, (unsigned long long)sz);
+      }
+      L->leaf_stride.push_back(st);
+    }
+    L->indexed = desc->indexed != 0;
+  }
   if (L->kind == RL_AOSOA) {
     // width 0: chosen by a batch ("auto"); buffers are sized for the widest candidate
     if (L->width >= 65536) { delete L; return fail(RL_EINVAL, "AoSoA block width must be 0..65535"); }
@@ -331,6 +349,7 @@ uint32_t layout_n_buffers(const rl_layout* L) {
   const rl_schema* s = L->schema;
   uint32_t n = 0;
   if (L->kind == RL_AOS) return 1 + (uint32_t)s->members.size();
+  if (L->kind == RL_STRIDED) return (uint32_t)s->leaves.size() + (L->indexed ? 1 : 0);
   n = L->kind == RL_SOA ? (uint32_t)s->leaves.size() : 1;
   for (const auto& m : s->members) n += 1 + (uint32_t)m.size();
   return n;
@@ -342,6 +361,12 @@ void layout_buffer_bytes(const rl_layout* L, uint64_t n, const uint64_t* members
   if (L->kind == RL_AOS) {
     bytes[k++] = n * L->stride;
     for (size_t g = 0; g < s->members.size(); ++g) bytes[k++] = (members ? members[g] : 0) * L->mstride[g];
+    return;
+  }
+  if (L->kind == RL_STRIDED) {
+    for (size_t c = 0; c < s->leaves.size(); ++c)
+      bytes[k++] = n ? (n - 1) * L->leaf_stride[c] + type_size(L->storage[c]) : 0;
+    if (L->indexed) bytes[k++] = n * 8;
     return;
   }
   if (L->kind == RL_SOA) {
@@ -363,6 +388,11 @@ void layout_buffer_align(const rl_layout* L, uint64_t* align) {
   if (L->kind == RL_AOS) {
     align[k++] = L->record_align;
     for (size_t g = 0; g < s->members.size(); ++g) align[k++] = L->malign[g];
+    return;
+  }
+  if (L->kind == RL_STRIDED) {
+    for (size_t c = 0; c < s->leaves.size(); ++c) align[k++] = type_size(L->storage[c]);
+    if (L->indexed) align[k++] = 8;
     return;
   }
   if (L->kind == RL_SOA) {
@@ -426,7 +456,10 @@ rl_status validate_view(const rl_view* v, uint64_t n, const char* which, std::ve
   const uint32_t nb = layout_n_buffers(L);
   if (nb && !v->buffers) return fail(RL_EINVAL, "%s: buffers is NULL", which);
   std::vector<uint64_t> bytes(nb), align(nb);
-  layout_buffer_bytes(L, n, v->member_capacity, bytes.data());
+  // an indexed strided view's objects may reach any of its `capacity`
+  // elements
+  const uint64_t reach = L->kind == RL_STRIDED && L->indexed ? v->capacity : n;
+  layout_buffer_bytes(L, reach, v->member_capacity, bytes.data());
   layout_buffer_align(L, align.data());
   for (uint32_t b = 0; b < nb; ++b) {
     const uintptr_t p = (uintptr_t)v->buffers[b];
@@ -439,10 +472,11 @@ rl_status validate_view(const rl_view* v, uint64_t n, const char* which, std::ve
   return RL_OK;
 }
 
-rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>& dst) {
+rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>& dst, bool dst_shared) {
   for (size_t i = 0; i < dst.size(); ++i) {
     for (const auto& s : src)
       if (dst[i].lo < s.hi && s.lo < dst[i].hi) return fail(RL_EOVERLAP, "a destination buffer overlaps a source buffer");
+    if (dst_shared) continue;
     for (size_t j = 0; j < i; ++j)
       if (dst[i].lo < dst[j].hi && dst[j].lo < dst[i].hi) return fail(RL_EOVERLAP, "destination buffers overlap");
   }
@@ -488,13 +522,15 @@ extern "C" rl_status rl_convert(const rl_view* src, const rl_view* dst, uint64_t
   if (st) return st;
   if (auto_width(src) || auto_width(dst)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
   if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
-  if ((st = check_overlap(rs, rd))) return st;
+  if ((st = check_overlap(rs, rd, dst->layout->kind == RL_STRIDED))) return st;
   if (!src->layout->schema->members.empty() && src->layout->kind == RL_AOS && dst->layout->kind == RL_AOS)
     return fail(RL_EUNSUPPORTED, "AoS -> AoS conversion of a schema with jagged groups");
   if (n == 0) return RL_OK;
   bool handled = false;
   st = run_specialisations(src, dst, n, stream, &handled);
   if (handled) return st;
+  if (src->layout->kind == RL_STRIDED || dst->layout->kind == RL_STRIDED)
+    return convert_general(*src, *dst, n, (hipStream_t)stream);
   Plan plan;
   PlanShape shape = shape_from_env();
   if (stream_capturing((hipStream_t)stream)) shape.fused = 0;

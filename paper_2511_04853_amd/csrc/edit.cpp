@@ -54,12 +54,22 @@ rl_status edit_scratch(hipStream_t s, uint64_t need, uint8_t** out) {
   return RL_OK;
 }
 
-GenSide gen_side(const rl_layout* L, void* const* bufs) {
+// `capacity`: the view's capacity (the elements of an indexed strided side).
+GenSide gen_side(const rl_layout* L, void* const* bufs, uint64_t capacity = 0) {
   GenSide s;
   memset(&s, 0, sizeof s);
   s.kind = (uint32_t)L->kind;
   const size_t nl = L->storage.size();
-  if (L->kind == RL_AOS) {
+  if (L->kind == RL_STRIDED) {
+    for (size_t c = 0; c < nl; ++c) {
+      s.col[c] = (uint8_t*)bufs[c];
+      s.off[c] = (uint32_t)L->leaf_stride[c];
+    }
+    if (L->indexed) {
+      s.index = (const uint64_t*)bufs[nl];
+      s.elements = capacity;
+    }
+  } else if (L->kind == RL_AOS) {
     s.base = (uint8_t*)bufs[0];
     s.stride = (uint32_t)L->stride;
     for (size_t c = 0; c < nl; ++c) s.off[c] = L->leaf_offset[c];
@@ -213,7 +223,7 @@ extern "C" rl_status rl_select(const rl_view* src, const rl_view* dst, uint64_t 
   if ((st = validate_view(dst, n, "dst", &rd, true))) return st;
   if (src->layout->schema != dst->layout->schema) return fail(RL_EINVAL, "src and dst use different schemas");
   if (auto_width(src) || auto_width(dst)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
-  if ((st = check_overlap(rs, rd))) return st;
+  if ((st = check_overlap(rs, rd, dst->layout->kind == RL_STRIDED))) return st;
   if (n && !keep) return fail(RL_EINVAL, "rl_select: keep is NULL");
   hipStream_t s = (hipStream_t)stream;
   const rl_layout* SL = src->layout;
@@ -247,9 +257,12 @@ extern "C" rl_status rl_select(const rl_view* src, const rl_view* dst, uint64_t 
     if ((st = launch_or_fail(launch_zero_bytes(dst->buffers[0], n * DL->stride, s), "zero"))) return st;
   }
   MoveDesc m;
-  if ((st = move_desc(SL, gen_side(SL, src->buffers), DL, gen_side(DL, dst->buffers), &m))) return st;
+  if ((st = move_desc(SL, gen_side(SL, src->buffers, src->capacity), DL, gen_side(DL, dst->buffers, dst->capacity),
+                      &m)))
+    return st;
   m.count_dev = sd.count;
   m.map = sd.map;
+  m.status = status;
   if ((st = launch_or_fail(launch_move(m, n, s), "move"))) return st;
   for (uint32_t g = 0; g < ng; ++g) {
     sd.src = gen_group(SL, src->buffers, g, src->member_capacity[g]);
@@ -268,11 +281,35 @@ extern "C" rl_status rl_select(const rl_view* src, const rl_view* dst, uint64_t 
   return RL_OK;
 }
 
+namespace rl {
+
+rl_status convert_general(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t s) {
+  const rl_layout* SL = src.layout;
+  const rl_layout* DL = dst.layout;
+  uint32_t* status = stream_status(s);
+  if (!status) return fail(RL_EHIP, "status words of the current device");
+  rl_status st;
+  // the padding bytes of destination records are zero, as in every conversion
+  if (DL->kind == RL_AOS && DL->has_gaps &&
+      (st = launch_or_fail(launch_zero_bytes(dst.buffers[0], n * DL->stride, s), "zero")))
+    return st;
+  MoveDesc m;
+  if ((st = move_desc(SL, gen_side(SL, src.buffers, src.capacity), DL, gen_side(DL, dst.buffers, dst.capacity), &m)))
+    return st;
+  m.count = n;
+  m.status = status;
+  if ((st = launch_or_fail(launch_move(m, n, s), "move"))) return st;
+  return zero_block_tail(DL, dst.buffers, n, s);
+}
+
+}  // namespace rl
+
 extern "C" rl_status rl_erase(const rl_view* view, uint64_t n, uint64_t at, uint64_t count, void* stream) {
   std::vector<Range> rv;
   rl_status st = validate_view(view, n, "view", &rv, true);
   if (st) return st;
   if (auto_width(view)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
+  if (view->layout->kind == RL_STRIDED) return fail(RL_EUNSUPPORTED, "erase on a strided view");
   if (at > n || count > n - at) return fail(RL_EINVAL, "erase [%llu, %llu) outside %llu objects",
                                             (unsigned long long)at, (unsigned long long)(at + count),
                                             (unsigned long long)n);
@@ -293,6 +330,7 @@ extern "C" rl_status rl_insert(const rl_view* view, uint64_t n, uint64_t at, con
   if ((st = validate_view(src, count, "src", &rs, true))) return st;
   if (view->layout->schema != src->layout->schema) return fail(RL_EINVAL, "view and src use different schemas");
   if (auto_width(view) || auto_width(src)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
+  if (view->layout->kind == RL_STRIDED) return fail(RL_EUNSUPPORTED, "insert into a strided view");
   if (at > n) return fail(RL_EINVAL, "insert position %llu beyond %llu objects", (unsigned long long)at,
                           (unsigned long long)n);
   if (n + count > view->capacity)
@@ -314,14 +352,15 @@ extern "C" rl_status rl_insert(const rl_view* view, uint64_t n, uint64_t at, con
     uint8_t* rec = (uint8_t*)view->buffers[0];
     if ((st = launch_or_fail(launch_zero_bytes(rec + at * L->stride, count * L->stride, s), "zero"))) return st;
   }
-  MoveDesc m;
-  if ((st = move_desc(SL, gen_side(SL, src->buffers), L, gen_side(L, view->buffers), &m))) return st;
-  m.count = count;
-  m.dst0 = at;
-  if ((st = launch_or_fail(launch_move(m, count, s), "move"))) return st;
-  if ((st = zero_block_tail(L, view->buffers, n + count, s))) return st;
   uint32_t* status = stream_status(s);
   if (!status) return fail(RL_EHIP, "status words of the current device");
+  MoveDesc m;
+  if ((st = move_desc(SL, gen_side(SL, src->buffers, src->capacity), L, gen_side(L, view->buffers), &m))) return st;
+  m.count = count;
+  m.dst0 = at;
+  m.status = status;
+  if ((st = launch_or_fail(launch_move(m, count, s), "move"))) return st;
+  if ((st = zero_block_tail(L, view->buffers, n + count, s))) return st;
   for (uint32_t g = 0; g < ng; ++g) {
     AppendDesc ad;
     memset(&ad, 0, sizeof ad);

@@ -1511,10 +1511,27 @@ __global__ void __launch_bounds__(256) copy_kernel(uint8_t* dst, const uint8_t* 
 // every value of a chosen source object.  The mover below handles any pair
 // of layout kinds at any object index, one thread per object (simple and
 // general: these are not the bandwidth-critical path); members of jagged
-// groups move with a wave per object.
+// groups move with a wave per object.  The same mover converts layouts
+// whose arrays are a user's index-to-address map (strided leaves, reached
+// directly or through an index table; Sec. VII-B).
 
+// Where object i sits in a side: its element for a strided side with an
+// index table (false if past the elements), else i itself.
+template <class GS>
+__device__ __forceinline__ bool gen_element(const GS& s, uint64_t i, uint64_t* e) {
+  if (s.kind != KIND_STRIDED || !s.index) {
+    *e = i;
+    return true;
+  }
+  *e = gp(s.index)[i];
+  return *e < s.elements;
+}
+
+// Address of leaf c at position i (the object index, or a strided side's
+// element from gen_element).
 template <class GS>
 __device__ __forceinline__ uint8_t* gen_addr(const GS& s, uint32_t c, uint32_t size, uint64_t i) {
+  if (s.kind == KIND_STRIDED) return s.col[c] + i * s.off[c];
   if (s.kind == KIND_AOS) return s.base + i * s.stride + s.off[c];
   if (s.kind == KIND_SOA) return s.col[c] + i * size;
   const uint64_t blk = i / s.width;
@@ -1559,8 +1576,13 @@ __global__ void __launch_bounds__(256) move_kernel(const MoveDesc) {
   const uint64_t count = d.count_dev ? *gp(d.count_dev) : d.count;
   const uint64_t nt = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count; k += nt) {
-    const uint64_t i = d.map ? gp(d.map)[k] : d.src0 + k;
-    const uint64_t o = d.dst0 + k;
+    uint64_t i = 0, o;
+    const bool in_src = d.zero_only || gen_element(d.src, d.map ? gp(d.map)[k] : d.src0 + k, &i);
+    const bool in_dst = gen_element(d.dst, d.dst0 + k, &o);
+    if (!in_src || !in_dst) {
+      flag(d.status, ST_FLAG_BOUNDS);
+      continue;
+    }
     for (uint32_t c = 0; c < d.n_leaves; ++c) {
       uint8_t* dp = gen_addr(d.dst, c, d.dst_size[c], o);
       if (d.zero_only) {

@@ -374,6 +374,8 @@ rl_status make_plan(const rl_view& src, const rl_view& dst, uint64_t n, const Pl
                     Plan* plan) {
   const rl_layout* SL = src.layout;
   const rl_layout* DL = dst.layout;
+  if (SL->kind == RL_STRIDED || DL->kind == RL_STRIDED)
+    return fail(RL_EUNSUPPORTED, "strided layouts take the general mover, not a tiled plan");
   const rl_schema* sc = SL->schema;
   const uint32_t ng = (uint32_t)sc->members.size();
   uint32_t* const status = nullptr;   // stamped with the stream's word at enqueue

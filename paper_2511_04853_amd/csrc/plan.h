@@ -56,7 +56,13 @@ struct Range {
 };
 rl_status validate_view(const rl_view* v, uint64_t n, const char* which, std::vector<Range>* ranges,
                         bool want_device);
-rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>& dst);
+// dst_shared: the destination's buffers may overlap each other (the leaves
+// of a strided layout sharing a record array); they are still checked
+// against the source.
+rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>& dst, bool dst_shared = false);
+// Conversion through the general one-thread-per-object mover (any kinds on
+// either side; used for strided layouts).
+rl_status convert_general(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t s);
 
 uint32_t type_size(rl_type t);
 uint32_t layout_n_buffers(const rl_layout* L);

@@ -23,7 +23,7 @@ constexpr uint32_t kDenseMaxThreads = 256;  // launch bound of the dense kernels
 constexpr uint32_t kStatusSlots = 4096;     // device status words (one per stream)
 
 // Kinds of one side of a dense conversion (match rl_kind).
-enum SideKind : uint32_t { KIND_AOS = 0, KIND_SOA = 1, KIND_AOSOA = 2 };
+enum SideKind : uint32_t { KIND_AOS = 0, KIND_SOA = 1, KIND_AOSOA = 2, KIND_STRIDED = 3 };
 
 // Value operations of one leaf.
 enum LeafOp : uint8_t {
@@ -201,8 +201,10 @@ constexpr uint64_t kLookbackValueLimit = (1ull << 40) - 1;
 struct GenSide {
   uint8_t* base;
   uint32_t kind, stride, width, obj_bytes;
-  uint32_t off[kMaxLeaves];
-  uint8_t* col[kMaxLeaves];
+  uint32_t off[kMaxLeaves];      // AoS/AoSoA: leaf offsets; strided: leaf strides
+  uint8_t* col[kMaxLeaves];      // SoA, strided: one buffer per leaf
+  const uint64_t* index;         // strided: element of each object, or NULL
+  uint64_t elements;             // strided with an index: elements per leaf
 };
 
 // Objects moved one thread per object: destination object dst0 + k takes
@@ -219,6 +221,7 @@ struct MoveDesc {
   const uint64_t* count_dev;
   const uint64_t* map;
   uint64_t src0, dst0;
+  uint32_t* status;              // bounds flag for indexes past the elements
 };
 
 // Member storage of one jagged group for the member mover: records with
@@ -397,4 +400,6 @@ struct rl_layout {
   std::vector<uint32_t> mstride, malign;    // AoS: per group member record
   std::vector<std::vector<uint32_t>> moff;  // AoS: per group member offsets
   bool has_gaps;                            // AoS: bytes not covered by a written slot
+  std::vector<uint64_t> leaf_stride;        // strided: bytes between elements, per leaf
+  bool indexed;                             // strided: elements reached through an index table
 };

@@ -146,6 +146,8 @@ rl_status transfer_impl(const rl_view* src, const rl_view* dst, uint64_t n, hipS
   const rl_layout* DL = dst->layout;
   if (SL->schema != DL->schema) return fail(RL_EINVAL, "src and dst use different schemas");
   if (auto_width(src) || auto_width(dst)) return fail(RL_EINVAL, "block width 0 (auto) is only for batches");
+  if (SL->kind == RL_STRIDED || DL->kind == RL_STRIDED)
+    return fail(RL_EUNSUPPORTED, "transfers of strided layouts (convert on the device, or register a user transfer)");
   const bool sh = is_host(SL->space), dh = is_host(DL->space);
   if (sh == dh) return fail(RL_EUNSUPPORTED, "rl_transfer needs one host and one device view (use rl_convert on device)");
   if (n == 0) return RL_OK;
@@ -256,7 +258,9 @@ extern "C" rl_status rl_transfer_noalloc(const rl_view* src, const rl_view* dst,
   // before anything is enqueued
   const bool one_host = src && dst && src->layout && dst->layout &&
                         rl::is_host(src->layout->space) != rl::is_host(dst->layout->space);
-  if (!one_host || n == 0) return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
+  const bool strided = src && dst && src->layout && dst->layout &&
+                       (src->layout->kind == RL_STRIDED || dst->layout->kind == RL_STRIDED);
+  if (!one_host || n == 0 || strided) return rl::transfer_impl(src, dst, n, (hipStream_t)stream, opts, nullptr, 0);
   const rl_view& hv = rl::is_host(src->layout->space) ? *src : *dst;
   uint8_t* base = nullptr;
   if (!rl::transfer_is_staged(hv, opts)) {
