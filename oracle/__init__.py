@@ -131,8 +131,13 @@ class Schema:
     group's first field is declared.
     """
 
-    def __init__(self, decl: SchemaDecl):
+    def __init__(self, decl):
         self.decl = decl
+        self.tree = None
+        if hasattr(decl, "props"):
+            self._from_tree(decl)
+            return
+        self.offset_types = list(decl.offset_types)
         self.leaves, self.slots = [], []
         self.members = [[] for _ in decl.offset_types]
         seen_groups = set()
@@ -150,6 +155,48 @@ class Schema:
                     self.members[f.group].append((f, e))
         self.n_groups = len(decl.offset_types)
 
+    def _from_tree(self, decl):
+        """A property tree (Sec. VI: array properties holding a list of
+        properties, sub-groups and jagged vectors nested in them): walked in
+        pre-order, each array element in turn.  An item outside a jagged
+        vector is a per-object leaf and a record slot; each jagged vector
+        reached (one per element of an array holding it) is the next group,
+        its (ptr, len) slots where it is reached, its items the group's
+        member leaves.  Leaves are named by path (names joined by '.', an
+        element as '[e]')."""
+        self.tree = decl.props
+        self.leaves, self.slots, self.members, self.offset_types = [], [], [], []
+
+        def visit(p, path, group):
+            name = f"{path}.{p.name}" if path else p.name
+            kind = type(p).__name__
+            if kind == "Item":
+                ref = _PathLeaf(name, p.type)
+                if group is None:
+                    self.slots.append(("leaf", len(self.leaves)))
+                    self.leaves.append((ref, 0))
+                else:
+                    self.members[group].append((ref, 0))
+            elif kind == "Array":
+                for e in range(p.extent):
+                    for c in p.props:
+                        visit(c, f"{name}[{e}]", group)
+            elif kind == "SubGroup":
+                for c in p.props:
+                    visit(c, name, group)
+            else:
+                assert group is None, "a jagged vector inside another"
+                g = len(self.members)
+                self.members.append([])
+                self.offset_types.append(p.offset_type)
+                self.slots += [("ptr", g), ("len", g)]
+                for c in p.props:
+                    visit(c, name, g)
+
+        for p in decl.props:
+            visit(p, "", None)
+        self.n_groups = len(self.members)
+
     def leaf_types(self):
         return [f.type for f, _ in self.leaves]
 
@@ -163,8 +210,68 @@ class Schema:
         return "u64" if k == "ptr" else "u32"
 
 
+@dataclass(frozen=True)
+class _PathLeaf:
+    """A leaf of a property tree: its path, its type, one value per object."""
+    name: str
+    type: str
+    extent: int = 1
+
+
 def _round_up(x, a):
     return (x + a - 1) // a * a
+
+
+def _tree_struct(props, sizes):
+    """C layout of a struct whose members are `props` (Sec. VI property
+    kinds): an item is a scalar member; a sub-group a nested struct; an
+    array `extent` nested structs, one per element, each made of the
+    element's properties; a jagged vector two members, u64 ptr and u32 len.
+    `sizes` yields the byte size of each item (and 8, 4 for each ptr, len)
+    in walk order.  Returns (offsets in walk order, size, alignment):
+    members aligned to their own alignment, the size rounded up to the
+    largest."""
+    offs, pos, align = [], 0, 1
+
+    def place(o_rel, size, al):
+        nonlocal pos, align
+        pos = _round_up(pos, al)
+        offs.extend(pos + o for o in o_rel)
+        pos += size
+        align = max(align, al)
+
+    for p in props:
+        kind = type(p).__name__
+        if kind == "Item":
+            sz = next(sizes)
+            place([0], sz, sz)
+        elif kind == "Jagged":
+            place([0], next(sizes), 8)
+            place([0], next(sizes), 4)
+        elif kind == "SubGroup":
+            place(*_tree_struct(p.props, sizes))
+        else:
+            for _ in range(p.extent):
+                place(*_tree_struct(p.props, sizes))
+    return offs, (_round_up(pos, align) if pos else 0), align
+
+
+def _group_props(schema, g):
+    """The property of jagged group g (the g-th reached by the walk)."""
+    found = []
+
+    def visit(p):
+        kind = type(p).__name__
+        if kind == "Jagged":
+            found.append(p)
+        elif kind != "Item":
+            for _ in range(getattr(p, "extent", 1)):
+                for c in p.props:
+                    visit(c)
+
+    for p in schema.tree:
+        visit(p)
+    return found[g]
 
 
 def natural_record(schema: Schema, leaf_types=None):
@@ -181,6 +288,10 @@ def natural_record(schema: Schema, leaf_types=None):
         if k == "leaf":
             return TYPE_SIZE[types[idx]]
         return 8 if k == "ptr" else 4
+
+    if schema.tree is not None:
+        offs, stride, _ = _tree_struct(schema.tree, iter([slot_size(sl) for sl in schema.slots]))
+        return offs, stride
 
     # the sub-group id of each record slot (ptr/len pairs are top level)
     sub_of_slot = []
@@ -230,6 +341,8 @@ def natural_record(schema: Schema, leaf_types=None):
 
 def natural_member_record(schema: Schema, g: int, member_types=None):
     types = member_types or schema.member_types(g)
+    if schema.tree is not None:
+        return _tree_struct(_group_props(schema, g).props, iter([TYPE_SIZE[t] for t in types]))
     pos, ma, offs = 0, 1, []
     for t in types:
         s = TYPE_SIZE[t]
@@ -329,7 +442,7 @@ def buffer_sizes(L: Layout, n: int, members=()):
         nblk = -(-n // L.width)
         out.append(nblk * L.width * obj_bytes(L))
     for g in range(S.n_groups):
-        out.append((n + 1) * TYPE_SIZE[S.decl.offset_types[g]])
+        out.append((n + 1) * TYPE_SIZE[S.offset_types[g]])
         out += [members[g] * TYPE_SIZE[t] for t in L.member_storage[g]]
     return out
 
@@ -402,7 +515,7 @@ def _group_struct(L: Layout, g: int, bufs, capacity: int, keep):
     else:
         gs.form = 1
         gs.offsets = bufs[i0].ctypes.data
-        gs.off_type = TYPE_CODES.index(S.decl.offset_types[g])
+        gs.off_type = TYPE_CODES.index(S.offset_types[g])
         gs.mcol = _ptrs(bufs[i0 + 1: i0 + 1 + len(types)])
         keep.append(gs.mcol)
     keep.append(gs)
@@ -507,7 +620,7 @@ def _lengths(L: Layout, bufs, g, n):
         off = L.slot_offsets[S.slots.index(("len", g))]
         rec = np.ascontiguousarray(bufs[0]).view(np.uint8)[:n * L.stride].reshape(n, L.stride)
         return rec[:, off:off + 4].copy().view(np.uint32).reshape(-1).astype(np.uint64)
-    o = np.ascontiguousarray(bufs[_group_buffers(L, g, bufs)]).view(NP_DTYPE[S.decl.offset_types[g]])
+    o = np.ascontiguousarray(bufs[_group_buffers(L, g, bufs)]).view(NP_DTYPE[S.offset_types[g]])
     return (o[1:n + 1].astype(np.int64) - o[:n].astype(np.int64)).astype(np.uint64)
 
 
@@ -597,7 +710,7 @@ def _count_members(L: Layout, bufs, g, n):
                           strides=(L.stride,))
         return int(lens.astype(np.uint64).sum())
     i0 = _group_buffers(L, g, bufs)
-    t = S.decl.offset_types[g]
+    t = S.offset_types[g]
     offs = np.frombuffer(bufs[i0].tobytes(), dtype=NP_DTYPE[t])
     return int(offs[n]) - int(offs[0]) if n >= 0 else 0
 
@@ -631,7 +744,7 @@ def values_buffers(schema: Schema, v: Values):
         col = a if f.extent == 1 else a[:, e]
         bufs.append(np.ascontiguousarray(col, dtype=NP_DTYPE[f.type]).view(np.uint8).copy())
     for g in range(schema.n_groups):
-        t = schema.decl.offset_types[g]
+        t = schema.offset_types[g]
         offs = np.zeros(v.n + 1, dtype=np.uint64)
         np.cumsum(v.lengths[g].astype(np.uint64), out=offs[1:])
         bufs.append(offs.astype(NP_DTYPE[t]).view(np.uint8).copy())

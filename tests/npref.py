@@ -69,3 +69,69 @@ def aosoa_column(buf, width, sizes, c, n, dtype):
     start = width * sum(sizes[:c])
     run = blocks[:, start:start + width * sizes[c]]
     return np.ascontiguousarray(run).reshape(-1).view(dtype)[:n]
+
+
+# ---- property trees (nested structured dtypes)
+
+def tree_dtype(props, leaf_type=None):
+    """numpy structured dtype (C alignment, align=True) of a struct made of
+    tree properties: an item a scalar field, a sub-group a nested struct, an
+    array a sub-array of element structs, a jagged vector two fields
+    '<name>#ptr' (u64) and '<name>#len' (u32).  leaf_type(path, type) may
+    change an item's type (paths as the workloads name them)."""
+    return _tree_dtype(props, "", leaf_type)
+
+
+def _tree_dtype(props, prefix, leaf_type):
+    names, formats = [], []
+    for p in props:
+        path = f"{prefix}.{p.name}" if prefix else p.name
+        kind = type(p).__name__
+        if kind == "Item":
+            t = leaf_type(path, p.type) if leaf_type else p.type
+            names.append(p.name)
+            formats.append(NP_DTYPE[t])
+        elif kind == "Jagged":
+            names += [p.name + "#ptr", p.name + "#len"]
+            formats += [np.uint64, np.uint32]
+        elif kind == "SubGroup":
+            names.append(p.name)
+            formats.append(_tree_dtype(p.props, path, leaf_type))
+        else:
+            # element structs may differ when leaf_type narrows some elements
+            elems = [_tree_dtype(p.props, f"{path}[{e}]", leaf_type) for e in range(p.extent)]
+            if all(el == elems[0] for el in elems):
+                names.append(p.name)
+                formats.append((elems[0], (p.extent,)))
+            else:
+                for e, el in enumerate(elems):
+                    names.append(f"{p.name}@{e}")
+                    formats.append(el)
+    return np.dtype({"names": names, "formats": formats}, align=True)
+
+
+def flatten_dtype(dt, prefix="", base=0):
+    """(path, byte offset, dtype) of every scalar of a structured dtype in
+    declaration order, sub-arrays element by element; sub-array elements
+    named '<name>[e]', split arrays' '<name>@e' named the same way."""
+    out = []
+    for name in dt.names:
+        sub, off = dt.fields[name][0], dt.fields[name][1]
+        nm = name
+        if "@" in nm:
+            a, e = nm.split("@")
+            nm = f"{a}[{e}]"
+        path = f"{prefix}.{nm}" if prefix else nm
+        if sub.subdtype is not None:
+            el, shape = sub.subdtype
+            for e in range(shape[0]):
+                ep = f"{path}[{e}]"
+                if el.names:
+                    out += flatten_dtype(el, ep, base + off + e * el.itemsize)
+                else:
+                    out.append((ep, base + off + e * el.itemsize, el))
+        elif sub.names:
+            out += flatten_dtype(sub, path, base + off)
+        else:
+            out.append((path, base + off, sub))
+    return out

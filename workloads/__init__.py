@@ -102,6 +102,135 @@ PARTICLE = SchemaDecl("particle", (
 SCHEMAS = {s.name: s for s in (PLAIN8, CELL, CLUSTER, SENSOR, PARTICLE)}
 
 
+# ---------------------------------------------------------------- property trees
+#
+# Schemas whose properties nest (Sec. VI): an array property holds a list of
+# properties, and sub-groups and jagged vectors may sit inside arrays.  A
+# tree's logical values are named by paths: names joined by ".", an array
+# element as "[e]" after the array's name (e.g. "layers[1].pos.x").  Each
+# jagged vector reached -- each element of an array holding one is its own
+# -- is a jagged group; groups are numbered in the order a pre-order walk
+# reaches them, array elements in turn.
+
+@dataclass(frozen=True)
+class Item:
+    name: str
+    type: str
+
+
+@dataclass(frozen=True)
+class Array:
+    name: str
+    extent: int
+    props: tuple
+
+
+@dataclass(frozen=True)
+class SubGroup:
+    name: str
+    props: tuple
+
+
+@dataclass(frozen=True)
+class Jagged:
+    name: str
+    offset_type: str
+    props: tuple
+
+
+@dataclass(frozen=True)
+class TreeDecl:
+    name: str
+    props: tuple
+
+    def _walk(self):
+        """(object paths and types, [(offset type, member paths and types)])
+        in walk order."""
+        objs, groups = [], []
+
+        def go(p, prefix, members):
+            path = f"{prefix}.{p.name}" if prefix else p.name
+            if isinstance(p, Item):
+                (members if members is not None else objs).append((path, p.type))
+            elif isinstance(p, Array):
+                for e in range(p.extent):
+                    for c in p.props:
+                        go(c, f"{path}[{e}]", members)
+            elif isinstance(p, SubGroup):
+                for c in p.props:
+                    go(c, path, members)
+            else:
+                assert members is None, "jagged vectors do not nest"
+                mem = []
+                groups.append((path, p.offset_type, mem))
+                for c in p.props:
+                    go(c, path, mem)
+
+        for p in self.props:
+            go(p, "", None)
+        return objs, groups
+
+    @property
+    def offset_types(self):
+        return tuple(t for _, t, _ in self._walk()[1])
+
+    def object_paths(self):
+        return self._walk()[0]
+
+    def group_paths(self):
+        """Per group: (path of the jagged vector, offset type, member paths and types)."""
+        return self._walk()[1]
+
+
+def tree_values(decl: TreeDecl, n: int, seed: int, mean_len: float = 4.0,
+                shuffle_pool: bool = True) -> Values:
+    """Uniform values for a property tree, keyed by path: floats in
+    [-1e3, 1e3], integers over their full range, member counts of every
+    group Poisson(mean_len)."""
+    rng = np.random.default_rng(seed)
+    v = Values(decl, n)
+    for path, t in decl.object_paths():
+        v.fields[path] = _uniform_values(rng, Field(path, t), (n,))
+    for _, _, mem in decl.group_paths():
+        lens = rng.poisson(mean_len, size=n).astype(np.uint32)
+        v.lengths.append(lens)
+        tot = int(lens.sum())
+        for path, t in mem:
+            v.members[path] = _uniform_values(rng, Field(path, t), (tot,))
+        v.block_order.append(rng.permutation(n) if shuffle_pool else np.arange(n))
+    return v
+
+
+# Event-like record with nesting at every level: per-layer arrays of a
+# sub-group and items, per-calorimeter-side jagged cell lists (an array of
+# jagged vectors, u32 prefix sums) whose members hold an array, and a
+# track list with a sub-group inside each member (u64 prefix sums).
+TRACKER = TreeDecl("tracker", (
+    Item("energy", "f32"),
+    Array("layers", 3, (Item("hits", "u16"),
+                        SubGroup("pos", (Item("x", "f32"), Item("y", "f32"))),
+                        Item("flag", "u8"))),
+    Array("calo", 2, (Jagged("cells", "u32", (Item("id", "u32"),
+                                              Array("w", 2, (Item("v", "f32"),)))),)),
+    Item("id", "u64"),
+    Jagged("tracks", "u64", (Item("pt", "f32"),
+                             SubGroup("dir", (Item("eta", "f32"), Item("phi", "f32"))))),
+))
+
+# Arrays of sub-groups holding arrays (properties nested inside arrays,
+# extents multiplying), an f64 item to narrow, and an i32-offset jagged
+# vector of 8-byte members.
+DETECTOR = TreeDecl("detector", (
+    Item("flags", "u8"),
+    Array("modules", 4, (SubGroup("cal", (Item("gain", "f64"), Array("ped", 2, (Item("v", "i16"),)))),
+                         Item("ok", "u8"))),
+    Item("t0", "f64"),
+    Jagged("hits", "i32", (Item("adc", "u64"),)),
+))
+
+TREES = {t.name: t for t in (TRACKER, DETECTOR)}
+
+
 @dataclass
 class Values:
     """Logical content of a collection of ``n`` objects.
