@@ -103,6 +103,56 @@ rl_status rl_schema_create(const rl_field* fields, uint32_t n_fields,
                            rl_schema** out);
 void rl_schema_destroy(rl_schema* schema);
 
+/* A node of a property tree (Sec. VI: the kinds of property), for schemas
+ * whose properties nest: arrays holding several properties, sub-groups or
+ * jagged vectors inside arrays, arrays and sub-groups inside jagged vectors.
+ *  - RL_PROP_ITEM: a per-item property holding one value of `type`
+ *    (n_children 0).
+ *  - RL_PROP_ARRAY: an array property of `extent` elements (1..64), each
+ *    element holding the n_children child properties.
+ *  - RL_PROP_SUBGROUP: the n_children child properties as a sub-object.
+ *  - RL_PROP_JAGGED: a jagged vector property: each object holds a
+ *    variable number of members, each member holding the n_children child
+ *    properties; `type` is the type of the prefix sum of member counts
+ *    (RL_U32, RL_I32 or RL_U64).  A jagged vector inside another is not
+ *    supported.
+ * Nodes are listed in pre-order: a node is followed by its children's
+ * subtrees; the top-level properties follow each other.  name: may be
+ * NULL; copied. */
+typedef enum rl_prop_kind {
+  RL_PROP_ITEM = 0,
+  RL_PROP_ARRAY = 1,
+  RL_PROP_SUBGROUP = 2,
+  RL_PROP_JAGGED = 3
+} rl_prop_kind;
+
+typedef struct rl_prop {
+  rl_prop_kind kind;
+  const char* name;
+  rl_type type;
+  uint32_t extent;
+  uint32_t n_children;
+} rl_prop;
+
+/* Register a schema from a property tree.  Flattening walks the tree in
+ * pre-order, each array element in turn (element-major): every item
+ * outside a jagged vector is a per-object leaf and a record slot; every
+ * jagged vector reached (each element of an array holding one is its own)
+ * is the next jagged group, with a (ptr, len) slot pair where it is
+ * reached and its items as the group's member leaves.  The natural record
+ * (RL_AOS without explicit offsets) follows C rules: a sub-group is a
+ * nested struct; an array element is a struct of the element's properties
+ * (each element aligned to its largest member, its size rounded up to
+ * it); a jagged vector's pair is two members (u64 ptr, u32 len) of the
+ * enclosing struct; member records are the struct of a member's
+ * properties.  rl_schema_create's flat fields are the special case of
+ * extents over one item, one level of sub-groups, and jagged groups of
+ * items.  Limits as rl_schema_create.
+ * Errors: RL_EINVAL (bad kind, type, extent or child count, children past
+ * the end, an empty array, sub-group or jagged vector, a limit exceeded);
+ * RL_EUNSUPPORTED (a jagged vector inside another). */
+rl_status rl_schema_create_tree(const rl_prop* props, uint32_t n_props, rl_schema** out);
+
 /* Leaf counts of a schema.  Any out pointer may be NULL. */
 rl_status rl_schema_info(const rl_schema* schema, uint32_t* n_leaves,
                          uint32_t* n_groups, uint32_t* n_slots);

@@ -44,6 +44,14 @@ class rl_field(ctypes.Structure):
                 ("group", ctypes.c_int32), ("subgroup", ctypes.c_int32)]
 
 
+class rl_prop(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("name", ctypes.c_char_p), ("type", ctypes.c_int),
+                ("extent", ctypes.c_uint32), ("n_children", ctypes.c_uint32)]
+
+
+PROP_ITEM, PROP_ARRAY, PROP_SUBGROUP, PROP_JAGGED = 0, 1, 2, 3
+
+
 class rl_jagged(ctypes.Structure):
     _fields_ = [("offset_type", ctypes.c_int)]
 
@@ -106,6 +114,7 @@ _P = ctypes.POINTER
 TRANSFER_FN = ctypes.CFUNCTYPE(ctypes.c_int, _P(rl_view), _P(rl_view), ctypes.c_uint64, _VP, _VP)
 SIGNATURES = {
     "rl_schema_create": (ctypes.c_int, [_P(rl_field), ctypes.c_uint32, _P(rl_jagged), ctypes.c_uint32, _P(_VP)]),
+    "rl_schema_create_tree": (ctypes.c_int, [_P(rl_prop), ctypes.c_uint32, _P(_VP)]),
     "rl_schema_destroy": (None, [_VP]),
     "rl_schema_info": (ctypes.c_int, [_VP, _P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
     "rl_layout_create": (ctypes.c_int, [_VP, _P(rl_layout_desc), _P(_VP)]),
@@ -183,11 +192,39 @@ def __getattr__(name):
 
 # ------------------------------------------------------------------ helpers
 
+def _prop_list(props, out, names):
+    """Pre-order rl_prop entries of a property tree (nodes with ``props``
+    are arrays when they have an ``extent``, jagged vectors when they have
+    an ``offset_type``, sub-groups otherwise; leaves have a ``type``)."""
+    for p in props:
+        nm = p.name.encode()
+        names.append(nm)
+        if not hasattr(p, "props"):
+            out.append(rl_prop(PROP_ITEM, nm, TYPES.index(p.type), 1, 0))
+            continue
+        if hasattr(p, "extent"):
+            out.append(rl_prop(PROP_ARRAY, nm, 0, p.extent, len(p.props)))
+        elif hasattr(p, "offset_type"):
+            out.append(rl_prop(PROP_JAGGED, nm, TYPES.index(p.offset_type), 1, len(p.props)))
+        else:
+            out.append(rl_prop(PROP_SUBGROUP, nm, 0, 1, len(p.props)))
+        _prop_list(p.props, out, names)
+
+
 class Schema:
-    """An rl_schema registered from a workloads.SchemaDecl."""
+    """An rl_schema registered from a workloads.SchemaDecl (flat fields) or
+    a workloads.TreeDecl (a property tree)."""
 
     def __init__(self, decl):
         self.decl = decl
+        if hasattr(decl, "props"):
+            entries, self._names = [], []
+            _prop_list(decl.props, entries, self._names)
+            arr = (rl_prop * max(1, len(entries)))(*entries)
+            h = ctypes.c_void_p()
+            check(lib().rl_schema_create_tree(arr, len(entries), ctypes.byref(h)), "rl_schema_create_tree")
+            self._finish(h)
+            return
         fields = (rl_field * max(1, len(decl.fields)))()
         self._names = []
         for k, f in enumerate(decl.fields):
@@ -200,6 +237,9 @@ class Schema:
         h = ctypes.c_void_p()
         check(lib().rl_schema_create(fields, len(decl.fields), groups, len(decl.offset_types),
                                      ctypes.byref(h)), "rl_schema_create")
+        self._finish(h)
+
+    def _finish(self, h):
         self.handle = h
         nl, ng, ns = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         check(lib().rl_schema_info(h, ctypes.byref(nl), ctypes.byref(ng), ctypes.byref(ns)), "rl_schema_info")

@@ -94,139 +94,7 @@ static uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 using namespace rl;
 
-// ------------------------------------------------------------------ schema
-
-extern "C" rl_status rl_schema_create(const rl_field* fields, uint32_t n_fields,
-                                      const rl_jagged* groups, uint32_t n_groups,
-                                      rl_schema** out) {
-  if (!out) return fail(RL_EINVAL, "rl_schema_create: out is NULL");
-  *out = nullptr;
-  if (n_fields && !fields) return fail(RL_EINVAL, "rl_schema_create: fields is NULL");
-  if (n_groups && !groups) return fail(RL_EINVAL, "rl_schema_create: groups is NULL");
-  if (n_groups > (uint32_t)kMaxGroups) return fail(RL_EINVAL, "at most %d jagged groups", kMaxGroups);
-  auto* s = new rl_schema();
-  std::vector<int> group_seen(n_groups, 0);
-  int32_t prev_sub = -1;
-  std::vector<int> sub_closed;
-  for (uint32_t k = 0; k < n_fields; ++k) {
-    const rl_field& f = fields[k];
-    if (!valid_type(f.type)) { delete s; return fail(RL_EINVAL, "field %u: bad type %d", k, (int)f.type); }
-    if (f.extent < 1 || f.extent > (uint32_t)kMaxExtent) {
-      delete s; return fail(RL_EINVAL, "field %u: extent %u outside 1..%d", k, f.extent, kMaxExtent);
-    }
-    if (f.group < -1 || f.group >= (int32_t)n_groups) {
-      delete s; return fail(RL_EINVAL, "field %u: group %d out of range", k, f.group);
-    }
-    if (f.subgroup < -1) { delete s; return fail(RL_EINVAL, "field %u: bad subgroup", k); }
-    if (f.group >= 0 && f.subgroup >= 0) {
-      delete s; return fail(RL_EINVAL, "field %u: a member field cannot be in a sub-group", k);
-    }
-    // sub-groups label consecutive runs of per-object fields
-    if (f.group < 0) {
-      if (f.subgroup >= 0 && f.subgroup != prev_sub) {
-        if (std::find(sub_closed.begin(), sub_closed.end(), f.subgroup) != sub_closed.end()) {
-          delete s; return fail(RL_EINVAL, "field %u: sub-group %d is not consecutive", k, f.subgroup);
-        }
-      }
-      if (prev_sub >= 0 && f.subgroup != prev_sub) sub_closed.push_back(prev_sub);
-      prev_sub = f.subgroup;
-    }
-    s->fields.push_back(f);
-    s->names.push_back(f.name ? f.name : "");
-  }
-  for (uint32_t g = 0; g < n_groups; ++g) {
-    const rl_type t = groups[g].offset_type;
-    if (t != RL_U32 && t != RL_I32 && t != RL_U64) {
-      delete s; return fail(RL_EINVAL, "group %u: offset type must be U32, I32 or U64", g);
-    }
-    s->offset_types.push_back(t);
-  }
-  s->members.resize(n_groups);
-  for (uint32_t k = 0; k < n_fields; ++k) {
-    const rl_field& f = fields[k];
-    if (f.group < 0) {
-      for (uint32_t e = 0; e < f.extent; ++e) {
-        s->slots.push_back({0, (int)s->leaves.size(), f.subgroup});
-        s->leaves.push_back({f.type, type_size(f.type), (int32_t)k, e, f.subgroup});
-      }
-    } else {
-      if (!group_seen[f.group]) {
-        group_seen[f.group] = 1;
-        s->slots.push_back({1, f.group, -1});
-        s->slots.push_back({2, f.group, -1});
-      }
-      for (uint32_t e = 0; e < f.extent; ++e)
-        s->members[f.group].push_back({f.type, type_size(f.type), (int32_t)k, e, -1});
-    }
-  }
-  for (uint32_t g = 0; g < n_groups; ++g) {
-    if (!group_seen[g]) { delete s; return fail(RL_EINVAL, "group %u has no member field", g); }
-    if (s->members[g].size() > (size_t)kMaxMembers) {
-      delete s; return fail(RL_EINVAL, "group %u: at most %d member leaves", g, kMaxMembers);
-    }
-  }
-  if (s->leaves.size() + 2 * n_groups > (size_t)kMaxLeaves) {
-    delete s; return fail(RL_EINVAL, "at most %d per-object leaves (plus 2 per group)", kMaxLeaves);
-  }
-  *out = s;
-  return RL_OK;
-}
-
-extern "C" void rl_schema_destroy(rl_schema* schema) { delete schema; }
-
-extern "C" rl_status rl_schema_info(const rl_schema* s, uint32_t* n_leaves, uint32_t* n_groups,
-                                    uint32_t* n_slots) {
-  if (!s) return fail(RL_EINVAL, "schema is NULL");
-  if (n_leaves) *n_leaves = (uint32_t)s->leaves.size();
-  if (n_groups) *n_groups = (uint32_t)s->offset_types.size();
-  if (n_slots) *n_slots = (uint32_t)s->slots.size();
-  return RL_OK;
-}
-
 // ------------------------------------------------------------------ layouts
-
-// C natural alignment of the record slots (sub-groups as nested structs).
-static void natural_record(const rl_schema* s, const std::vector<rl_type>& storage,
-                           std::vector<uint64_t>& offs, uint64_t& stride) {
-  offs.assign(s->slots.size(), 0);
-  auto slot_size = [&](const rl_schema::Slot& sl) -> uint64_t {
-    if (sl.kind == 0) return type_size(storage[sl.index]);
-    return sl.kind == 1 ? 8 : 4;
-  };
-  uint64_t pos = 0, max_align = 1;
-  size_t k = 0;
-  while (k < s->slots.size()) {
-    const int32_t sub = s->slots[k].subgroup;
-    if (sub < 0) {
-      const uint64_t sz = slot_size(s->slots[k]);
-      pos = round_up(pos, sz);
-      offs[k] = pos;
-      pos += sz;
-      max_align = std::max(max_align, sz);
-      ++k;
-      continue;
-    }
-    // nested struct: the run of slots with this sub-group id
-    size_t e = k;
-    uint64_t inner = 0, ia = 1;
-    std::vector<uint64_t> local;
-    while (e < s->slots.size() && s->slots[e].subgroup == sub) {
-      const uint64_t sz = slot_size(s->slots[e]);
-      inner = round_up(inner, sz);
-      local.push_back(inner);
-      inner += sz;
-      ia = std::max(ia, sz);
-      ++e;
-    }
-    inner = round_up(inner, ia);
-    pos = round_up(pos, ia);
-    for (size_t j = k; j < e; ++j) offs[j] = pos + local[j - k];
-    pos += inner;
-    max_align = std::max(max_align, ia);
-    k = e;
-  }
-  stride = pos ? round_up(pos, max_align) : 0;
-}
 
 extern "C" rl_status rl_layout_create(const rl_schema* schema, const rl_layout_desc* desc,
                                       rl_layout** out) {
@@ -323,17 +191,12 @@ extern "C" rl_status rl_layout_create(const rl_schema* schema, const rl_layout_d
       else if (sl.kind == 1) L->ptr_off[sl.index] = (uint32_t)L->slot_offsets[k];
       else L->len_off[sl.index] = (uint32_t)L->slot_offsets[k];
     }
-    for (size_t g = 0; g < schema->members.size(); ++g) {
-      uint32_t pos = 0, ma = 1;
+    for (uint32_t g = 0; g < (uint32_t)schema->members.size(); ++g) {
       std::vector<uint32_t> mo;
-      for (const auto& m : schema->members[g]) {
-        pos = (uint32_t)round_up(pos, m.size);
-        mo.push_back(pos);
-        pos += m.size;
-        ma = std::max(ma, m.size);
-      }
+      uint32_t ms = 0, ma = 1;
+      natural_member_record(schema, g, mo, ms, ma);
       L->moff.push_back(mo);
-      L->mstride.push_back((uint32_t)round_up(pos, ma));
+      L->mstride.push_back(ms);
       L->malign.push_back(ma);
     }
   }

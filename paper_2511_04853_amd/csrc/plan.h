@@ -65,6 +65,12 @@ rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>&
 rl_status convert_general(const rl_view& src, const rl_view& dst, uint64_t n, hipStream_t s);
 
 uint32_t type_size(rl_type t);
+// Natural (C) record of a schema's per-object slots in the given leaf
+// storage types, and of group g's member record.
+void natural_record(const rl_schema* s, const std::vector<rl_type>& storage, std::vector<uint64_t>& offs,
+                    uint64_t& stride);
+void natural_member_record(const rl_schema* s, uint32_t g, std::vector<uint32_t>& offs, uint32_t& stride,
+                           uint32_t& align);
 uint32_t layout_n_buffers(const rl_layout* L);
 void layout_buffer_bytes(const rl_layout* L, uint64_t n, const uint64_t* members, uint64_t* bytes);
 uint32_t group_buffer(const rl_layout* L, uint32_t g);

@@ -376,6 +376,17 @@ struct rl_schema {
     int index;
     int32_t subgroup;
   };
+  // A property of the schema's tree; flat field lists are turned into one.
+  struct Prop {
+    rl_prop_kind kind;
+    rl_type type;                  // item: value type; jagged: offset type
+    uint32_t extent;               // array
+    int32_t group;                 // jagged from a flat list: its group; -1: numbered in walk order
+    std::string name;
+    std::vector<Prop> children;
+  };
+  std::vector<Prop> tree;
+  std::vector<const Prop*> group_prop;      // per group: its jagged property
   std::vector<rl_field> fields;
   std::vector<std::string> names;
   std::vector<Leaf> leaves;
