@@ -51,7 +51,8 @@ typedef enum rl_status {
   RL_EHIP = 9,          /* a HIP runtime call failed (message has its text) */
   RL_EBUSY = 10,        /* the object is in use (e.g. ticket not complete) */
   RL_EBOUNDS = 11,      /* a source member block outside its pool/columns, or misaligned */
-  RL_ELIMIT = 12        /* a request beyond a fixed size limit of the library */
+  RL_ELIMIT = 12,       /* a request beyond a fixed size limit of the library */
+  RL_ECANCELED = 13     /* the event was cancelled before it was admitted */
 } rl_status;
 
 /* Scalar types of a property (Sec. VI: per-item properties hold one native
@@ -607,11 +608,23 @@ rl_status rl_server_create(const rl_server_opts* opts, rl_server** out);
 /* Errors: RL_EBUDGET (the event alone exceeds the budget), RL_EINVAL. */
 rl_status rl_server_submit(rl_server* server, const rl_event* event,
                            uint64_t* ticket);
-/* Block until the event is done (timeout_ms < 0: forever); RL_EBUSY on
-   timeout. */
+/* Block until the event is done (timeout_ms < 0: forever) and return its
+   status (result, may be NULL, receives its buffers).  RL_EBUSY on
+   timeout; RL_ECANCELED if the event is cancelled (or the server destroyed)
+   while waiting; RL_EINVAL for an unknown ticket (released or cancelled
+   before the call).  The result's pointers stay valid until the event is
+   released. */
 rl_status rl_server_wait(rl_server* server, uint64_t ticket, int64_t timeout_ms,
                          rl_event_result* result);
+/* Free a finished event's resident results (RL_EBUSY if it is not done). */
 rl_status rl_server_release(rl_server* server, uint64_t ticket);
+/* Withdraw an event that is still queued (not yet admitted): it is never
+   converted and its ticket is forgotten.  RL_EBUSY once it has been
+   admitted (it then runs to completion and is released as usual);
+   RL_EINVAL for an unknown ticket.  The head of the queue admits in
+   arrival order and waits for budget; cancelling it lets the next one
+   through. */
+rl_status rl_server_cancel(rl_server* server, uint64_t ticket);
 rl_status rl_server_stats_get(rl_server* server, rl_server_stats* stats);
 void rl_server_destroy(rl_server* server);
 

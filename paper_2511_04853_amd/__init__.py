@@ -20,11 +20,12 @@ LIB_PATH = os.path.join(_HERE, "librelayout.so")
 RL_OK, RL_EINVAL, RL_EALIGN, RL_EOVERLAP, RL_ECAPACITY, RL_EOVERFLOW = 0, 1, 2, 3, 4, 5
 RL_ENOMEM, RL_EBUDGET, RL_EUNSUPPORTED, RL_EHIP, RL_EBUSY, RL_EBOUNDS = 6, 7, 8, 9, 10, 11
 RL_ELIMIT = 12
+RL_ECANCELED = 13
 # staging limit of rl_transfer_noalloc (RL_TRANSFER_NOALLOC_LIMIT in the header)
 TRANSFER_NOALLOC_LIMIT = 32 << 20
 STATUS_NAMES = {0: "RL_OK", 1: "RL_EINVAL", 2: "RL_EALIGN", 3: "RL_EOVERLAP", 4: "RL_ECAPACITY",
                 5: "RL_EOVERFLOW", 6: "RL_ENOMEM", 7: "RL_EBUDGET", 8: "RL_EUNSUPPORTED",
-                9: "RL_EHIP", 10: "RL_EBUSY", 11: "RL_EBOUNDS", 12: "RL_ELIMIT"}
+                9: "RL_EHIP", 10: "RL_EBUSY", 11: "RL_EBOUNDS", 12: "RL_ELIMIT", 13: "RL_ECANCELED"}
 TYPES = ["u8", "i8", "u16", "i16", "u32", "i32", "u64", "i64", "f32", "f64"]
 KINDS = {"aos": 0, "soa": 1, "aosoa": 2, "strided": 3}
 SPACES = {"device": 0, "host": 1, "pinned": 2}
@@ -150,6 +151,7 @@ SIGNATURES = {
     "rl_server_submit": (ctypes.c_int, [_VP, _P(rl_event), _P(ctypes.c_uint64)]),
     "rl_server_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int64, _P(rl_event_result)]),
     "rl_server_release": (ctypes.c_int, [_VP, ctypes.c_uint64]),
+    "rl_server_cancel": (ctypes.c_int, [_VP, ctypes.c_uint64]),
     "rl_server_stats_get": (ctypes.c_int, [_VP, _P(rl_server_stats)]),
     "rl_server_destroy": (None, [_VP]),
 }
@@ -466,6 +468,14 @@ class Server:
     def release(self, ticket):
         check(lib().rl_server_release(self.h, ticket), "rl_server_release")
         self._keep.pop(ticket, None)
+
+    def cancel(self, ticket):
+        """rl_server_cancel: withdraw a queued event; returns the status
+        (RL_OK, or RL_EBUSY once admitted)."""
+        st = lib().rl_server_cancel(self.h, ticket)
+        if st == RL_OK:
+            self._keep.pop(ticket, None)
+        return st
 
     def stats(self):
         s = rl_server_stats()

@@ -2,7 +2,8 @@
 collections converted concurrently on several streams, results resident
 until released.  Each event's result must be the same bytes alone and in
 the mix (and the oracle's); the budget is never exceeded; an event larger
-than the budget is refused; a stalled consumer blocks admission."""
+than the budget is refused; a stalled consumer blocks admission; queued
+events can be cancelled."""
 import ctypes
 
 import numpy as np
@@ -179,4 +180,34 @@ def test_zero_object_items_take_no_pool_block():
     res = srv.wait(t, timeout_ms=20_000)
     assert res is not None and res["status"] == 0
     srv.release(t)
+    srv.close()
+
+
+def test_queued_events_can_be_cancelled():
+    """The largest event fills the budget and is held; events queued behind
+    it can be cancelled (never converted, tickets forgotten), the admitted
+    one cannot; after its release the remaining events complete with the
+    oracle's bytes."""
+    ev = Events(6, scale=20, seed=77)
+    needs = [sum(sum((b + 255) // 256 * 256 for b in it["sizes"]) for it in items) for items in ev.events]
+    big = int(np.argmax(needs))
+    order = [big] + [e for e in range(len(ev.events)) if e != big]
+    srv = P.Server(needs[big] + (256 << 10), max_in_flight=8, n_streams=1)   # + the look-back region
+    tickets = {e: ev.submit(srv, e) for e in order}
+    res = srv.wait(tickets[big], timeout_ms=20_000)
+    assert res is not None and res["status"] == 0
+    ev.check(big, res)
+    assert srv.cancel(tickets[big]) == P.RL_EBUSY
+    gone = order[1::2]
+    for e in gone:
+        assert srv.cancel(tickets[e]) == P.RL_OK
+        assert srv.cancel(tickets[e]) == P.RL_EINVAL
+    srv.release(tickets[big])
+    for e in order[2::2]:
+        res = srv.wait(tickets[e], timeout_ms=20_000)
+        assert res is not None and res["status"] == 0
+        ev.check(e, res)
+        srv.release(tickets[e])
+    st = srv.stats()
+    assert st["submitted"] == len(order) and st["completed"] == len(order) - len(gone)
     srv.close()
