@@ -53,6 +53,7 @@ struct Config {
   uint32_t grid = 0;     // dense work-groups; 0: as many as fit on the device at once
   uint32_t direct = 0;   // 1: launch the batch kernels directly instead of replaying the graph
   uint32_t gather_threads = kGatherThreads;   // member-gather work-groups
+  uint32_t pipe = 0;     // 1: dense steps double-buffered (two tile slots per work-group)
 };
 
 struct DeviceTables {
@@ -267,7 +268,12 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   t.rebase_tiles = (uint32_t)rprefix.back();
   out->dense_lds = dense_lds;
   out->gather_lds = gather_lds;
-  (void)c;
+  t.pipe_slot = 0;
+  const uint32_t slot = (dense_lds + 15u) & ~15u;
+  if (c.pipe && 2 * slot <= 64 * 1024) {
+    t.pipe_slot = slot;
+    out->dense_lds = 2 * slot;
+  }
   return RL_OK;
 }
 
@@ -336,6 +342,7 @@ bool cache_lookup(const std::string& path, const std::string& sig, Config* c) {
     if (num("tile", &t.tile) && num("threads", &t.threads) && num("grid", &t.grid) && num("width", &t.width)) {
       num("direct", &t.direct);
       num("gather_threads", &t.gather_threads);
+      num("pipe", &t.pipe);
       *c = t;
       return true;
     }
@@ -358,8 +365,8 @@ void cache_store(const std::string& path, const std::string& sig, const Config& 
   char buf[256];
   snprintf(buf, sizeof buf,
            "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"direct\":%u, "
-           "\"gather_threads\":%u, \"us\":%.2f}",
-           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, c.gather_threads, us);
+           "\"gather_threads\":%u, \"pipe\":%u, \"us\":%.2f}",
+           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, c.gather_threads, c.pipe, us);
   keep.push_back(buf);
   std::ofstream o(path + ".tmp");
   o << "{\n";
@@ -404,18 +411,22 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
     for (uint32_t threads : {64u, 128u, 256u})
       // 0: as many work-groups as fit at once (persistent); kOnePerTile: one
       // work-group per tile (the dispatcher balances uneven tiles)
-      for (uint32_t grid : {0u, 1024u, 2048u, 4096u, 8192u, kOnePerTile}) {
-        if (threads > 2 * tile) continue;   // at least half the threads hold an object
-        Config c;
-        c.tile = tile;
-        c.threads = threads;
-        c.grid = grid;
-        c.width = 64;
-        double us;
-        rl_status st = time_config(b, c, s, &us);
-        if (st) return st;
-        if (us < best_us) { best_us = us; bc = c; }
-      }
+      for (uint32_t grid : {0u, 1024u, 2048u, 4096u, 8192u, kOnePerTile})
+        // double-buffered work-groups need more than one tile each
+        for (uint32_t pipe : {0u, 1u}) {
+          if (threads > 2 * tile) continue;   // at least half the threads hold an object
+          if (pipe && grid == kOnePerTile) continue;
+          Config c;
+          c.tile = tile;
+          c.threads = threads;
+          c.grid = grid;
+          c.width = 64;
+          c.pipe = pipe;
+          double us;
+          rl_status st = time_config(b, c, s, &us);
+          if (st) return st;
+          if (us < best_us) { best_us = us; bc = c; }
+        }
   // member gathers: one-wave work-groups keep more sub-tiles in flight,
   // larger ones fewer instructions per member
   if (std::any_of(b->items.begin(), b->items.end(), [](const Item& i) { return !i.src_layout->schema->members.empty(); }))
@@ -608,6 +619,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (const char* v = getenv("RL_BATCH_GRID")) c.grid = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_THREADS")) c.threads = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_GATHER_THREADS")) c.gather_threads = (uint32_t)strtoul(v, nullptr, 10);
+  if (const char* v = getenv("RL_BATCH_PIPE")) c.pipe = (uint32_t)strtoul(v, nullptr, 10) ? 1 : 0;
   if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 128;
   if (c.gather_threads < 64 || c.gather_threads > 256 || c.gather_threads % 64) c.gather_threads = kGatherThreads;
 
@@ -664,7 +676,7 @@ extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t*
     // at once, at most one per tile
     const uint32_t g = b->cfg.grid ? b->cfg.grid
                                    : batch_resident_blocks(std::min<uint32_t>(b->cfg.threads, kDenseMaxThreads),
-                                                           b->dev.dense_lds);
+                                                           b->dev.dense_lds, b->dev.t.pipe_slot != 0);
     *grid = std::min<uint32_t>(g, std::max(1u, b->dev.t.dense_tiles));
   }
   if (graph_replay) *graph_replay = b->cfg.direct ? 0 : 1;

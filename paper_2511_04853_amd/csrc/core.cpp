@@ -353,7 +353,8 @@ rl_status check_overlap(const std::vector<Range>& src, const std::vector<Range>&
 namespace rl {
 // Tile shape override for experiments and the tile-independence tests:
 // RL_TILE_OBJECTS (objects per tile), RL_BLOCK_THREADS, RL_GRID_BLOCKS;
-// RL_DST_DIRECT, RL_SOURCE_DMA and RL_JAGGED_FUSED (0 turns a path off;
+// RL_DST_DIRECT, RL_SOURCE_DMA, RL_JAGGED_FUSED and RL_PIPELINE (0 turns a path off;
+// RL_PIPELINE=1 double-buffers every dense step where two tile slots fit;
 // RL_JAGGED_FUSED=2 makes a jagged records conversion fail with
 // RL_EUNSUPPORTED where the single-pass kernel does not apply).
 PlanShape shape_from_env() {
@@ -367,6 +368,7 @@ PlanShape shape_from_env() {
   if (const char* v = getenv("RL_DST_DIRECT")) s.direct = atoi(v) ? -1 : 0;
   if (const char* v = getenv("RL_SOURCE_DMA")) s.dma = atoi(v) ? -1 : 0;
   if (const char* v = getenv("RL_JAGGED_FUSED")) s.fused = atoi(v) == 2 ? 2 : atoi(v) ? -1 : 0;
+  if (const char* v = getenv("RL_PIPELINE")) s.pipe = atoi(v) == 1 ? 1 : atoi(v) ? -1 : 0;
   return s;
 }
 }  // namespace rl

@@ -359,21 +359,43 @@ __device__ __forceinline__ void dma16(const uint8_t* g, uint32_t lds_base) {
 // Copy a 16-byte aligned global run of `bytes` into LDS (16-byte aligned)
 // by DMA; the last bytes % 16 go through registers.  Wave w takes the
 // 64-vector chunks w, w + waves, ...
-__device__ __forceinline__ void dma_run(uint8_t* lds, const uint8_t* g, uint32_t bytes) {
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+__device__ __forceinline__ void dma_run(uint8_t* lds, const uint8_t* g, uint32_t bytes, uint32_t nthreads = blockDim.x) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = nthreads >> 6;
   const uint32_t nv = bytes >> 4;
   for (uint32_t vb = wave * 64; vb < nv; vb += nw * 64) {
     const uint32_t v = vb + lane;
     const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr)(lds + (size_t)vb * 16));
     if (v < nv) dma16(g + (size_t)v * 16, base);
   }
-  for (uint32_t b = (nv << 4) + threadIdx.x; b < bytes; b += blockDim.x) lds[b] = gp(g)[b];
+  for (uint32_t b = (nv << 4) + threadIdx.x; b < bytes; b += nthreads) lds[b] = gp(g)[b];
 }
 
 // Wait for this wave's DMA into LDS (and every earlier vector-memory
 // operation: the counter retires in order).  A barrier must follow before
 // other waves read what this wave loaded.
 __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
+
+// Wait until at most `n` of this wave's vector-memory operations are
+// outstanding (n wave-uniform).  The counter retires in order, so every
+// operation issued before the last n has completed.  Rounded down to a
+// few counts (waiting for more is always correct); vmcnt's 6 bits are
+// split over simm16 bits 3:0 and 15:14, expcnt and lgkmcnt left at their
+// maxima.
+template <uint32_t N>
+__device__ __forceinline__ void vm_wait_le() {
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+__device__ __forceinline__ void vm_wait_at_most(uint32_t n) {
+  if (n >= 56) vm_wait_le<56>();
+  else if (n >= 48) vm_wait_le<48>();
+  else if (n >= 40) vm_wait_le<40>();
+  else if (n >= 32) vm_wait_le<32>();
+  else if (n >= 24) vm_wait_le<24>();
+  else if (n >= 16) vm_wait_le<16>();
+  else if (n >= 8) vm_wait_le<8>();
+  else if (n >= 4) vm_wait_le<4>();
+  else vm_wait_le<0>();
+}
 
 // A wave's copy of the fast-path fields of a descriptor's leaves: lane c
 // holds leaf c (a schema has at most one wavefront of leaves).  Loaded with
@@ -408,6 +430,51 @@ __device__ __forceinline__ void load_lanes(const DD& d, uint32_t item, LeafLanes
   t.item = item;
 }
 
+// load_lanes through scalar loads (leaf c read at a uniform index, then
+// placed in lane c): no vector-memory operation, so nothing that waits on
+// the in-order vector counter (the double-buffered pipeline fills the lanes
+// of its next tile while the current tile's stores are still in flight).
+// The byte fields of a leaf descriptor in constant memory, read as whole
+// words: there are no sub-word scalar loads, so a u8 or u16 field would be
+// read with a per-lane vector load that waits behind every store in
+// flight.  Word 2: src_size | dst_size << 8 | op << 16 | byte_wise << 24;
+// word 3: mstride | off_type << 16 | code << 24.
+template <class LD>
+__device__ __forceinline__ uint32_t leaf_word(const LD& L, uint32_t k) {
+  return reinterpret_cast<const RL_C uint32_t*>(&L)[k];
+}
+
+// vec with lane c set to v (v and c wave-uniform).  The empty asm keeps v
+// a per-iteration scalar: without it the compiler turns the caller's loop
+// over leaves into one vector load per lane, whose wait would also wait
+// for every store in flight.
+__device__ __forceinline__ uint32_t put_lane(uint32_t vec, uint32_t v, uint32_t c) {
+  return (threadIdx.x & 63) == c ? v : vec;
+}
+
+template <class DD>
+__device__ __forceinline__ void load_lanes_scalar(const DD& d, uint32_t item, LeafLanes& t) {
+  const uint32_t nl = d.n_leaves;
+  for (uint32_t c = 0; c < nl; ++c) {
+    const auto& L = d.leaf[c];
+    const uint32_t w2 = leaf_word(L, 2), w3 = leaf_word(L, 3);
+    const uint32_t op = (w2 >> 16) & 255;
+    const uint32_t src_off = op == OP_PTR ? (w3 & 0xffff) : L.src_off;
+    const uint32_t code = (w3 >> 24) | ((w2 & 255) << 8) | (op << 16) | ((w2 >> 24) << 24) |
+                          (((w3 >> 16) & 255) << 25);
+    const uint64_t col = reinterpret_cast<uint64_t>(L.dst_col);
+    const uint64_t scol = reinterpret_cast<uint64_t>(L.src_col);
+    t.src_off = put_lane(t.src_off, src_off, c);
+    t.dst_off = put_lane(t.dst_off, L.dst_off, c);
+    t.code = put_lane(t.code, code, c);
+    t.col_lo = put_lane(t.col_lo, (uint32_t)col, c);
+    t.col_hi = put_lane(t.col_hi, (uint32_t)(col >> 32), c);
+    t.scol_lo = put_lane(t.scol_lo, (uint32_t)scol, c);
+    t.scol_hi = put_lane(t.scol_hi, (uint32_t)(scol >> 32), c);
+  }
+  t.item = item;
+}
+
 __device__ __forceinline__ uint32_t lane_of(uint32_t v, uint32_t c) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)c);
 }
@@ -416,7 +483,7 @@ __device__ __forceinline__ uint32_t lane_of(uint32_t v, uint32_t c) {
 // 16-byte aligned, else through registers (complete on return).
 template <class DD>
 __device__ __forceinline__ void issue_image(const DD& d, uint8_t* img, const TileJob& j, const LeafLanes& lt,
-                                            bool lanes_ready) {
+                                            bool lanes_ready, uint32_t nthreads = blockDim.x) {
   const uint64_t i0 = j.tile * d.tile;
   const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, j.count - i0);
   const uint64_t idx0 = i0 + j.base;
@@ -425,7 +492,7 @@ __device__ __forceinline__ void issue_image(const DD& d, uint8_t* img, const Til
     if (s.kind == KIND_AOS || s.kind == KIND_AOSOA) {
       const uint8_t* run = s.base + idx0 * (s.kind == KIND_AOS ? s.stride : s.obj_bytes);
       if (((uintptr_t)run & 15) == 0) {
-        dma_run(img, run, s.kind == KIND_AOS ? cnt * s.stride : image_used(s, cnt));
+        dma_run(img, run, s.kind == KIND_AOS ? cnt * s.stride : image_used(s, cnt), nthreads);
         return;
       }
     } else if ((idx0 & 15) == 0) {
@@ -442,13 +509,15 @@ __device__ __forceinline__ void issue_image(const DD& d, uint8_t* img, const Til
           if (op == OP_PTR || op == OP_LEN) continue;
           const uint8_t* col =
               reinterpret_cast<const uint8_t*>(((uint64_t)lane_of(lt.scol_hi, c) << 32) | lane_of(lt.scol_lo, c));
-          dma_run(img + lane_of(lt.src_off, c), col + idx0 * sz, cnt * sz);
+          dma_run(img + lane_of(lt.src_off, c), col + idx0 * sz, cnt * sz, nthreads);
         }
       } else {
         for (uint32_t c = 0; c < nl; ++c) {
           const auto& L = d.leaf[c];
-          if (L.op == OP_PTR || L.op == OP_LEN) continue;
-          dma_run(img + L.src_off, L.src_col + idx0 * L.src_size, cnt * L.src_size);
+          const uint32_t w2 = leaf_word(L, 2);
+          const uint32_t op = (w2 >> 16) & 255, sz = w2 & 255;
+          if (op == OP_PTR || op == OP_LEN) continue;
+          dma_run(img + L.src_off, L.src_col + idx0 * sz, cnt * sz, nthreads);
         }
       }
       return;
@@ -473,8 +542,8 @@ __device__ __forceinline__ uint64_t staged_off(const uint8_t* run, uint32_t type
 // n + 1 entries.  LDS holds entry 0's vector, then the run.
 template <class DD>
 __device__ __forceinline__ void issue_source(const DD& d, uint8_t* smem, const TileJob& j, const LeafLanes& lt,
-                                             bool lanes_ready) {
-  issue_image(d, smem, j, lt, lanes_ready);
+                                             bool lanes_ready, uint32_t nthreads = blockDim.x) {
+  issue_image(d, smem, j, lt, lanes_ready, nthreads);
   if (!d.stage_offsets) return;
   const uint64_t i0 = j.tile * d.tile;
   const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, j.count - i0);
@@ -485,8 +554,8 @@ __device__ __forceinline__ void issue_source(const DD& d, uint8_t* smem, const T
   const uint64_t column = (d.n + 1) * es;
   if (d.dma && ((uintptr_t)g & 15) == 0) {
     const uint32_t up = round16(need);
-    dma_run(head, d.stage_offsets, column >= 16 ? 16u : es);
-    dma_run(head + 16, g, (uint64_t)up <= column - i0 * es ? up : need);
+    dma_run(head, d.stage_offsets, column >= 16 ? 16u : es, nthreads);
+    dma_run(head + 16, g, (uint64_t)up <= column - i0 * es ? up : need, nthreads);
   } else {
     g2l(head, d.stage_offsets, es, threadIdx.x, blockDim.x);
     g2l(head + 16, g, need, threadIdx.x, blockDim.x);
@@ -688,14 +757,16 @@ template <class DD>
 __device__ __forceinline__ void zero_tail_direct(const DD& d, uint64_t i0, uint32_t cnt, uint32_t tx, uint32_t ntx) {
   const auto& s = d.dst;
   const uint32_t end = s.width == 1 ? cnt : __umulhi(cnt + s.width - 1, s.width_magic) * s.width;
+  if (end == cnt) return;
   uint8_t* const Dtile = s.base + i0 * s.obj_bytes;
   for (uint32_t c = 0; c < d.n_leaves; ++c) {
     const auto& L = d.leaf[c];
+    const uint32_t dsz = (leaf_word(L, 2) >> 8) & 255;
     for (uint32_t o = cnt + tx; o < end; o += ntx) {
       uint32_t a, b;
       obj_terms<KIND_AOSOA>(s, o, a, b);
-      uint8_t* p = Dtile + a + L.dst_off + b * L.dst_size;
-      switch (L.dst_size) {
+      uint8_t* p = Dtile + a + L.dst_off + b * dsz;
+      switch (dsz) {
         case 1: put<true, uint8_t>(p, 0); break;
         case 2: put<true, uint16_t>(p, 0); break;
         case 4: put<true, uint32_t>(p, 0); break;
@@ -721,24 +792,25 @@ __device__ __forceinline__ void transform_kinds(const DD& d, const DenseLds& m, 
 // stores coalesce without a destination image.
 template <class DD>
 __device__ __forceinline__ void transform_direct(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
-                                                 uint32_t cnt) {
+                                                 uint32_t cnt, uint32_t nt) {
+  const uint32_t tx = threadIdx.x;
   switch (d.src.kind * 3 + d.dst.kind) {
-    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true>(d, m, lt, i0, cnt); break;
-    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true>(d, m, lt, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
-    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true>(d, m, lt, i0, cnt); break;
-    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, true>(d, m, lt, i0, cnt); break;
-    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, true>(d, m, lt, i0, cnt); break;
-    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true>(d, m, lt, i0, cnt); break;
+    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, true>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, true>(d, m, lt, i0, cnt, tx, nt); break;
+    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true>(d, m, lt, i0, cnt, tx, nt); break;
   }
 }
 
 template <class DD>
 __device__ __forceinline__ void transform_tile(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
-                                               uint32_t cnt, uint32_t* status) {
+                                               uint32_t cnt, uint32_t* status, uint32_t nt = blockDim.x) {
   if (d.dst_direct) {
-    transform_direct(d, m, lt, i0, cnt);
+    transform_direct(d, m, lt, i0, cnt, nt);
     return;
   }
   if (d.slow_leaves) {
@@ -811,15 +883,93 @@ __device__ __forceinline__ void dense_pipeline(uint8_t* smem, Next next, Desc de
   }
 }
 
+// A lower bound of the vector-memory instructions each wave issues while
+// transforming a tile: direct destinations store every fast leaf of each
+// of a thread's kObjPerThread objects with one instruction per full pass
+// (full passes have no per-object branches).  Other paths count nothing,
+// which is always a lower bound.
+template <class DD>
+__device__ __forceinline__ uint32_t stores_at_least(const DD& d, uint32_t cnt, uint32_t nt) {
+  if (!d.dst_direct || d.slow_leaves || d.scan_offsets) return 0;
+  const uint32_t per_pass = kObjPerThread * nt;
+  return (cnt / per_pass) * kObjPerThread * d.fast_leaves;
+}
+
+// One tile of the double-buffered pipeline: `cur` (its image in `cur_smem`,
+// its leaf lanes in lc) is converted while the next tile's DMA, issued
+// first into `nxt_smem` with its lanes in ln, is in flight.  `after` holds
+// a lower bound of this wave's vector-memory instructions issued after the
+// current tile's DMA; the wait lets that many stay outstanding, so the
+// previous tile's stores keep draining while this tile starts.  Returns
+// false when no tile follows.
+template <class Next, class Desc>
+__device__ __forceinline__ bool db_tile(uint8_t* cur_smem, uint8_t* nxt_smem, LeafLanes& lc, LeafLanes& ln,
+                                        TileJob& cur, uint32_t& after, Next& next, Desc& desc, uint32_t* status,
+                                        uint32_t nt) {
+  vm_wait_at_most(after);
+  __syncthreads();
+  // every wave is past the previous tile, whose slot the next DMA reuses
+  const TileJob nxt = next();
+  if (nxt.valid) {
+    const bool same = nxt.item == lc.item;
+    if (same) ln = lc;
+    else load_lanes_scalar(desc(nxt.item), nxt.item, ln);
+    issue_source(desc(nxt.item), nxt_smem, nxt, lc, same, nt);
+  }
+  const auto& d = desc(cur.item);
+  const DenseLds m = carve(cur_smem, d);
+  const uint64_t i0 = cur.tile * d.tile;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, cur.count - i0);
+  const bool full = cnt == d.tile;
+  if (!d.dst_direct && (d.zero_dst || (!full && d.dst.kind == KIND_AOSOA))) {
+    v4u* z = reinterpret_cast<v4u*>(m.dst);
+    const uint32_t nv = d.dst.image_bytes >> 4;
+    for (uint32_t v = threadIdx.x; v < nv; v += nt) z[v] = v4u{0u, 0u, 0u, 0u};
+    __syncthreads();
+  }
+  if (d.scan_offsets) scan_tile(d, m, i0, cnt, status);
+  transform_tile(d, m, lc, i0, cnt, status, nt);
+  if (!d.dst_direct) {
+    __syncthreads();
+    store_side(d, m.dst, i0, cnt, full);
+  }
+  after = stores_at_least(d, cnt, nt);
+  cur = nxt;
+  return nxt.valid != 0;
+}
+
+// The tiles handed out by `next`, two at a time: each work-group owns two
+// LDS slots of `slot` bytes, and a tile's source DMA is issued before the
+// previous tile's transform, so loads and stores of consecutive tiles
+// overlap instead of the next DMA waiting behind the stores (the
+// vector-memory counter retires in order).
+template <class Next, class Desc>
+__device__ __forceinline__ void dense_pipeline_db(uint8_t* smem, uint32_t slot, Next next, Desc desc,
+                                                  uint32_t* status) {
+  // the thread count is read once: blockDim.x is a 16-bit implicit
+  // argument, read with a vector load wherever it is evaluated
+  const uint32_t nt = blockDim.x;
+  LeafLanes l0, l1;
+  TileJob cur = next();
+  if (!cur.valid) return;
+  load_lanes_scalar(desc(cur.item), cur.item, l0);
+  issue_source(desc(cur.item), smem, cur, l0, false, nt);
+  uint32_t after = 0;
+  while (db_tile(smem, smem + slot, l0, l1, cur, after, next, desc, status, nt) &&
+         db_tile(smem + slot, smem, l1, l0, cur, after, next, desc, status, nt)) {
+  }
+}
+
 // Tiles blockIdx.x, blockIdx.x + gridDim.x, ... of one conversion.
 struct StridedTiles {
   uint64_t t, ntiles, count, base;
+  uint32_t g;   // gridDim.x, read once (a 16-bit implicit argument is read with a vector load)
   __device__ __forceinline__ TileJob operator()() {
     TileJob j{0, 0, 0, count, base};
     if (t < ntiles) {
       j.valid = 1;
       j.tile = t;
-      t += gridDim.x;
+      t += g;
     }
     return j;
   }
@@ -831,8 +981,21 @@ __global__ void __launch_bounds__(256, 7) dense_kernel(const DenseDesc) {
   uint64_t count, base;
   dense_count(d, &count, &base);
   dense_pipeline(reinterpret_cast<uint8_t*>(smem_raw),
-                 StridedTiles{blockIdx.x, (count + d.tile - 1) / d.tile, count, base},
+                 StridedTiles{blockIdx.x, (count + d.tile - 1) / d.tile, count, base, gridDim.x},
                  [&](uint32_t) -> const RL_C DenseDesc& { return kernel_arg<DenseDesc>(); }, d.status);
+}
+
+// The same conversion double-buffered (two tile slots of d.pipe_slot bytes
+// per work-group).  The slots already limit residency, so registers may
+// hold both tiles' leaf lanes: at least 4 waves per SIMD.
+__global__ void __launch_bounds__(256, 4) dense_db_kernel(const DenseDesc) {
+  extern __shared__ uint4 smem_raw[];
+  const RL_C DenseDesc& d = kernel_arg<DenseDesc>();
+  uint64_t count, base;
+  dense_count(d, &count, &base);
+  dense_pipeline_db(reinterpret_cast<uint8_t*>(smem_raw), d.pipe_slot,
+                    StridedTiles{blockIdx.x, (count + d.tile - 1) / d.tile, count, base, gridDim.x},
+                    [&](uint32_t) -> const RL_C DenseDesc& { return kernel_arg<DenseDesc>(); }, d.status);
 }
 
 // ------------------------------------------------------------------ offsets
@@ -1901,6 +2064,58 @@ __global__ void __launch_bounds__(256, 6) batch_dense_kernel(const BatchTables b
                  [&](uint32_t item) -> const RL_C DenseDesc& { return cdesc(b.dense, item); }, b.status);
 }
 
+// The same tiles for the double-buffered pipeline: each wave holds the
+// work-group's next 64 map entries, one per lane (with their steps' counts
+// and bases), loaded together and refilled every 64 tiles, so handing out
+// a tile makes no memory access: a load there would be waited for with
+// every store still in flight (the counter retires in order).
+struct ChunkTiles {
+  const BatchTables* b;
+  uint64_t t;         // first tile of the held chunk
+  uint32_t k, n;      // next entry to hand out, entries held
+  uint64_t e, c, base;
+  uint32_t g;         // gridDim.x, read once
+  __device__ __forceinline__ explicit ChunkTiles(const BatchTables* tb)
+      : b(tb), t(blockIdx.x), k(0), n(0), e(0), c(0), base(0), g(gridDim.x) {}
+  __device__ __forceinline__ void refill() {
+    const uint64_t tiles = b->dense_tiles;
+    const uint64_t tl = t + (uint64_t)(threadIdx.x & 63) * g;
+    n = t < tiles ? (uint32_t)min<uint64_t>(64, (tiles - t + g - 1) / g) : 0;
+    k = 0;
+    if (tl < tiles) {
+      e = gp(b->dense_map)[tl];
+      const uint32_t item = (uint32_t)(e >> 32);
+      c = gp(b->dense_counts)[2 * item];
+      base = gp(b->dense_counts)[2 * item + 1];
+    }
+  }
+  __device__ __forceinline__ static uint64_t lane64(uint64_t v, uint32_t l) {
+    return ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+  }
+  __device__ __forceinline__ TileJob operator()() {
+    while (true) {
+      if (k == n) {
+        if (t >= b->dense_tiles) return TileJob{0, 0, 0, 0, 0};
+        refill();
+        if (n == 0) return TileJob{0, 0, 0, 0, 0};
+      }
+      const uint32_t idx = k++;
+      if (k == n) t += 64ull * g;
+      const uint64_t ee = lane64(e, idx), cc = lane64(c, idx), bb = lane64(base, idx);
+      const uint32_t item = (uint32_t)(ee >> 32), local = (uint32_t)ee;
+      if ((uint64_t)local * cdesc(b->dense, item).tile < cc) return TileJob{1, item, local, cc, bb};
+    }
+  }
+};
+
+// Batches with double-buffered dense steps (two slots of b.pipe_slot bytes).
+__global__ void __launch_bounds__(256, 4) batch_dense_db_kernel(const BatchTables b) {
+  extern __shared__ uint4 smem_raw[];
+  dense_pipeline_db(reinterpret_cast<uint8_t*>(smem_raw), b.pipe_slot, ChunkTiles(&b),
+                    [&](uint32_t item) -> const RL_C DenseDesc& { return cdesc(b.dense, item); }, b.status);
+}
+
 // Tile-total scans (one work-group each) and offsets rebases.
 __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   __shared__ uint64_t wsum[17];
@@ -1967,18 +2182,22 @@ static uint32_t resident_blocks(const void* kernel, uint32_t threads, uint32_t l
   return r;
 }
 
-uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds) {
-  return resident_blocks(reinterpret_cast<const void*>(batch_dense_kernel), threads, lds);
+uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined) {
+  return resident_blocks(pipelined ? reinterpret_cast<const void*>(batch_dense_db_kernel)
+                                   : reinterpret_cast<const void*>(batch_dense_kernel), threads, lds);
 }
 
 hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid, hipStream_t s) {
   if (threads == 0 || threads > kDenseMaxThreads || threads % 64) return hipErrorInvalidValue;
-  const uint32_t lds = dense_lds_bytes(d);
+  if (d.pipe_slot && d.pipe_slot < dense_lds_bytes(d)) return hipErrorInvalidValue;
+  const uint32_t lds = d.pipe_slot ? 2 * d.pipe_slot : dense_lds_bytes(d);
   // persistent work-groups: no more than fit at once (a second round of
   // work-groups would start late and leave the tail on few units)
-  const uint32_t res = resident_blocks(reinterpret_cast<const void*>(dense_kernel), threads, lds);
+  const void* k = d.pipe_slot ? reinterpret_cast<const void*>(dense_db_kernel) : reinterpret_cast<const void*>(dense_kernel);
+  const uint32_t res = resident_blocks(k, threads, lds);
   if (res && grid > res) grid = res;
-  hipLaunchKernelGGL(dense_kernel, dim3(grid), dim3(threads), lds, s, d);
+  if (d.pipe_slot) hipLaunchKernelGGL(dense_db_kernel, dim3(grid), dim3(threads), lds, s, d);
+  else hipLaunchKernelGGL(dense_kernel, dim3(grid), dim3(threads), lds, s, d);
   return hipGetLastError();
 }
 
@@ -2014,7 +2233,8 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
   if (gather_threads == 0 || gather_threads > 256 || gather_threads % 64) return hipErrorInvalidValue;
   const uint32_t dense_grid = std::min<uint32_t>(
-      grid ? grid : std::max<uint32_t>(1, batch_resident_blocks(dense_threads, dense_lds)), std::max(1u, b.dense_tiles));
+      grid ? grid : std::max<uint32_t>(1, batch_resident_blocks(dense_threads, dense_lds, b.pipe_slot != 0)),
+      std::max(1u, b.dense_tiles));
   if (!grid) grid = 2048;   // finalisation and gather kernels
   if (b.dense_tiles) {
     if (b.device_counts) {
@@ -2022,7 +2242,8 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
       hipError_t e0 = hipGetLastError();
       if (e0 != hipSuccess) return e0;
     }
-    hipLaunchKernelGGL(batch_dense_kernel, dim3(dense_grid), dim3(dense_threads), dense_lds, s, b);
+    if (b.pipe_slot) hipLaunchKernelGGL(batch_dense_db_kernel, dim3(dense_grid), dim3(dense_threads), dense_lds, s, b);
+    else hipLaunchKernelGGL(batch_dense_kernel, dim3(dense_grid), dim3(dense_threads), dense_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -16,6 +16,9 @@ struct PlanShape {
   int dma = -1;           // source runs DMA'd into LDS: -1 where aligned, 0 never
   int fused = -1;         // single-pass jagged kernel: -1 where it applies, 0 never,
                           // 2 required (a jagged records source fails where it does not apply)
+  int pipe = -1;          // dense steps double-buffered (two tile slots in LDS):
+                          // -1 for long conversions where two slots fit, 0 never,
+                          // 1 wherever two slots fit
   // Look-back memory of single-pass jagged steps given by the caller
   // (zeroed before its first use, used by one stream at a time); null:
   // the library's per-stream buffer.  A step needing more tiles than it

@@ -103,6 +103,9 @@ struct DenseDesc {
   uint32_t dst_direct;     // 1: values go straight from the source image to global memory
                            //    (SoA / AoSoA destination, no destination image in LDS)
   uint32_t vt_magic;       // ceil(2^32 / (tile / 16)): SoA image vector -> byte unit
+  uint32_t fast_leaves;    // leaves on the fast transform path (code below CODE_BYTES)
+  uint32_t pipe_slot;      // single conversions: LDS bytes of each of two tile slots
+                           // (double-buffered pipeline); 0: one slot
   uint64_t src_capacity;   // with count_offsets: source member capacity (count <= it - base)
   // Offsets column staged in LDS per tile for the record (pointer, count)
   // leaves of an AoS destination (null: read from global memory per object).
@@ -301,6 +304,7 @@ struct BatchTables {
   const uint64_t* rebase_prefix;    // first rebase tile of each rebase step
   const uint32_t* rebase_item;      // rebase tile -> rebase step
   uint32_t rebase_tiles;
+  uint32_t pipe_slot;               // dense steps: LDS bytes of each of two tile slots; 0: one slot
   uint32_t* status;                 // status word of the launching stream
 };
 constexpr uint32_t kRebaseTile = 8192;   // offsets entries per rebase work-group
@@ -344,7 +348,7 @@ constexpr uint32_t kGatherThreads = 128;
 uint32_t dense_lds_bytes(const DenseDesc& d);
 // Work-groups of the batch dense kernel that fit on the current device at
 // once for this block size and LDS size (0 if unknown).
-uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds);
+uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined);
 uint64_t dense_tiles(const DenseDesc& d);
 
 // ---- errors ----
