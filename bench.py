@@ -772,7 +772,8 @@ def _cluster_device_collection(P, W, torch, n, g, aos, soa):
     return av, tot
 
 
-def sweep(P, W, torch, stream, copies=4):
+def sweep(P, W, torch, stream, copies=4, schemas=("plain8", "cell"), sizes=(1 << 20, 1 << 22, 1 << 24, 1 << 25),
+          jagged=True):
     """AoS records -> SoA at larger object counts, `copies` copies rotating
     (cold at every size): the plain schema (8 scalars) and the cell schema
     (energy_d narrowed) at 2^20 .. 2^25 objects, the cluster schema (jagged,
@@ -790,11 +791,13 @@ def sweep(P, W, torch, stream, copies=4):
         return round(2 * half / (ms * 1e-3) / 1e9, 1)
 
     for sname, decl in (("plain8", W.PLAIN8), ("cell", W.CELL)):
+        if sname not in schemas:
+            continue
         S = P.Schema(decl)
         narrowed = ["f32" if f.type == "f64" else f.type for f in decl.fields] if decl is W.CELL else None
         aos = P.Layout(S, "aos")
         soa = P.Layout(S, "soa", storage=narrowed)
-        for n in (1 << 20, 1 << 22, 1 << 24, 1 << 25):
+        for n in sizes:
             pairs = []
             for _ in range(copies):
                 src = torch.randint(0, 255, (aos.buffer_bytes(n)[0],), dtype=torch.uint8, device="cuda")
@@ -812,6 +815,8 @@ def sweep(P, W, torch, stream, copies=4):
                                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "copy_kernel_GBps": cp,
                                    "frac_of_copy": round(gbs / cp, 4)}
             torch.cuda.empty_cache()
+    if not jagged:
+        return res
     # jagged: cluster records + pool -> SoA + offsets + member columns
     S = P.Schema(W.CLUSTER)
     aos, soa = P.Layout(S, "aos"), P.Layout(S, "soa")
@@ -1090,6 +1095,9 @@ LEGS = {
                                                    warmup=min(1000, SERVING_EVENTS[0])),
     "cpu_events": cpu_events,
     "pipeline": pipeline,
+    # one sweep row alone (cell AoS -> SoA at 2^24 objects), for its counters
+    "sweep_cell_2_24": lambda P, W, torch, stream: sweep(P, W, torch, stream, schemas=("cell",), sizes=(1 << 24,),
+                                                         jagged=False),
 }
 EXTRA_ORDER = ["single_conversion", "copy_peak", "round_trip", "jagged", "batched", "sweep", "h2d", "d2h",
                "pipeline", "serving", "cpu_events"]
