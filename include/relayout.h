@@ -353,7 +353,10 @@ void rl_collection_destroy(rl_collection* c);
  * argument validation, with the caller's arguments.  Returns RL_OK once it
  * has enqueued the whole transfer on `stream`; RL_EUNSUPPORTED to decline
  * (the next matching specialisation is tried, then the library's own
- * implementation); any other status fails the call with that status. */
+ * implementation); any other status fails the call with that status.
+ * rl_convert and rl_transfer called from inside a user transfer (on the
+ * same thread) go straight to the library's own implementation, so a
+ * specialisation can wrap the default transfer without recursing. */
 typedef rl_status (*rl_transfer_fn)(const rl_view* src, const rl_view* dst,
                                     uint64_t n, void* stream, void* user);
 

@@ -163,3 +163,36 @@ def test_user_transfer_on_the_device_matches_the_oracle():
         H.assert_same_bytes(H.to_numpy(ddst2), want, "declined: library kernels")
     finally:
         P.unregister_transfer(i)
+
+
+@pytest.mark.gpu
+def test_a_user_transfer_can_wrap_the_library_transfer():
+    """A specialisation that calls rl_convert itself (for instance to do
+    work around the default conversion) reaches the library's own kernels:
+    it runs once, does not recurse, and the result is the oracle's."""
+    pytest.importorskip("torch")
+    sp = H.SchemaPair(W.CELL)
+    aos, soa = sp.layout("aos"), sp.layout("soa", storage=H.narrowed_storage(W.CELL))
+    n = 50_001
+    v = W.cell_values(n, seed=8)
+    sb = oracle.pack(sp.orc, v, aos.orc)
+    st, want, _ = oracle.convert(aos.orc, sb, soa.orc, n)
+    assert st == 0
+    dsrc = H.to_device(sb)
+    ddst = H.alloc_device(soa.lib.buffer_bytes(n))
+    calls, nested = [], []
+
+    def wrapper(src, dst, cnt, stream, u):
+        calls.append(cnt)
+        r = P.lib().rl_convert(src, dst, cnt, ctypes.c_void_p(stream))
+        nested.append(r)
+        return r
+
+    i, keep = P.register_transfer(aos.lib, soa.lib, 5, wrapper)
+    try:
+        P.convert(P.View(aos.lib, n, dsrc), P.View(soa.lib, n, ddst), n)
+        assert P.sync() == 0, P.rl_last_error()
+        assert calls == [n] and nested == [P.RL_OK]
+        H.assert_same_bytes(H.to_numpy(ddst), want, "wrapped library transfer")
+    finally:
+        P.unregister_transfer(i)
