@@ -133,6 +133,10 @@ def main():
         sets.append((sv, outs, b))
     torch.cuda.synchronize()
     shape = sets[0][2].shape()
+    binfo = sets[0][2].info()
+    fanned = binfo.fanout_steps == binfo.dense_steps and binfo.fanout_groups > 0
+    step_kernel = ("rl::batch_fanout_kernel" if fanned else
+                   "rl::batch_dense_db_kernel" if binfo.double_buffered else "rl::batch_dense_kernel")
 
     src_bytes = aos.buffer_bytes(n)[0]
     conv_bytes = [src_bytes + sum(L.buffer_bytes(n)) for L in dsts]
@@ -163,9 +167,10 @@ def main():
     ms_per_step = ms_total / K
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
 
-    # A step is one launch of the batch dense kernel (the only kernel of a
-    # step whose counts are host-known), so its mean launch duration in the
-    # timed region is ms_per_step.  An event pair around each of 50 launches
+    # A step is one launch of one batch kernel (the fan-out kernel when all
+    # four conversions share each source tile, else the dense kernel; the
+    # counts are host-known, so no other kernel runs), so its mean launch
+    # duration in the timed region is ms_per_step.  An event pair around each of 50 launches
     # of a second pass gives the paper's statistic for isolated launches
     # (each includes its dispatch latency).
     mean_launch_ms = ms_per_step
@@ -206,7 +211,10 @@ def main():
             "bytes_per_step": step_bytes,
             "conversions_per_step": len(dsts),
             "launch": f"one batch launch per step (the 4 conversions; {shape[3]}), "
-                      f"tile {shape[0]} objects, {shape[1]} threads, {shape[2]} work-groups (autotuned)",
+                      f"tile {shape[0]} objects, {shape[1]} threads, {shape[2]} work-groups"
+                      + (f", one source tile read per work-group for all {binfo.fanout_steps} conversions "
+                         f"({binfo.fanout_threads} threads each)" if fanned else "")
+                      + (", double-buffered" if binfo.double_buffered else "") + " (autotuned)",
         },
         "roofline": {
             "bound": "hbm",
@@ -215,7 +223,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "kernel": "rl::batch_dense_kernel",
+            "kernel": step_kernel,
             "bytes_basis": "algorithmic: per conversion, source footprint read + destination footprint written",
             "mean_launch_us": round(mean_launch_ms * 1e3, 3),
             "isolated_launch_us": iso,
@@ -277,6 +285,11 @@ class Batch:
         self.P.check(self.P.lib().rl_batch_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                                  ctypes.byref(g)), "shape")
         return a.value, b.value, c.value, "graph replay" if g.value else "direct launch"
+
+    def info(self):
+        i = self.P.rl_batch_info()
+        self.P.check(self.P.lib().rl_batch_get_info(self.h, ctypes.byref(i)), "rl_batch_get_info")
+        return i
 
 
 def batched(P, W, torch, stream, tune_cache):

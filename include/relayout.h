@@ -549,10 +549,27 @@ rl_status rl_batch_item_width(const rl_batch* batch, uint32_t item,
 /* Shape chosen for the batch: objects per tile, threads per block,
    persistent blocks, and whether rl_batch_launch replays the captured graph
    (1) or launches the same kernels directly (0; the autotuner keeps
-   whichever it measured faster).  Any out pointer may be NULL. */
+   whichever it measured faster).  When every dense step sits in a fan-out
+   group (rl_batch_info), threads and blocks are those of the fan-out
+   launch.  Any out pointer may be NULL. */
 rl_status rl_batch_shape(const rl_batch* batch, uint32_t* tile_objects,
                          uint32_t* block_threads, uint32_t* grid_blocks,
                          uint32_t* graph_replay);
+/* How the batch's dense steps run, as the autotuner (or the RL_BATCH_*
+   environment overrides) left them.  Steps that convert the same source
+   view into direct destinations (SoA, AoSoA) may form fan-out groups of up
+   to four: one work-group per source tile reads the tile into LDS once and
+   a thread group per step stores that step's destination. */
+typedef struct rl_batch_info {
+  uint32_t double_buffered;   /* 1: dense steps run with two tile slots per work-group */
+  uint32_t fanout_threads;    /* threads per destination in fan-out groups; 0: no fan-out */
+  uint32_t fanout_groups;     /* fan-out groups formed */
+  uint32_t fanout_steps;      /* dense steps inside them */
+  uint32_t dense_steps;       /* dense steps in all */
+  uint32_t reserved[3];
+} rl_batch_info;
+/* RL_EINVAL for a NULL argument or a batch not finalized. */
+rl_status rl_batch_get_info(const rl_batch* batch, rl_batch_info* info);
 void rl_batch_destroy(rl_batch* batch);
 
 /* ------------------------------------------------------------------ serving */

@@ -80,6 +80,12 @@ class rl_batch_opts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
+class rl_batch_info(ctypes.Structure):
+    _fields_ = [("double_buffered", ctypes.c_uint32), ("fanout_threads", ctypes.c_uint32),
+                ("fanout_groups", ctypes.c_uint32), ("fanout_steps", ctypes.c_uint32),
+                ("dense_steps", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+
 class rl_server_opts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_in_flight", ctypes.c_uint32),
                 ("n_streams", ctypes.c_uint32)]
@@ -146,6 +152,7 @@ SIGNATURES = {
     "rl_batch_item_width": (ctypes.c_int, [_VP, ctypes.c_uint32, _P(ctypes.c_uint32)]),
     "rl_batch_shape": (ctypes.c_int, [_VP, _P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32),
                                       _P(ctypes.c_uint32)]),
+    "rl_batch_get_info": (ctypes.c_int, [_VP, _P(rl_batch_info)]),
     "rl_batch_destroy": (None, [_VP]),
     "rl_server_create": (ctypes.c_int, [_P(rl_server_opts), _P(_VP)]),
     "rl_server_submit": (ctypes.c_int, [_VP, _P(rl_event), _P(ctypes.c_uint64)]),

@@ -54,12 +54,16 @@ struct Config {
   uint32_t direct = 0;   // 1: launch the batch kernels directly instead of replaying the graph
   uint32_t gather_threads = kGatherThreads;   // member-gather work-groups
   uint32_t pipe = 0;     // 1: dense steps double-buffered (two tile slots per work-group)
+  uint32_t fanout = 0;   // >0: steps reading the same source tiles share one work-group per tile,
+                         // this many threads per destination (64 or 128)
 };
 
 struct DeviceTables {
   uint8_t* mem = nullptr;
   BatchTables t{};
   uint32_t dense_lds = 0, gather_lds = 0;
+  uint32_t fan_threads = 0, fan_lds = 0;
+  uint32_t fan_groups = 0, fan_steps = 0, dense_steps = 0;
   void release() {
     if (mem) (void)hipFree(mem);
     mem = nullptr;
@@ -138,16 +142,19 @@ static uint64_t source_key(const DenseDesc& d) {
 // run that goes to one XCD's consecutive entries: the later reads of the
 // run hit that XCD's L2.  Runs go to the XCD with the most entries left,
 // so single-tile runs interleave over the XCDs as in plain order.
-static void fill_dense_map(const std::vector<DenseDesc>& dense, const std::vector<uint64_t>& prefix,
-                           uint64_t* map) {
+// `steps` lists the dense steps the map covers (those not in a fan-out
+// group); prefix[k] is the first tile of steps[k].
+static void fill_dense_map(const std::vector<DenseDesc>& dense, const std::vector<uint32_t>& steps,
+                           const std::vector<uint64_t>& prefix, uint64_t* map) {
   struct T {
     uint64_t key, first, entry;
   };
   std::vector<T> tiles;
   tiles.reserve(prefix.back());
-  for (size_t k = 0; k + 1 < prefix.size(); ++k) {
+  for (size_t i = 0; i + 1 < prefix.size(); ++i) {
+    const uint32_t k = steps[i];
     const uint64_t key = source_key(dense[k]);
-    for (uint64_t t = 0; t < prefix[k + 1] - prefix[k]; ++t)
+    for (uint64_t t = 0; t < prefix[i + 1] - prefix[i]; ++t)
       tiles.push_back({key ? key : (uint64_t)k + 1, t * dense[k].tile, ((uint64_t)k << 32) | t});
   }
   std::stable_sort(tiles.begin(), tiles.end(),
@@ -187,8 +194,6 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
       switch (s.kind) {
         case Step::DENSE:
           dense.push_back(s.dense);
-          dprefix.push_back(dprefix.back() + dense_tiles(s.dense));
-          dense_lds = std::max(dense_lds, dense_lds_bytes(s.dense));
           break;
         case Step::GATHER:
           gather.push_back(s.gather);
@@ -202,7 +207,61 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
           break;
       }
     }
-  if (dprefix.back() >= (1ull << 32) || gprefix.back() >= (1ull << 32))
+  // fan-out groups: steps that read the same source tiles, their counts
+  // known on the host, with direct destinations and no scan, staged
+  // offsets or slow leaves; up to kFanMax steps per group
+  std::vector<FanGroup> fans;
+  std::vector<uint8_t> grouped(dense.size(), 0);
+  if (c.fanout) {
+    std::map<std::string, std::vector<uint32_t>> by_source;
+    for (uint32_t k = 0; k < dense.size(); ++k) {
+      const DenseDesc& d = dense[k];
+      if (d.count_offsets || d.scan_offsets || d.stage_offsets || !d.dst_direct || d.slow_leaves || !d.n) continue;
+      std::string key(reinterpret_cast<const char*>(&d.src), sizeof d.src);
+      auto add = [&](const void* p, size_t n) { key.append(reinterpret_cast<const char*>(p), n); };
+      add(&d.n, sizeof d.n);
+      add(&d.tile, sizeof d.tile);
+      add(&d.n_leaves, sizeof d.n_leaves);
+      add(&d.dma, sizeof d.dma);
+      for (uint32_t c2 = 0; c2 < d.n_leaves; ++c2) {
+        add(&d.leaf[c2].src_off, sizeof d.leaf[c2].src_off);
+        add(&d.leaf[c2].src_size, sizeof d.leaf[c2].src_size);
+        add(&d.leaf[c2].src_col, sizeof d.leaf[c2].src_col);
+      }
+      by_source[key].push_back(k);
+    }
+    for (auto& kv : by_source) {
+      const auto& v = kv.second;
+      if (v.size() < 2) continue;
+      for (size_t i = 0; i < v.size(); i += kFanMax) {
+        FanGroup g{};
+        g.n_dst = (uint32_t)std::min<size_t>(kFanMax, v.size() - i);
+        if (g.n_dst < 2) break;   // a lone remainder stays a plain step
+        for (uint32_t w = 0; w < g.n_dst; ++w) {
+          g.step[w] = v[i + w];
+          grouped[v[i + w]] = 1;
+        }
+        fans.push_back(g);
+      }
+    }
+  }
+  std::vector<uint32_t> singles;
+  for (uint32_t k = 0; k < dense.size(); ++k)
+    if (!grouped[k]) {
+      singles.push_back(k);
+      dprefix.push_back(dprefix.back() + dense_tiles(dense[k]));
+      dense_lds = std::max(dense_lds, dense_lds_bytes(dense[k]));
+    }
+  uint64_t fan_tiles = 0;
+  uint32_t fan_lds = 0, fan_threads = 0;
+  for (uint32_t g = 0; g < fans.size(); ++g) {
+    fans[g].first = (uint32_t)std::min<uint64_t>(fan_tiles, UINT32_MAX);
+    fan_tiles += dense_tiles(dense[fans[g].step[0]]);
+    fans[g].end = (uint32_t)std::min<uint64_t>(fan_tiles, UINT32_MAX);
+    for (uint32_t w = 0; w < fans[g].n_dst; ++w) fan_lds = std::max(fan_lds, dense_lds_bytes(dense[fans[g].step[w]]));
+    fan_threads = std::max(fan_threads, c.fanout * fans[g].n_dst);
+  }
+  if (dprefix.back() >= (1ull << 32) || gprefix.back() >= (1ull << 32) || fan_tiles >= (1ull << 32))
     return fail(RL_EUNSUPPORTED, "batch has more than 2^32 tiles");
   // one allocation: tables, prefix arrays and tile -> item maps
   size_t sz = 0;
@@ -218,6 +277,7 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   const size_t o_gitem = reserve(gprefix.back() * 4);
   const size_t o_rp = reserve(rprefix.size() * 8);
   const size_t o_ritem = reserve(rprefix.back() * 4);
+  const size_t o_fan = reserve(fans.size() * sizeof(FanGroup));
   std::vector<uint8_t> host(sz, 0);
   memcpy(host.data() + o_dense, dense.data(), dense.size() * sizeof(DenseDesc));
   memcpy(host.data() + o_dp, dprefix.data(), dprefix.size() * 8);
@@ -232,7 +292,8 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
       dc[2 * k] = dense[k].n;
       dc[2 * k + 1] = 0;
     }
-    fill_dense_map(dense, dprefix, (uint64_t*)(host.data() + o_dmap));
+    fill_dense_map(dense, singles, dprefix, (uint64_t*)(host.data() + o_dmap));
+    memcpy(host.data() + o_fan, fans.data(), fans.size() * sizeof(FanGroup));
     uint32_t* gi = (uint32_t*)(host.data() + o_gitem);
     for (size_t k = 0; k + 1 < gprefix.size(); ++k)
       for (uint64_t t = gprefix[k]; t < gprefix[k + 1]; ++t) gi[t] = (uint32_t)k;
@@ -266,6 +327,14 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   t.rebase_prefix = (const uint64_t*)(out->mem + o_rp);
   t.rebase_item = (const uint32_t*)(out->mem + o_ritem);
   t.rebase_tiles = (uint32_t)rprefix.back();
+  t.fan = (const FanGroup*)(out->mem + o_fan);
+  t.fan_tiles = (uint32_t)fan_tiles;
+  t.fan_per = c.fanout;
+  out->fan_threads = fan_threads;
+  out->fan_lds = fan_lds;
+  out->fan_groups = (uint32_t)fans.size();
+  out->fan_steps = (uint32_t)(dense.size() - singles.size());
+  out->dense_steps = (uint32_t)dense.size();
   out->dense_lds = dense_lds;
   out->gather_lds = gather_lds;
   t.pipe_slot = 0;
@@ -283,7 +352,7 @@ rl_status launch_tables(const DeviceTables& d, const Config& c, hipStream_t s, u
   const uint32_t dt = std::min<uint32_t>(c.threads, kDenseMaxThreads);
   BatchTables t = d.t;
   t.status = status;
-  hipError_t e = launch_batch(t, dt, c.gather_threads, c.grid, d.dense_lds, d.gather_lds, s);
+  hipError_t e = launch_batch(t, dt, c.gather_threads, c.grid, d.dense_lds, d.gather_lds, s, d.fan_threads, d.fan_lds);
   return e == hipSuccess ? RL_OK : hip_fail(e, "batch launch");
 }
 
@@ -343,6 +412,8 @@ bool cache_lookup(const std::string& path, const std::string& sig, Config* c) {
       num("direct", &t.direct);
       num("gather_threads", &t.gather_threads);
       num("pipe", &t.pipe);
+      num("fanout", &t.fanout);
+      if (t.fanout) t.fanout = t.fanout >= 128 ? 128 : 64;
       *c = t;
       return true;
     }
@@ -365,8 +436,8 @@ void cache_store(const std::string& path, const std::string& sig, const Config& 
   char buf[256];
   snprintf(buf, sizeof buf,
            "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"direct\":%u, "
-           "\"gather_threads\":%u, \"pipe\":%u, \"us\":%.2f}",
-           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, c.gather_threads, c.pipe, us);
+           "\"gather_threads\":%u, \"pipe\":%u, \"fanout\":%u, \"us\":%.2f}",
+           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, c.gather_threads, c.pipe, c.fanout, us);
   keep.push_back(buf);
   std::ofstream o(path + ".tmp");
   o << "{\n";
@@ -401,6 +472,18 @@ rl_status time_config(rl_batch* b, const Config& c, hipStream_t s, double* us) {
   d.release();
   *us = ms * 1000.0 / reps;
   return st;
+}
+
+// Whether two items convert the same source view (candidates for a
+// fan-out group; build_tables decides which steps qualify).
+static bool has_fanout(const rl_batch* b) {
+  for (size_t i = 0; i < b->items.size(); ++i)
+    for (size_t k = i + 1; k < b->items.size(); ++k) {
+      const Item& x = b->items[i];
+      const Item& y = b->items[k];
+      if (x.src_layout == y.src_layout && x.n == y.n && x.src_bufs == y.src_bufs) return true;
+    }
+  return false;
 }
 
 rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
@@ -438,6 +521,21 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
       if (st) return st;
       if (us < best_us * 0.98) { best_us = us; bc = c; }
     }
+  // steps sharing a source: one work-group per source tile for all of them
+  if (has_fanout(b)) {
+    const Config base = bc;
+    for (uint32_t tile : {64u, 128u, 256u, 512u})
+      for (uint32_t per : {64u, 128u}) {
+        Config c = base;
+        c.tile = tile;
+        c.fanout = per;
+        c.pipe = 0;
+        double us;
+        rl_status st = time_config(b, c, s, &us);
+        if (st) return st;
+        if (us < best_us * 0.98) { best_us = us; bc = c; }
+      }
+  }
   if (any_auto)
     for (uint32_t w : kAutoWidths) {
       Config c = bc;
@@ -620,6 +718,10 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (const char* v = getenv("RL_BATCH_THREADS")) c.threads = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_GATHER_THREADS")) c.gather_threads = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_PIPE")) c.pipe = (uint32_t)strtoul(v, nullptr, 10) ? 1 : 0;
+  if (const char* v = getenv("RL_BATCH_FANOUT")) {
+    const uint32_t f = (uint32_t)strtoul(v, nullptr, 10);
+    c.fanout = f == 0 ? 0 : f >= 128 ? 128 : 64;
+  }
   if (c.threads < 64 || c.threads > kDenseMaxThreads || c.threads % 64) c.threads = 128;
   if (c.gather_threads < 64 || c.gather_threads > 256 || c.gather_threads % 64) c.gather_threads = kGatherThreads;
 
@@ -640,7 +742,9 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
 
 extern "C" rl_status rl_batch_launch(rl_batch* b, void* stream) {
   if (!b || !b->finalized) return fail(RL_EINVAL, "batch not finalized");
-  if (!b->dev.t.dense_tiles && !b->dev.t.gather_tiles && !b->dev.t.n_totals && !b->dev.t.rebase_tiles) return RL_OK;
+  if (!b->dev.t.dense_tiles && !b->dev.t.fan_tiles && !b->dev.t.gather_tiles && !b->dev.t.n_totals &&
+      !b->dev.t.rebase_tiles)
+    return RL_OK;
   if (b->cfg.direct) return launch_tables(b->dev, b->cfg, (hipStream_t)stream);
   hipGraphExec_t x = nullptr;
   if (rl_status st = graph_for(b, (hipStream_t)stream, &x)) return st;
@@ -670,6 +774,16 @@ extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t*
                                     uint32_t* graph_replay) {
   if (!b) return fail(RL_EINVAL, "batch is NULL");
   if (tile) *tile = b->cfg.tile;
+  if (!b->dev.t.dense_tiles && b->dev.t.fan_tiles) {
+    // every dense step is in a fan-out group: the fan-out kernel's launch
+    if (threads) *threads = b->dev.fan_threads;
+    if (grid) {
+      const uint32_t r = fanout_resident_blocks(b->dev.fan_threads, b->dev.fan_lds);
+      *grid = std::min<uint32_t>(b->cfg.grid ? b->cfg.grid : (r ? r : 2048), b->dev.t.fan_tiles);
+    }
+    if (graph_replay) *graph_replay = b->cfg.direct ? 0 : 1;
+    return RL_OK;
+  }
   if (threads) *threads = b->cfg.threads;
   if (grid) {
     // dense work-groups as launched: the configured count or as many as fit
@@ -680,6 +794,18 @@ extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t*
     *grid = std::min<uint32_t>(g, std::max(1u, b->dev.t.dense_tiles));
   }
   if (graph_replay) *graph_replay = b->cfg.direct ? 0 : 1;
+  return RL_OK;
+}
+
+extern "C" rl_status rl_batch_get_info(const rl_batch* b, rl_batch_info* info) {
+  if (!b || !info) return fail(RL_EINVAL, "NULL argument");
+  if (!b->finalized) return fail(RL_EINVAL, "batch not finalized");
+  *info = rl_batch_info{};
+  info->double_buffered = b->dev.t.pipe_slot != 0;
+  info->fanout_threads = b->dev.t.fan_tiles ? b->dev.t.fan_per : 0;
+  info->fanout_groups = b->dev.fan_groups;
+  info->fanout_steps = b->dev.fan_steps;
+  info->dense_steps = b->dev.dense_steps;
   return RL_OK;
 }
 

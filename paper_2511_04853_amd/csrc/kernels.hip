@@ -792,8 +792,7 @@ __device__ __forceinline__ void transform_kinds(const DD& d, const DenseLds& m, 
 // stores coalesce without a destination image.
 template <class DD>
 __device__ __forceinline__ void transform_direct(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
-                                                 uint32_t cnt, uint32_t nt) {
-  const uint32_t tx = threadIdx.x;
+                                                 uint32_t cnt, uint32_t nt, uint32_t tx = threadIdx.x) {
   switch (d.src.kind * 3 + d.dst.kind) {
     case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true>(d, m, lt, i0, cnt, tx, nt); break;
     case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, m, lt, i0, cnt, tx, nt); break;
@@ -2116,6 +2115,47 @@ __global__ void __launch_bounds__(256, 4) batch_dense_db_kernel(const BatchTable
                     [&](uint32_t item) -> const RL_C DenseDesc& { return cdesc(b.dense, item); }, b.status);
 }
 
+// Fan-out groups (steps converting the same source tiles, their counts
+// known on the host, direct destinations): a work-group brings a source
+// tile into LDS once, and its thread groups of b.fan_per threads convert
+// it, group k into step k's destination.  Each wave holds its own step's
+// leaf lanes; the source fields of a group's steps are identical, so any
+// wave's lanes serve the shared DMA.
+__global__ void __launch_bounds__(512) batch_fanout_kernel(const BatchTables b) {
+  extern __shared__ uint4 smem_raw[];
+  uint8_t* const smem = reinterpret_cast<uint8_t*>(smem_raw);
+  // 16-bit implicit arguments, read once
+  const uint32_t nt = blockDim.x, g = gridDim.x;
+  const uint32_t per = b.fan_per;
+  const uint32_t sub = __builtin_amdgcn_readfirstlane(threadIdx.x / per);
+  const uint32_t tx = threadIdx.x - sub * per;
+  LeafLanes lt;
+  lt.item = ~0u;
+  // a tile's group is found by walking the group ranges with scalar loads
+  // (a vector load of a tile map would wait behind this wave's stores)
+  uint32_t grp = 0;
+  for (uint32_t u = blockIdx.x; u < b.fan_tiles; u += g) {
+    while (u >= cdesc(b.fan, grp).end) ++grp;
+    const RL_C FanGroup& fg = cdesc(b.fan, grp);
+    const uint64_t tile = u - fg.first;
+    const uint32_t nd = fg.n_dst, s0 = fg.step[0];
+    const uint32_t mine = sub < nd ? fg.step[sub] : s0;
+    const bool fresh = mine != lt.item;
+    if (fresh) load_lanes(cdesc(b.dense, mine), mine, lt);
+    const RL_C DenseDesc& d0 = cdesc(b.dense, s0);
+    issue_source(d0, smem, TileJob{1, s0, tile, d0.n, 0}, lt, !fresh, nt);
+    dma_wait();
+    __syncthreads();
+    if (sub < nd) {
+      const RL_C DenseDesc& d = cdesc(b.dense, mine);
+      const uint64_t i0 = tile * d.tile;
+      transform_direct(d, carve(smem, d), lt, i0, (uint32_t)min<uint64_t>(d.tile, d.n - i0), per, tx);
+    }
+    // the next tile's DMA overwrites the image
+    __syncthreads();
+  }
+}
+
 // Tile-total scans (one work-group each) and offsets rebases.
 __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   __shared__ uint64_t wsum[17];
@@ -2187,6 +2227,10 @@ uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined) {
                                    : reinterpret_cast<const void*>(batch_dense_kernel), threads, lds);
 }
 
+uint32_t fanout_resident_blocks(uint32_t threads, uint32_t lds) {
+  return resident_blocks(reinterpret_cast<const void*>(batch_fanout_kernel), threads, lds);
+}
+
 hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid, hipStream_t s) {
   if (threads == 0 || threads > kDenseMaxThreads || threads % 64) return hipErrorInvalidValue;
   if (d.pipe_slot && d.pipe_slot < dense_lds_bytes(d)) return hipErrorInvalidValue;
@@ -2229,9 +2273,14 @@ hipError_t launch_rebase(const RebaseDesc& d, hipStream_t s) {
 }
 
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
-                        uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s) {
+                        uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s,
+                        uint32_t fan_threads, uint32_t fan_lds) {
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
   if (gather_threads == 0 || gather_threads > 256 || gather_threads % 64) return hipErrorInvalidValue;
+  if (b.fan_tiles && (b.fan_per == 0 || b.fan_per % 64 || fan_threads % b.fan_per || fan_threads == 0 ||
+                      fan_threads > kFanMaxThreads))
+    return hipErrorInvalidValue;
+  const uint32_t grid_req = grid;
   const uint32_t dense_grid = std::min<uint32_t>(
       grid ? grid : std::max<uint32_t>(1, batch_resident_blocks(dense_threads, dense_lds, b.pipe_slot != 0)),
       std::max(1u, b.dense_tiles));
@@ -2244,6 +2293,13 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
     }
     if (b.pipe_slot) hipLaunchKernelGGL(batch_dense_db_kernel, dim3(dense_grid), dim3(dense_threads), dense_lds, s, b);
     else hipLaunchKernelGGL(batch_dense_kernel, dim3(dense_grid), dim3(dense_threads), dense_lds, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.fan_tiles) {
+    const uint32_t fres = fanout_resident_blocks(fan_threads, fan_lds);
+    const uint32_t fgrid = std::min<uint32_t>(b.fan_tiles, grid_req ? grid_req : (fres ? fres : 2048));
+    hipLaunchKernelGGL(batch_fanout_kernel, dim3(fgrid), dim3(fan_threads), fan_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -284,6 +284,18 @@ struct AppendDesc {
 
 // Device-resident tables of a batch: every step of every item, grouped by
 // the kernel that runs it.  Prefix arrays have one entry per item plus one.
+// A fan-out group of a batch: dense steps that read the same source tiles
+// (one source converted into several layouts).  One work-group converts a
+// tile of the source for all of them: the tile is read into LDS once and
+// thread group k (fan_per threads) stores destination k.
+constexpr uint32_t kFanMax = 4;
+constexpr uint32_t kFanMaxThreads = 512;
+struct FanGroup {
+  uint32_t n_dst;              // steps in the group (2 .. kFanMax)
+  uint32_t step[kFanMax];      // their dense step indices
+  uint32_t first, end;         // the group's tiles in the fan-out tile space
+};
+
 struct BatchTables {
   const DenseDesc* dense;
   const uint64_t* dense_prefix;     // first tile of each dense step
@@ -305,6 +317,9 @@ struct BatchTables {
   const uint32_t* rebase_item;      // rebase tile -> rebase step
   uint32_t rebase_tiles;
   uint32_t pipe_slot;               // dense steps: LDS bytes of each of two tile slots; 0: one slot
+  const FanGroup* fan;              // fan-out groups (their steps are not in dense_map)
+  uint32_t fan_tiles;               // tiles of all fan-out groups
+  uint32_t fan_per;                 // threads per destination of a fan-out group (a multiple of 64)
   uint32_t* status;                 // status word of the launching stream
 };
 constexpr uint32_t kRebaseTile = 8192;   // offsets entries per rebase work-group
@@ -335,7 +350,8 @@ hipError_t launch_zero_bytes(void* p, uint64_t bytes, hipStream_t s);
 // Device address of the status words of the current device.
 hipError_t status_words(uint32_t** out);
 hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t gather_threads,
-                        uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s);
+                        uint32_t grid, uint32_t dense_lds, uint32_t gather_lds, hipStream_t s,
+                        uint32_t fan_threads = 0, uint32_t fan_lds = 0);
 // Members per pass of the packed-word gather (LDS staging per word).
 constexpr uint32_t kGatherStage = 1024;
 // LDS of a gather work-group: staged objects, then the word columns.
@@ -349,6 +365,8 @@ uint32_t dense_lds_bytes(const DenseDesc& d);
 // Work-groups of the batch dense kernel that fit on the current device at
 // once for this block size and LDS size (0 if unknown).
 uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined);
+// Fan-out work-groups of a batch that fit on the device at once; 0 if unknown.
+uint32_t fanout_resident_blocks(uint32_t threads, uint32_t lds);
 uint64_t dense_tiles(const DenseDesc& d);
 
 // ---- errors ----

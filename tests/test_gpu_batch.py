@@ -58,6 +58,11 @@ class Batch:
         P.check(P.lib().rl_batch_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), None), "shape")
         return a.value, b.value, c.value
 
+    def info(self):
+        i = P.rl_batch_info()
+        P.check(P.lib().rl_batch_get_info(self.h, ctypes.byref(i)), "rl_batch_get_info")
+        return i
+
     def __del__(self):
         if getattr(self, "h", None):
             P.lib().rl_batch_destroy(self.h)
