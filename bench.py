@@ -135,7 +135,7 @@ def main():
     shape = sets[0][2].shape()
     binfo = sets[0][2].info()
     fanned = binfo.fanout_steps == binfo.dense_steps and binfo.fanout_groups > 0
-    step_kernel = ("rl::batch_fanout_kernel" if fanned else
+    step_kernel = (("rl::batch_fanout_db_kernel" if binfo.double_buffered else "rl::batch_fanout_kernel") if fanned else
                    "rl::batch_dense_db_kernel" if binfo.double_buffered else "rl::batch_dense_kernel")
 
     src_bytes = aos.buffer_bytes(n)[0]

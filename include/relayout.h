@@ -561,7 +561,8 @@ rl_status rl_batch_shape(const rl_batch* batch, uint32_t* tile_objects,
    to four: one work-group per source tile reads the tile into LDS once and
    a thread group per step stores that step's destination. */
 typedef struct rl_batch_info {
-  uint32_t double_buffered;   /* 1: dense steps run with two tile slots per work-group */
+  uint32_t double_buffered;   /* 1: dense steps (fan-out groups included) run with two
+                                 tile slots per work-group */
   uint32_t fanout_threads;    /* threads per destination in fan-out groups; 0: no fan-out */
   uint32_t fanout_groups;     /* fan-out groups formed */
   uint32_t fanout_steps;      /* dense steps inside them */

@@ -332,6 +332,14 @@ rl_status build_tables(rl_batch* b, const Config& c, DeviceTables* out) {
   t.fan_per = c.fanout;
   out->fan_threads = fan_threads;
   out->fan_lds = fan_lds;
+  t.fan_slot = 0;
+  if (c.pipe && fan_tiles) {
+    const uint32_t fslot = (fan_lds + 15u) & ~15u;
+    if (2 * fslot <= 64 * 1024) {
+      t.fan_slot = fslot;
+      out->fan_lds = 2 * fslot;
+    }
+  }
   out->fan_groups = (uint32_t)fans.size();
   out->fan_steps = (uint32_t)(dense.size() - singles.size());
   out->dense_steps = (uint32_t)dense.size();
@@ -447,8 +455,20 @@ void cache_store(const std::string& path, const std::string& sig, const Config& 
   rename((path + ".tmp").c_str(), path.c_str());
 }
 
-// Time one configuration (direct launches of the batch kernels).
-rl_status time_config(rl_batch* b, const Config& c, hipStream_t s, double* us) {
+// Device memory the tuner copies through between timed launches.
+struct FlushBuffer {
+  void* mem = nullptr;
+  uint64_t bytes = 0;
+};
+constexpr uint64_t kFlushBytes = 512ull << 20;   // twice the 256 MB Infinity Cache
+
+// Time one configuration (direct launches of the batch kernels).  A batch
+// whose launch takes under 100 us is timed cold, as it runs over data it
+// has not just touched: before each of 16 timed launches a copy through
+// the flush buffer evicts L2 and the Infinity Cache, and each launch is
+// timed alone.  Longer batches are timed back to back (their own
+// footprint evicts the caches).
+rl_status time_config(rl_batch* b, const Config& c, hipStream_t s, const FlushBuffer& flush, double* us) {
   rl_status st = resolve_widths(b, c.width);
   if (!st) st = plan_all(b, c);
   DeviceTables d;
@@ -458,14 +478,37 @@ rl_status time_config(rl_batch* b, const Config& c, hipStream_t s, double* us) {
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   for (int k = 0; k < 2 && !st; ++k) st = launch_tables(d, c, s);
-  const int reps = 5;
+  int reps = 5;
+  float ms = 0;
   (void)hipEventRecord(e0, s);
   for (int k = 0; k < reps && !st; ++k) st = launch_tables(d, c, s);
   (void)hipEventRecord(e1, s);
   hipError_t e = hipEventSynchronize(e1);
-  float ms = 0;
   if (!st && e != hipSuccess) st = hip_fail(e, "tuning run");
   if (!st) (void)hipEventElapsedTime(&ms, e0, e1);
+  if (!st && flush.mem && ms < 0.1f * reps) {
+    constexpr int kCold = 16;
+    hipEvent_t ev[2 * kCold];
+    for (hipEvent_t& x : ev) (void)hipEventCreate(&x);
+    const uint64_t half = flush.bytes / 2;
+    for (int k = 0; k < kCold && !st; ++k) {
+      hipError_t fe = launch_copy(static_cast<uint8_t*>(flush.mem) + half, flush.mem, half, s);
+      if (fe != hipSuccess) st = hip_fail(fe, "tuning flush");
+      (void)hipEventRecord(ev[2 * k], s);
+      if (!st) st = launch_tables(d, c, s);
+      (void)hipEventRecord(ev[2 * k + 1], s);
+    }
+    e = hipEventSynchronize(ev[2 * kCold - 1]);
+    if (!st && e != hipSuccess) st = hip_fail(e, "tuning run");
+    ms = 0;
+    for (int k = 0; k < kCold && !st; ++k) {
+      float one = 0;
+      (void)hipEventElapsedTime(&one, ev[2 * k], ev[2 * k + 1]);
+      ms += one;
+    }
+    reps = kCold;
+    for (hipEvent_t& x : ev) (void)hipEventDestroy(x);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(s);
@@ -487,9 +530,27 @@ static bool has_fanout(const rl_batch* b) {
 }
 
 rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
+  FlushBuffer flush;
+  if (hipMalloc(&flush.mem, kFlushBytes) == hipSuccess) {
+    flush.bytes = kFlushBytes;
+  } else {
+    flush.mem = nullptr;   // timed warm: still a valid comparison
+    (void)hipGetLastError();
+  }
+  struct Free {
+    FlushBuffer& f;
+    hipStream_t s;
+    ~Free() {
+      if (f.mem) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(f.mem);
+      }
+    }
+  } free_flush{flush, s};
   const bool any_auto = std::any_of(b->items.begin(), b->items.end(), [](const Item& i) { return i.auto_width(); });
   double best_us = 1e30;
   Config bc;
+  std::vector<std::pair<double, Config>> seen;   // every shape candidate timed
   for (uint32_t tile : {64u, 128u, 256u, 512u, 1024u})
     for (uint32_t threads : {64u, 128u, 256u})
       // 0: as many work-groups as fit at once (persistent); kOnePerTile: one
@@ -506,8 +567,9 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
           c.width = 64;
           c.pipe = pipe;
           double us;
-          rl_status st = time_config(b, c, s, &us);
+          rl_status st = time_config(b, c, s, flush, &us);
           if (st) return st;
+          seen.emplace_back(us, c);
           if (us < best_us) { best_us = us; bc = c; }
         }
   // member gathers: one-wave work-groups keep more sub-tiles in flight,
@@ -517,7 +579,7 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
       Config c = bc;
       c.gather_threads = gt;
       double us;
-      rl_status st = time_config(b, c, s, &us);
+      rl_status st = time_config(b, c, s, flush, &us);
       if (st) return st;
       if (us < best_us * 0.98) { best_us = us; bc = c; }
     }
@@ -525,23 +587,52 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
   if (has_fanout(b)) {
     const Config base = bc;
     for (uint32_t tile : {64u, 128u, 256u, 512u})
-      for (uint32_t per : {64u, 128u}) {
-        Config c = base;
-        c.tile = tile;
-        c.fanout = per;
-        c.pipe = 0;
-        double us;
-        rl_status st = time_config(b, c, s, &us);
-        if (st) return st;
-        if (us < best_us * 0.98) { best_us = us; bc = c; }
+      for (uint32_t per : {64u, 128u})
+        // double-buffered: work-groups that convert two or more tiles each
+        for (uint32_t pipe : {0u, 1u})
+          for (uint32_t grid : {0u, 256u, 512u}) {
+            if (!pipe && grid) continue;
+            Config c = base;
+            c.tile = tile;
+            c.fanout = per;
+            c.pipe = pipe;
+            c.grid = grid;
+            double us;
+            rl_status st = time_config(b, c, s, flush, &us);
+            if (st) return st;
+            seen.emplace_back(us, c);
+            if (us < best_us * 0.98) { best_us = us; bc = c; }
+          }
+  }
+  // the three fastest shapes timed twice more, interleaved: single timings
+  // of shapes within a few percent of each other order them at random
+  {
+    std::sort(seen.begin(), seen.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    const size_t top = std::min<size_t>(3, seen.size());
+    if (top > 1) {
+      std::vector<double> sum(top);
+      for (size_t i = 0; i < top; ++i) {
+        seen[i].second.gather_threads = bc.gather_threads;
+        sum[i] = seen[i].first;
       }
+      for (int round = 0; round < 2; ++round)
+        for (size_t i = 0; i < top; ++i) {
+          double us;
+          rl_status st = time_config(b, seen[i].second, s, flush, &us);
+          if (st) return st;
+          sum[i] += us;
+        }
+      const size_t k = std::min_element(sum.begin(), sum.end()) - sum.begin();
+      bc = seen[k].second;
+      best_us = sum[k] / 3;
+    }
   }
   if (any_auto)
     for (uint32_t w : kAutoWidths) {
       Config c = bc;
       c.width = w;
       double us;
-      rl_status st = time_config(b, c, s, &us);
+      rl_status st = time_config(b, c, s, flush, &us);
       if (st) return st;
       if (us < best_us * 0.98) { best_us = us; bc = c; }
     }
@@ -778,7 +869,7 @@ extern "C" rl_status rl_batch_shape(const rl_batch* b, uint32_t* tile, uint32_t*
     // every dense step is in a fan-out group: the fan-out kernel's launch
     if (threads) *threads = b->dev.fan_threads;
     if (grid) {
-      const uint32_t r = fanout_resident_blocks(b->dev.fan_threads, b->dev.fan_lds);
+      const uint32_t r = fanout_resident_blocks(b->dev.fan_threads, b->dev.fan_lds, b->dev.t.fan_slot != 0);
       *grid = std::min<uint32_t>(b->cfg.grid ? b->cfg.grid : (r ? r : 2048), b->dev.t.fan_tiles);
     }
     if (graph_replay) *graph_replay = b->cfg.direct ? 0 : 1;
@@ -801,7 +892,7 @@ extern "C" rl_status rl_batch_get_info(const rl_batch* b, rl_batch_info* info) {
   if (!b || !info) return fail(RL_EINVAL, "NULL argument");
   if (!b->finalized) return fail(RL_EINVAL, "batch not finalized");
   *info = rl_batch_info{};
-  info->double_buffered = b->dev.t.pipe_slot != 0;
+  info->double_buffered = b->dev.t.pipe_slot != 0 || b->dev.t.fan_slot != 0;
   info->fanout_threads = b->dev.t.fan_tiles ? b->dev.t.fan_per : 0;
   info->fanout_groups = b->dev.fan_groups;
   info->fanout_steps = b->dev.fan_steps;

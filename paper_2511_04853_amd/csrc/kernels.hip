@@ -2156,6 +2156,82 @@ __global__ void __launch_bounds__(512) batch_fanout_kernel(const BatchTables b) 
   }
 }
 
+// A fan-out tile: its group, the tile within the group's source, and the
+// step this thread group converts (the group's first step for thread
+// groups beyond its steps, which only help with the DMA).
+struct FanJob {
+  uint32_t valid, step, s0, nd;
+  uint64_t tile;
+};
+
+// Job of fan-out tile u; grp walks forward over the group ranges (u only
+// grows within a work-group).
+__device__ __forceinline__ FanJob fan_job(const BatchTables& b, uint32_t u, uint32_t& grp, uint32_t sub) {
+  FanJob j{0, 0, 0, 0, 0};
+  if (u >= b.fan_tiles) return j;
+  while (u >= cdesc(b.fan, grp).end) ++grp;
+  const RL_C FanGroup& fg = cdesc(b.fan, grp);
+  j.valid = 1;
+  j.nd = fg.n_dst;
+  j.s0 = fg.step[0];
+  j.step = sub < j.nd ? fg.step[sub] : j.s0;
+  j.tile = u - fg.first;
+  return j;
+}
+
+// The fan-out tiles double-buffered: two LDS slots of b.fan_slot bytes;
+// the next tile's source DMA is issued before the current tile's
+// transform, and the wait at the top of the next tile lets this wave's
+// stores of the current tile stay in flight (the counter retires in
+// order: with at most `after` operations outstanding, `after` a lower
+// bound of the stores issued after that DMA, the DMA is done).
+__global__ void __launch_bounds__(512) batch_fanout_db_kernel(const BatchTables b) {
+  extern __shared__ uint4 smem_raw[];
+  uint8_t* cs = reinterpret_cast<uint8_t*>(smem_raw);
+  uint8_t* ns = cs + b.fan_slot;
+  const uint32_t nt = blockDim.x, g = gridDim.x;
+  const uint32_t per = b.fan_per;
+  const uint32_t sub = __builtin_amdgcn_readfirstlane(threadIdx.x / per);
+  const uint32_t tx = threadIdx.x - sub * per;
+  uint32_t grp = 0, u = blockIdx.x;
+  FanJob cur = fan_job(b, u, grp, sub);
+  if (!cur.valid) return;
+  LeafLanes lc, ln;
+  load_lanes_scalar(cdesc(b.dense, cur.step), cur.step, lc);
+  {
+    const RL_C DenseDesc& d0 = cdesc(b.dense, cur.s0);
+    issue_source(d0, cs, TileJob{1, cur.s0, cur.tile, d0.n, 0}, lc, false, nt);
+  }
+  uint32_t after = 0;
+  while (true) {
+    vm_wait_at_most(after);
+    __syncthreads();
+    // every wave is past the previous tile, whose slot the next DMA reuses
+    u += g;
+    const FanJob nxt = fan_job(b, u, grp, sub);
+    if (nxt.valid) {
+      if (nxt.step == lc.item) ln = lc;
+      else load_lanes_scalar(cdesc(b.dense, nxt.step), nxt.step, ln);
+      const RL_C DenseDesc& d0 = cdesc(b.dense, nxt.s0);
+      issue_source(d0, ns, TileJob{1, nxt.s0, nxt.tile, d0.n, 0}, lc, false, nt);
+    }
+    after = 0;
+    if (sub < cur.nd) {
+      const RL_C DenseDesc& d = cdesc(b.dense, cur.step);
+      const uint64_t i0 = cur.tile * d.tile;
+      const uint32_t cnt = (uint32_t)min<uint64_t>(d.tile, d.n - i0);
+      transform_direct(d, carve(cs, d), lc, i0, cnt, per, tx);
+      after = stores_at_least(d, cnt, per);
+    }
+    if (!nxt.valid) break;
+    cur = nxt;
+    lc = ln;
+    uint8_t* const t = cs;
+    cs = ns;
+    ns = t;
+  }
+}
+
 // Tile-total scans (one work-group each) and offsets rebases.
 __global__ void __launch_bounds__(1024) batch_misc_kernel(const BatchTables b) {
   __shared__ uint64_t wsum[17];
@@ -2227,8 +2303,9 @@ uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined) {
                                    : reinterpret_cast<const void*>(batch_dense_kernel), threads, lds);
 }
 
-uint32_t fanout_resident_blocks(uint32_t threads, uint32_t lds) {
-  return resident_blocks(reinterpret_cast<const void*>(batch_fanout_kernel), threads, lds);
+uint32_t fanout_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined) {
+  return resident_blocks(pipelined ? reinterpret_cast<const void*>(batch_fanout_db_kernel)
+                                   : reinterpret_cast<const void*>(batch_fanout_kernel), threads, lds);
 }
 
 hipError_t launch_dense(const DenseDesc& d, uint32_t threads, uint32_t grid, hipStream_t s) {
@@ -2278,7 +2355,7 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
   if (dense_threads == 0 || dense_threads > kDenseMaxThreads || dense_threads % 64) return hipErrorInvalidValue;
   if (gather_threads == 0 || gather_threads > 256 || gather_threads % 64) return hipErrorInvalidValue;
   if (b.fan_tiles && (b.fan_per == 0 || b.fan_per % 64 || fan_threads % b.fan_per || fan_threads == 0 ||
-                      fan_threads > kFanMaxThreads))
+                      fan_threads > kFanMaxThreads || (b.fan_slot && (b.fan_slot % 16 || fan_lds < 2 * b.fan_slot))))
     return hipErrorInvalidValue;
   const uint32_t grid_req = grid;
   const uint32_t dense_grid = std::min<uint32_t>(
@@ -2297,9 +2374,10 @@ hipError_t launch_batch(const BatchTables& b, uint32_t dense_threads, uint32_t g
     if (e != hipSuccess) return e;
   }
   if (b.fan_tiles) {
-    const uint32_t fres = fanout_resident_blocks(fan_threads, fan_lds);
+    const uint32_t fres = fanout_resident_blocks(fan_threads, fan_lds, b.fan_slot != 0);
     const uint32_t fgrid = std::min<uint32_t>(b.fan_tiles, grid_req ? grid_req : (fres ? fres : 2048));
-    hipLaunchKernelGGL(batch_fanout_kernel, dim3(fgrid), dim3(fan_threads), fan_lds, s, b);
+    if (b.fan_slot) hipLaunchKernelGGL(batch_fanout_db_kernel, dim3(fgrid), dim3(fan_threads), fan_lds, s, b);
+    else hipLaunchKernelGGL(batch_fanout_kernel, dim3(fgrid), dim3(fan_threads), fan_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -320,6 +320,7 @@ struct BatchTables {
   const FanGroup* fan;              // fan-out groups (their steps are not in dense_map)
   uint32_t fan_tiles;               // tiles of all fan-out groups
   uint32_t fan_per;                 // threads per destination of a fan-out group (a multiple of 64)
+  uint32_t fan_slot;                // fan-out tiles: LDS bytes of each of two tile slots; 0: one slot
   uint32_t* status;                 // status word of the launching stream
 };
 constexpr uint32_t kRebaseTile = 8192;   // offsets entries per rebase work-group
@@ -366,7 +367,7 @@ uint32_t dense_lds_bytes(const DenseDesc& d);
 // once for this block size and LDS size (0 if unknown).
 uint32_t batch_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined);
 // Fan-out work-groups of a batch that fit on the device at once; 0 if unknown.
-uint32_t fanout_resident_blocks(uint32_t threads, uint32_t lds);
+uint32_t fanout_resident_blocks(uint32_t threads, uint32_t lds, bool pipelined);
 uint64_t dense_tiles(const DenseDesc& d);
 
 // ---- errors ----

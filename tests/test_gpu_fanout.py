@@ -68,15 +68,28 @@ def test_fanout_one_source_into_several_layouts(src, per, monkeypatch):
     _run(_shared_source_items(src, 30_001), per)
 
 
+@pytest.mark.parametrize("pipe", [0, 1], ids=["one_slot", "double_buffered"])
 @pytest.mark.parametrize("tile,grid", [(64, 3), (128, 0), (512, 11), (1024, 1)])
-def test_fanout_tiles_and_grids(tile, grid, monkeypatch):
+def test_fanout_tiles_and_grids(tile, grid, pipe, monkeypatch):
     """Small grids: work-groups step through the tiles of several groups
-    (the group is found by walking the group ranges)."""
+    (the group is found by walking the group ranges); double-buffered, the
+    next tile's DMA overlaps the current tile's stores."""
     monkeypatch.setenv("RL_BATCH_FANOUT", "64")
     monkeypatch.setenv("RL_BATCH_TILE", str(tile))
+    monkeypatch.setenv("RL_BATCH_PIPE", str(pipe))
     if grid:
         monkeypatch.setenv("RL_BATCH_GRID", str(grid))
-    _run(_shared_source_items("aos", 5_003), 64)
+    b = _run(_shared_source_items("aos", 5_003), 64)
+    # two slots of 1,024 cell records (33 KB each) exceed 64 KB: one slot
+    assert b.info().double_buffered == (pipe if tile <= 512 else 0)
+
+
+@pytest.mark.parametrize("src", ["soa", "aosoa"])
+def test_fanout_double_buffered_other_sources(src, monkeypatch):
+    monkeypatch.setenv("RL_BATCH_FANOUT", "128")
+    monkeypatch.setenv("RL_BATCH_PIPE", "1")
+    monkeypatch.setenv("RL_BATCH_GRID", "5")
+    _run(_shared_source_items(src, 20_011), 128)
 
 
 def test_fanout_partial_and_single_tiles(monkeypatch):
@@ -87,11 +100,15 @@ def test_fanout_partial_and_single_tiles(monkeypatch):
         _run(_shared_source_items("aos", n), 128)
 
 
+@pytest.mark.parametrize("pipe", [0, 1], ids=["one_slot", "double_buffered"])
 @pytest.mark.parametrize("per", [64, 128])
-def test_fanout_groups_alone(per, monkeypatch):
+def test_fanout_groups_alone(per, pipe, monkeypatch):
     """A batch whose dense steps all sit in fan-out groups (no other dense
     tile, no gather): one source converted into four direct layouts."""
     monkeypatch.setenv("RL_BATCH_FANOUT", str(per))
+    monkeypatch.setenv("RL_BATCH_PIPE", str(pipe))
+    if pipe:
+        monkeypatch.setenv("RL_BATCH_GRID", "64")
     schemas = {k: H.SchemaPair(d) for k, d in DECLS.items()}
     base = Item(schemas, dict(schema="cell", n=40_009, src="aos", dst="soa"))
     narrow = H.narrowed_storage(DECLS["cell"])
