@@ -141,6 +141,7 @@ def main():
     src_bytes = aos.buffer_bytes(n)[0]
     conv_bytes = [src_bytes + sum(L.buffer_bytes(n)) for L in dsts]
     step_bytes = sum(conv_bytes)
+    min_bytes = src_bytes + sum(sum(L.buffer_bytes(n)) for L in dsts)
 
     def run(k, loop=False):
         b = sets[k % len(sets)][2]
@@ -228,6 +229,10 @@ def main():
             "mean_launch_us": round(mean_launch_ms * 1e3, 3),
             "isolated_launch_us": iso,
             "bytes_per_launch": int(step_bytes),
+            # the least any kernel must move for the step: the shared source
+            # read once and the four destinations written
+            "bytes_min_per_launch": int(min_bytes),
+            "frac_min_bytes": round(min_bytes / (mean_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
         "step_launch_loop": {"ms_per_step": round(ms_loop, 5),
                              "GBps": round(step_bytes / (ms_loop * 1e-3) / 1e9, 2),
@@ -396,7 +401,7 @@ def measured_traffic(kernel, n):
     FETCH_SIZE / WRITE_SIZE counter summary, scaled by the same counters on
     a plain copy of known size; None when the kernel source changed since
     the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_batch_dense_kernel_cell190k_step.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel.split('::')[-1]}_cell190k_step.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
