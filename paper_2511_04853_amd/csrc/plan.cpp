@@ -78,8 +78,11 @@ uint32_t choose_tile(const SideSpec& s, const SideSpec& d, uint32_t target, uint
   const uint32_t scale = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(16, 32 / per));
   if (!target) {
     // long column runs favour large tiles; small collections need enough
-    // tiles to spread over the 256 compute units
-    target = kDefaultTile * scale;
+    // tiles to spread over the 256 compute units.  Records written from an
+    // LDS image of columns or blocks take half the tile: the two images
+    // then fit twice as many work-groups (SoA -> AoS at 2^22 - 2^24
+    // objects: 3-7% faster, AoSoA -> AoS about even)
+    target = (d.kind == KIND_AOS && s.kind != KIND_AOS ? kDefaultTile / 2 : kDefaultTile) * scale;
     while (target > 128 && n && (n + target - 1) / target < 1024) target /= 2;
   } else {
     target *= scale;
@@ -228,9 +231,14 @@ static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& sha
   // work-groups, which pays where each holds many tiles (measured: cell
   // and plain AoS -> SoA at 2^24 - 2^25 objects, 2-4% faster; at 2^20 -
   // 2^22 objects and for the step of four 190,000-object conversions,
-  // slower)
+  // slower), and only where one source run per tile comes in and the
+  // values go straight out: with a column run per leaf to bring in, or a
+  // destination image to write out, it lost at 2^24 objects (SoA -> AoS
+  // 2.2 against 3.3-3.9 TB/s, SoA -> AoSoA 3.9-4.5 against 5.0,
+  // AoSoA -> AoS 4.1 against 4.2-4.5)
   const uint32_t slot = (dense_lds_bytes(st.dense) + 15u) & ~15u;
-  const bool long_run = dense_tiles(st.dense) >= kPipeMinTiles;
+  const bool long_run = dense_tiles(st.dense) >= kPipeMinTiles && st.dense.dst_direct &&
+                        st.dense.src.kind != KIND_SOA;
   if (shape.pipe != 0 && (long_run || shape.pipe == 1) && 2 * slot <= kLdsBudget) st.dense.pipe_slot = slot;
   plan->steps.push_back(st);
   return RL_OK;
