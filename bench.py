@@ -1099,8 +1099,40 @@ def pipeline(P, W, torch, stream):
     return res
 
 
+def pairs(P, W, torch, stream, copies=4, n=1 << 24):
+    """Every ordered pair of layout kinds (AoS, SoA, AoSoA(64)) for the plain
+    and cell schemas at 2^24 objects, `copies` copies rotating (cold), each
+    against the copy kernel over the same bytes."""
+    res = {}
+    lib, sp = P.lib(), P.stream_ptr(stream)
+    kinds = (("aos", 0), ("soa", 0), ("aosoa", 64))
+    for sname, decl in (("plain8", W.PLAIN8), ("cell", W.CELL)):
+        S = P.Schema(decl)
+        for sk in kinds:
+            for dk in kinds:
+                if sk == dk:
+                    continue
+                sl, dl = P.Layout(S, sk[0], width=sk[1]), P.Layout(S, dk[0], width=dk[1])
+                views = []
+                for _ in range(copies):
+                    src = [torch.randint(0, 255, (b,), dtype=torch.uint8, device="cuda") for b in sl.buffer_bytes(n)]
+                    dst = [torch.empty(b, dtype=torch.uint8, device="cuda") for b in dl.buffer_bytes(n)]
+                    views.append((P.View(sl, n, src), P.View(dl, n, dst)))
+                nbytes = sum(sl.buffer_bytes(n)) + sum(dl.buffer_bytes(n))
+                ms = _time(lambda k=0: lib.rl_convert(views[k % copies][0].ref(), views[k % copies][1].ref(), n, sp),
+                           stream, torch, reps=12, warm=copies)
+                assert P.sync(stream) == 0, P.rl_last_error()
+                del views
+                torch.cuda.empty_cache()
+                gbs = nbytes / (ms * 1e-3) / 1e9
+                res[f"{sname}/{sk[0]}->{dk[0]}"] = {"us": round(ms * 1e3, 2), "GBps": round(gbs, 1),
+                                                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    return res
+
+
 LEGS = {
     "single_conversion": single_conversion,
+    "pairs": pairs,
     "copy_peak": copy_peak,
     "round_trip": lambda P, W, torch, stream: plain_round_trip(P, W, torch, stream),
     "jagged": jagged,
@@ -1117,7 +1149,7 @@ LEGS = {
     "sweep_cell_2_24": lambda P, W, torch, stream: sweep(P, W, torch, stream, schemas=("cell",), sizes=(1 << 24,),
                                                          jagged=False),
 }
-EXTRA_ORDER = ["single_conversion", "copy_peak", "round_trip", "jagged", "batched", "sweep", "h2d", "d2h",
+EXTRA_ORDER = ["single_conversion", "copy_peak", "round_trip", "jagged", "batched", "sweep", "pairs", "h2d", "d2h",
                "pipeline", "serving", "cpu_events"]
 
 
