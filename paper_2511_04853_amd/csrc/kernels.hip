@@ -1345,7 +1345,8 @@ struct JagLds {
   uint64_t* wsum;      // block scan: one u64 per wave + 1
   uint64_t* rsum;      // look-back sums, one per wave
   uint32_t* rmin;      // look-back minimum, one per wave
-  uint32_t* stage;     // member rows of NW words, stage of them (NW * (stage + 4) words reserved)
+  uint16_t* own;       // tile-local object of each member of a staging pass
+  uint32_t* stage;     // NW columns of (stage + 4) words
 };
 
 // LDS bytes before the staging columns: records, offsets, pointers,
@@ -1354,7 +1355,7 @@ template <class JD>
 __host__ __device__ __forceinline__ uint32_t jag_head_bytes(const JD& j) {
   const uint32_t T = j.dense.tile;
   return round16(j.dense.src.image_bytes) + round16((T + 1) * 8) + round16(T * 8) + round16(T * 4) +
-         round16(18 * 8) + round16(4 * 8) + round16(4 * 4);
+         round16(18 * 8) + round16(4 * 8) + round16(4 * 4) + round16(j.stage * 2);
 }
 
 template <class JD>
@@ -1374,6 +1375,7 @@ __device__ __forceinline__ JagLds jag_carve(uint8_t* smem, const JD& j) {
   m.wsum = reinterpret_cast<uint64_t*>(p); p += round16(18 * 8);
   m.rsum = reinterpret_cast<uint64_t*>(p); p += round16(4 * 8);
   m.rmin = reinterpret_cast<uint32_t*>(p); p += round16(4 * 4);
+  m.own = reinterpret_cast<uint16_t*>(p); p += round16(j.stage * 2);
   m.stage = reinterpret_cast<uint32_t*>(p);
   return m;
 }
@@ -1466,69 +1468,56 @@ __device__ uint64_t jag_look_back(const JD& j, const uint64_t* flags, uint64_t t
   return prefix;
 }
 
-__device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t l) {
-  return ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l) << 32) |
-         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
-}
-
-// DMA the members [lo, hi) of one object (tile-local member indices; the
-// object's first member is bi, its pool block at byte pi) into the LDS
-// columns of a staging pass that starts at member p0: the run is
-// contiguous in the pool and in each column, so a wave moves up to 64 of
-// its members per instruction and word (lane l: member lo + l).  All
-// arguments are wave-uniform.
-template <uint32_t NW>
-__device__ __forceinline__ void jag_issue_run(const uint8_t* pool, uint64_t pi, uint64_t bi, uint64_t lo, uint64_t hi,
-                                              uint64_t p0, uint32_t mstride, uint32_t col0, uint32_t cstride) {
-  const uint32_t lane = threadIdx.x & 63;
-  for (uint64_t k0 = lo; k0 < hi; k0 += 64) {
-    const bool ok = k0 + lane < hi;
-    const uint8_t* src = pool + pi + (k0 + lane - bi) * mstride;
-    const uint32_t slot = col0 + (uint32_t)(k0 - p0) * 4;
-#pragma unroll
-    for (uint32_t q = 0; q < NW; ++q)
-      if (ok) dma4(src + 4 * q, slot + q * cstride);
+// Owners (tile-local object index) of tile-local members [p0, p0 + pm)
+// into m.own[0 .. pm): each thread fills a contiguous run, finding the
+// owner of its first member by binary search over the tile-local offsets
+// and then stepping over object boundaries, so the work is spread by
+// members whatever the counts are.  All threads of the work-group take
+// part; a barrier must follow before m.own is read.
+__device__ __forceinline__ void jag_owners(const JagLds& m, uint32_t cnt, uint64_t p0, uint32_t pm) {
+  const uint32_t nt = blockDim.x;
+  const uint32_t R = (pm + nt - 1) / nt;
+  const uint32_t r0 = threadIdx.x * R, r1 = min(pm, r0 + R);
+  if (r0 >= r1) return;
+  const uint64_t k0 = p0 + r0;
+  uint32_t lo = 0, hi = cnt;   // last object whose first member is <= k0
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (m.loff[mid] <= k0) lo = mid; else hi = mid;
+  }
+  uint64_t next = m.loff[lo + 1];   // member k < total = loff[cnt], so lo + 1 <= cnt
+  for (uint32_t r = r0; r < r1; ++r) {
+    const uint64_t k = p0 + r;
+    while (k >= next) next = m.loff[++lo + 1];
+    m.own[r] = (uint16_t)lo;
   }
 }
 
-// LDS address of the staging columns and the byte distance between them.
-template <class JD>
-__device__ __forceinline__ void jag_columns(const JD& j, const JagLds& m, uint32_t* col0, uint32_t* cstride) {
-  *col0 = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr)(uint8_t*)m.stage);
-  *cstride = (j.stage + 4) * 4;
-}
-
-// DMA tile-local members [p0, p0 + pm) from the pool into the LDS columns
-// (slot k of a column holds member p0 + k), objects' offsets, pointers
-// and counts read from LDS: each wave takes every nw-th object, holding
-// the fields of 64 of them in its lanes, and moves each object's members
-// of the pass as one run.  Members outside their record's validated block
-// are not loaded (their destination entries are then unspecified and the
-// status says so).  Waves w0 .. w0 + nw - 1 of the work-group take part
-// (the calling wave must be one of them).
+// DMA the words of tile-local members [p0, p0 + pm) from the pool into the
+// LDS columns (slot k of a column holds member p0 + k); owners from m.own.
+// Members outside their record's validated block are not loaded (their
+// destination entries are then unspecified and the status says so).
+// Waves w0 .. w0 + nw - 1 of the work-group take part (the calling wave
+// must be one of them).
 template <uint32_t NW, class JD>
-__device__ __forceinline__ void jag_issue(const JD& j, const JagLds& m, uint32_t cnt, uint64_t p0, uint32_t pm,
+__device__ __forceinline__ void jag_issue(const JD& j, const JagLds& m, uint64_t p0, uint32_t pm,
                                           uint32_t w0, uint32_t nw) {
   const uint32_t lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) - w0;
-  const uint64_t pend = p0 + pm;
-  uint32_t col0, cstride;
-  jag_columns(j, m, &col0, &cstride);
-  for (uint32_t ob = wave; ob < cnt; ob += 64 * nw) {
-    const uint32_t o = ob + lane * nw;
-    uint64_t b = 0, e = 0, ptr = 0;
-    uint32_t vl = 0;
-    if (o < cnt) {
-      b = m.loff[o];
-      e = m.loff[o + 1];
-      ptr = m.ptrs[o];
-      vl = m.vlen[o];
+  for (uint32_t vb = wave * 64; vb < pm; vb += nw * 64) {
+    const uint32_t k = vb + lane;
+    bool ok = k < pm;
+    const uint8_t* src = j.pool;
+    if (ok) {
+      const uint32_t o = m.own[k];
+      const uint64_t jj = p0 + k - m.loff[o];
+      ok = jj < m.vlen[o];
+      src = j.pool + m.ptrs[o] + jj * j.mstride;
     }
-    const uint32_t nobj = min(64u, (cnt - ob + nw - 1) / nw);
-    for (uint32_t i = 0; i < nobj; ++i) {
-      const uint64_t bi = lane_u64(b, i);
-      const uint64_t hi = min(min(lane_u64(e, i), pend), bi + (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)i));
-      const uint64_t lo = max(bi, p0);
-      if (lo < hi) jag_issue_run<NW>(j.pool, lane_u64(ptr, i), bi, lo, hi, p0, j.mstride, col0, cstride);
+#pragma unroll
+    for (uint32_t q = 0; q < NW; ++q) {
+      uint32_t* col = m.stage + q * (j.stage + 4) + vb;
+      const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr)(uint8_t*)col);
+      if (ok) dma4(src + 4 * q, base);
     }
   }
 }
@@ -1576,10 +1565,11 @@ __global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
   if (i0 >= n) return;   // uniform
   const uint32_t cnt = (uint32_t)min<uint64_t>(T, n - i0);
   const uint32_t epoch = j.epoch;
-  // 1. records (an AoS source: its DMA needs no leaf lanes, which are
-  // loaded while it is in flight)
+  // 1. records (the leaf lanes are loaded first: issued after the DMA,
+  // their wait would also wait for it, which cost 10% at 2^21 objects)
   LeafLanes lt;
-  issue_source(d, smem, TileJob{1, 0, t, n, 0}, lt, false);
+  load_lanes(d, 0, lt);
+  issue_source(d, smem, TileJob{1, 0, t, n, 0}, lt, true);
   // the descriptor fields of the scan and the member requests, read while
   // the records are in flight (the empty asm makes them arrive here: left
   // to the compiler, each would be read where it is first used, one
@@ -1591,20 +1581,14 @@ __global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
   const uint8_t* const pool = j.pool;
   asm volatile("" ::"s"(stride), "s"(len_off), "s"(ptr_off), "s"(pool_end), "s"(mstride), "s"(malign), "s"(S),
                "s"(pool), "s"(flags), "s"(epoch));
-  load_lanes(d, 0, lt);
   dma_wait();
   __syncthreads();
-  // 2.-3. every wave scans the tile's counts by itself, 64 objects (one
-  // per lane) at a time, with no barrier: wave 0 publishes the tile's
-  // aggregate and then assembles the prefix, the last wave keeps the
-  // tile-local offsets, pointers and counts in LDS for the stores, and
-  // waves 1 .. on request the first staging pass of each chunk's members
-  // as soon as the chunk is scanned, then store the per-object leaves.  A
-  // one-wave work-group does these in turn, the look-back before the
-  // member requests (its loads would otherwise queue behind them).
+  // 2. counts: every wave scans the tile's counts by itself, one object
+  // per lane, 64 at a time (a DPP prefix sum: no LDS scan and no barrier
+  // inside it); the last wave keeps the tile-local offsets, pointers and
+  // validated counts in LDS, wave 1 publishes the tile's aggregate (wave
+  // 0's look-back loads would otherwise wait for the store)
   const uint32_t lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
-  uint32_t col0, cstride;
-  jag_columns(j, m, &col0, &cstride);
   uint64_t A = 0;
   bool bad = false;
   for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
@@ -1616,7 +1600,6 @@ __global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
       p = *reinterpret_cast<const uint64_t*>(rec + ptr_off);
     }
     const bool good = o >= cnt || ((p & (uint64_t)(malign - 1)) == 0 && p <= pool_end && len * mstride <= pool_end - p);
-    const uint32_t vl = good ? (uint32_t)len : 0u;
     bad |= !good;
     // counts below 2^26 sum to less than 2^32 over 64 lanes: a 32-bit scan
     uint64_t inc;
@@ -1630,28 +1613,24 @@ __global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
         if (lane >= (uint32_t)dd) inc += x;
       }
     }
-    const uint64_t b = A + inc - len;   // tile-local exclusive offset of object o
     if (wave == nwaves - 1 && o < cnt) {
-      m.loff[o] = b;
+      m.loff[o] = A + inc - len;
       m.ptrs[o] = p;
-      m.vlen[o] = vl;
+      m.vlen[o] = good ? (uint32_t)len : 0u;
     }
-    if (nwaves > 1 && wave > 0) {
-      const uint32_t nobj = min(64u, cnt - c0);
-      for (uint32_t i = wave - 1; i < nobj; i += nwaves - 1) {
-        const uint64_t bi = lane_u64(b, i);
-        const uint64_t hi = min<uint64_t>(bi + (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)i), S);
-        if (bi < hi) jag_issue_run<NW>(pool, lane_u64(p, i), bi, bi, hi, 0, mstride, col0, cstride);
-      }
-    }
-    A += lane_u64(inc, 63);
+    A += ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)(inc >> 32), 63) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)inc, 63);
   }
   if (bad && wave == 0) flag(status, ST_FLAG_BOUNDS);
-  if (tid == 0) lb_store(flags + t, lb_word(t == 0 ? 2u : 1u, epoch, A));
+  if (tid == (nt > 64 ? 64u : 0u)) lb_store(flags + t, lb_word(t == 0 ? 2u : 1u, epoch, A));
   if (wave == nwaves - 1 && lane == 0) m.loff[cnt] = A;
+  __syncthreads();   // tile-local offsets, pointers and counts in LDS
   const uint32_t pm0 = (uint32_t)min<uint64_t>(A, S);
-  // 4.-5. the prefix (wave 0) while the other waves store the per-object
-  // leaves
+  jag_owners(m, cnt, 0, pm0);
+  __syncthreads();
+  // 3.-5. wave 0 assembles the prefix while the other waves request the
+  // first members and store the per-object leaves (a one-wave work-group
+  // does the three in turn, the look-back first)
   DenseLds dm;
   dm.src = smem;
   dm.dst = smem;
@@ -1659,9 +1638,9 @@ __global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
   dm.offs = m.wsum;
   uint64_t P = 0;
   if (wave == 0 && t > 0) P = jag_look_back(j, flags, t, epoch);
-  if (nwaves == 1) jag_issue<NW>(j, m, cnt, 0, pm0, 0, 1);
   if (nwaves == 1 || wave > 0) {
     const uint32_t w0 = nwaves == 1 ? 0 : 1;
+    jag_issue<NW>(j, m, 0, pm0, w0, nwaves - w0);
     const uint32_t tx = tid - 64 * w0, ntx = nt - 64 * w0;
     if (d.dst.kind == KIND_SOA) transform_kinds<KIND_AOS, KIND_SOA, true>(d, dm, lt, i0, cnt, tx, ntx);
     else transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, dm, lt, i0, cnt, tx, ntx);
@@ -1682,7 +1661,11 @@ __global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
   const uint64_t stored = min<uint64_t>(A, P < j.capacity ? j.capacity - P : 0);
   for (uint64_t p0 = 0; p0 < stored; p0 += S) {
     const uint32_t pm = (uint32_t)min<uint64_t>(S, stored - p0);
-    if (p0 > 0) jag_issue<NW>(j, m, cnt, p0, pm, 0, nwaves);
+    if (p0 > 0) {
+      jag_owners(m, cnt, p0, pm);
+      __syncthreads();
+      jag_issue<NW>(j, m, p0, pm, 0, nwaves);
+    }
     dma_wait();
     __syncthreads();
     jag_store<NW>(j, m, P, p0, pm);
