@@ -215,7 +215,8 @@ def main():
                       f"tile {shape[0]} objects, {shape[1]} threads, {shape[2]} work-groups"
                       + (f", one source tile read per work-group for all {binfo.fanout_steps} conversions "
                          f"({binfo.fanout_threads} threads each)" if fanned else "")
-                      + (", double-buffered" if binfo.double_buffered else "") + " (autotuned)",
+                      + (", double-buffered" if binfo.double_buffered else "")
+                      + (", non-temporal stores" if binfo.stream_stores else "") + " (autotuned)",
         },
         "roofline": {
             "bound": "hbm",

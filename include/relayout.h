@@ -567,7 +567,9 @@ typedef struct rl_batch_info {
   uint32_t fanout_groups;     /* fan-out groups formed */
   uint32_t fanout_steps;      /* dense steps inside them */
   uint32_t dense_steps;       /* dense steps in all */
-  uint32_t reserved[3];
+  uint32_t stream_stores;     /* 1: values written straight to SoA / AoSoA destinations
+                                 use non-temporal stores (the tuner's choice) */
+  uint32_t reserved[2];
 } rl_batch_info;
 /* RL_EINVAL for a NULL argument or a batch not finalized. */
 rl_status rl_batch_get_info(const rl_batch* batch, rl_batch_info* info);

@@ -83,7 +83,8 @@ class rl_batch_opts(ctypes.Structure):
 class rl_batch_info(ctypes.Structure):
     _fields_ = [("double_buffered", ctypes.c_uint32), ("fanout_threads", ctypes.c_uint32),
                 ("fanout_groups", ctypes.c_uint32), ("fanout_steps", ctypes.c_uint32),
-                ("dense_steps", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("dense_steps", ctypes.c_uint32), ("stream_stores", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class rl_server_opts(ctypes.Structure):

@@ -54,6 +54,7 @@ struct Config {
   uint32_t direct = 0;   // 1: launch the batch kernels directly instead of replaying the graph
   uint32_t gather_threads = kGatherThreads;   // member-gather work-groups
   uint32_t pipe = 0;     // 1: dense steps double-buffered (two tile slots per work-group)
+  uint32_t stream = 1;   // 1: values stored straight from the transform are non-temporal
   uint32_t fanout = 0;   // >0: steps reading the same source tiles share one work-group per tile,
                          // this many threads per destination (64 or 128)
 };
@@ -113,6 +114,7 @@ rl_status plan_all(rl_batch* b, const Config& c) {
   shape.threads = c.threads;
   shape.direct = shape_from_env().direct;
   shape.fused = 0;   // batches run their jagged items through the table kernels
+  shape.stream = c.stream ? 1 : 0;
   for (auto& it : b->items) {
     Plan p;
     if (it.n) {
@@ -421,6 +423,7 @@ bool cache_lookup(const std::string& path, const std::string& sig, Config* c) {
       num("gather_threads", &t.gather_threads);
       num("pipe", &t.pipe);
       num("fanout", &t.fanout);
+      num("stream", &t.stream);
       if (t.fanout) t.fanout = t.fanout >= 128 ? 128 : 64;
       *c = t;
       return true;
@@ -444,8 +447,8 @@ void cache_store(const std::string& path, const std::string& sig, const Config& 
   char buf[256];
   snprintf(buf, sizeof buf,
            "  \"%s\": {\"tile\":%u, \"threads\":%u, \"grid\":%u, \"width\":%u, \"direct\":%u, "
-           "\"gather_threads\":%u, \"pipe\":%u, \"fanout\":%u, \"us\":%.2f}",
-           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, c.gather_threads, c.pipe, c.fanout, us);
+           "\"gather_threads\":%u, \"pipe\":%u, \"fanout\":%u, \"stream\":%u, \"us\":%.2f}",
+           sig.c_str(), c.tile, c.threads, c.grid, c.width, c.direct, c.gather_threads, c.pipe, c.fanout, c.stream, us);
   keep.push_back(buf);
   std::ofstream o(path + ".tmp");
   o << "{\n";
@@ -608,6 +611,18 @@ rl_status autotune(rl_batch* b, hipStream_t s, Config* best) {
           if (us < best_us * 0.98) { best_us = us; bc = c; }
         }
     }
+  }
+  // ordinary stores for the values of direct destinations (non-temporal
+  // ones help a few conversions of one source and cost the 512-collection
+  // batch 5%)
+  {
+    Config c = bc;
+    c.stream = 0;
+    double us;
+    rl_status st = time_config(b, c, s, flush, &us);
+    if (st) return st;
+    seen.emplace_back(us, c);
+    if (us < best_us * 0.98) { best_us = us; bc = c; }
   }
   // the three fastest shapes timed twice more, interleaved: single timings
   // of shapes within a few percent of each other order them at random
@@ -814,6 +829,7 @@ extern "C" rl_status rl_batch_finalize(rl_batch* b, void* stream) {
   if (const char* v = getenv("RL_BATCH_THREADS")) c.threads = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_GATHER_THREADS")) c.gather_threads = (uint32_t)strtoul(v, nullptr, 10);
   if (const char* v = getenv("RL_BATCH_PIPE")) c.pipe = (uint32_t)strtoul(v, nullptr, 10) ? 1 : 0;
+  if (const char* v = getenv("RL_BATCH_STREAM")) c.stream = (uint32_t)strtoul(v, nullptr, 10) ? 1 : 0;
   if (const char* v = getenv("RL_BATCH_FANOUT")) {
     const uint32_t f = (uint32_t)strtoul(v, nullptr, 10);
     c.fanout = f == 0 ? 0 : f >= 128 ? 128 : 64;
@@ -902,6 +918,7 @@ extern "C" rl_status rl_batch_get_info(const rl_batch* b, rl_batch_info* info) {
   info->fanout_groups = b->dev.fan_groups;
   info->fanout_steps = b->dev.fan_steps;
   info->dense_steps = b->dev.dense_steps;
+  info->stream_stores = b->cfg.stream;
   return RL_OK;
 }
 

@@ -369,6 +369,7 @@ PlanShape shape_from_env() {
   if (const char* v = getenv("RL_SOURCE_DMA")) s.dma = atoi(v) ? -1 : 0;
   if (const char* v = getenv("RL_JAGGED_FUSED")) s.fused = atoi(v) == 2 ? 2 : atoi(v) ? -1 : 0;
   if (const char* v = getenv("RL_PIPELINE")) s.pipe = atoi(v) == 1 ? 1 : atoi(v) ? -1 : 0;
+  if (const char* v = getenv("RL_STREAM_STORES")) s.stream = atoi(v) ? 1 : 0;
   return s;
 }
 }  // namespace rl

@@ -105,6 +105,23 @@ __device__ __forceinline__ void g2l(uint8_t* lds, const uint8_t* g, uint32_t byt
   }
 }
 
+// Values stored straight from the transform can be non-temporal
+// (DenseDesc::stream_stores): a conversion streams its destination out and
+// never reads it back, and such stores leave the caches to the data still
+// to be read (measured: the benchmark step of four conversions 10.7 ->
+// 8.4 us, AoS -> SoA at 2^22 - 2^24 objects 4.8 -> 5.1 and 5.2 -> 5.4 TB/s,
+// single conversions 7-9% faster; but the 512-collection batch 1.29 ->
+// 1.35 ms, so batches leave the choice to their tuner).  Destination images copied out of LDS (records, host
+// memory) keep ordinary stores: non-temporal there, AoSoA -> AoS lost 6%
+// and zero-copy writes into pinned host memory up to 13%.  Member columns
+// of the single-pass jagged kernel are non-temporal only for conversions
+// of at most one round of work-groups (50,000 clusters: 15.3 -> 13.6 us;
+// at 2^21 objects, 32,768 tiles, 460 -> 520 us).
+template <class T>
+__device__ __forceinline__ void st_nt(RL_G T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // Copy `bytes` from LDS (16-byte aligned) to global memory.
 __device__ __forceinline__ void l2g(uint8_t* g, const uint8_t* lds, uint32_t bytes,
                                     uint32_t tid, uint32_t nt) {
@@ -289,7 +306,7 @@ __device__ __forceinline__ void store_side(const DD& d, const uint8_t* img, uint
       const auto& L = d.leaf[c];
       const uint32_t first_v = L.dst_off >> 4;
       RL_G v4u* col = gp(reinterpret_cast<v4u*>(L.dst_col + idx0 * L.dst_size));
-      col[v - first_v] = lv[v];
+      st_nt(col + (v - first_v), lv[v]);
     }
   } else {
     for (uint32_t c = 0; c < d.n_leaves; ++c) {
@@ -629,15 +646,17 @@ __device__ __forceinline__ uint32_t at(uint32_t a, uint32_t off, uint32_t b) {
   return K == KIND_AOS ? a + off : a + off + b * SIZE;
 }
 
-// Store a value into an LDS image, or (GLOBAL) into global memory.
-template <bool GLOBAL, class T>
+// Store a value into an LDS image, or (GLOBAL) into global memory,
+// non-temporally with NT.
+template <bool GLOBAL, class T, bool NT = false>
 __device__ __forceinline__ void put(uint8_t* p, T v) {
-  if (GLOBAL) *gp(reinterpret_cast<T*>(p)) = v;
+  if (GLOBAL && NT) st_nt(gp(reinterpret_cast<T*>(p)), v);
+  else if (GLOBAL) *gp(reinterpret_cast<T*>(p)) = v;
   else *reinterpret_cast<T*>(p) = v;
 }
 
 // Threads tx of ntx (normally the whole work-group) take part.
-template <uint32_t SK, uint32_t DK, bool FULL, bool DIRECT, class DD>
+template <uint32_t SK, uint32_t DK, bool FULL, bool DIRECT, bool NT = false, class DD>
 __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
                                                uint32_t o0, uint32_t cnt, uint32_t tx, uint32_t ntx) {
   constexpr uint32_t P = kObjPerThread;
@@ -660,7 +679,7 @@ __device__ __forceinline__ void transform_pass(const DD& d, const DenseLds& m, c
   _Pragma("unroll") for (uint32_t k = 0; k < P; ++k) {                                 \
     if (FULL || ok[k]) {                                                               \
       const ST x = *reinterpret_cast<const ST*>(S + at<SK, SS>(sa[k], so, sb[k]));     \
-      put<DIRECT, DT>((col ? colp + i0 * DS : Dtile) + at<DK, DS>(da[k], dof, db[k]), (EXPR)); \
+      put<DIRECT, DT, NT>((col ? colp + i0 * DS : Dtile) + at<DK, DS>(da[k], dof, db[k]), (EXPR)); \
     }                                                                                  \
   }
   const uint32_t nl = d.n_leaves;
@@ -784,13 +803,13 @@ __device__ __forceinline__ void zero_tail_direct(const DD& d, uint64_t i0, uint3
   }
 }
 
-template <uint32_t SK, uint32_t DK, bool DIRECT, class DD>
+template <uint32_t SK, uint32_t DK, bool DIRECT, bool NT = false, class DD>
 __device__ __forceinline__ void transform_kinds(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
                                                 uint32_t cnt, uint32_t tx = threadIdx.x, uint32_t ntx = blockDim.x) {
   const uint32_t per_pass = kObjPerThread * ntx;
   for (uint32_t o0 = 0; o0 < cnt; o0 += per_pass) {
-    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true, DIRECT>(d, m, lt, i0, o0, cnt, tx, ntx);
-    else transform_pass<SK, DK, false, DIRECT>(d, m, lt, i0, o0, cnt, tx, ntx);
+    if (o0 + per_pass <= cnt) transform_pass<SK, DK, true, DIRECT, NT>(d, m, lt, i0, o0, cnt, tx, ntx);
+    else transform_pass<SK, DK, false, DIRECT, NT>(d, m, lt, i0, o0, cnt, tx, ntx);
   }
   if (DIRECT && DK == KIND_AOSOA) zero_tail_direct(d, i0, cnt, tx, ntx);
 }
@@ -798,19 +817,26 @@ __device__ __forceinline__ void transform_kinds(const DD& d, const DenseLds& m, 
 // Direct destinations (SoA columns, AoSoA blocks): each leaf of a wave's
 // consecutive objects is one contiguous run in global memory, so the
 // stores coalesce without a destination image.
+template <bool NT, class DD>
+__device__ __forceinline__ void transform_direct_kinds(const DD& d, const DenseLds& m, const LeafLanes& lt,
+                                                       uint64_t i0, uint32_t cnt, uint32_t nt, uint32_t tx) {
+  switch (d.src.kind * 3 + d.dst.kind) {
+    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true, NT>(d, m, lt, i0, cnt, tx, nt); break;
+  }
+}
+
 template <class DD>
 __device__ __forceinline__ void transform_direct(const DD& d, const DenseLds& m, const LeafLanes& lt, uint64_t i0,
                                                  uint32_t cnt, uint32_t nt, uint32_t tx = threadIdx.x) {
-  switch (d.src.kind * 3 + d.dst.kind) {
-    case KIND_AOS * 3 + KIND_SOA: transform_kinds<KIND_AOS, KIND_SOA, true>(d, m, lt, i0, cnt, tx, nt); break;
-    case KIND_AOS * 3 + KIND_AOSOA: transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, m, lt, i0, cnt, tx, nt); break;
-    case KIND_SOA * 3 + KIND_SOA: transform_kinds<KIND_SOA, KIND_SOA, true>(d, m, lt, i0, cnt, tx, nt); break;
-    case KIND_SOA * 3 + KIND_AOSOA: transform_kinds<KIND_SOA, KIND_AOSOA, true>(d, m, lt, i0, cnt, tx, nt); break;
-    case KIND_AOSOA * 3 + KIND_SOA: transform_kinds<KIND_AOSOA, KIND_SOA, true>(d, m, lt, i0, cnt, tx, nt); break;
-    case KIND_SOA * 3 + KIND_AOS: transform_kinds<KIND_SOA, KIND_AOS, true>(d, m, lt, i0, cnt, tx, nt); break;
-    case KIND_AOSOA * 3 + KIND_AOS: transform_kinds<KIND_AOSOA, KIND_AOS, true>(d, m, lt, i0, cnt, tx, nt); break;
-    default: transform_kinds<KIND_AOSOA, KIND_AOSOA, true>(d, m, lt, i0, cnt, tx, nt); break;
-  }
+  if (d.stream_stores) transform_direct_kinds<true>(d, m, lt, i0, cnt, nt, tx);
+  else transform_direct_kinds<false>(d, m, lt, i0, cnt, nt, tx);
 }
 
 template <class DD>
@@ -1542,7 +1568,8 @@ __device__ __forceinline__ void jag_store(const JD& j, const JagLds& m, uint64_t
     RL_G v4u* cv = reinterpret_cast<RL_G v4u*>(col + a0);
     for (uint32_t v = tid; v < nv; v += nt) {
       const uint32_t* x = s0 + 4 * v;
-      cv[v] = v4u{x[0], x[1], x[2], x[3]};
+      if (j.stream_members) st_nt(cv + v, v4u{x[0], x[1], x[2], x[3]});
+      else cv[v] = v4u{x[0], x[1], x[2], x[3]};
     }
     for (uint64_t i = a1 + tid; i < hi; i += nt) col[i] = sq[i - lo];
   }
@@ -1642,8 +1669,15 @@ __global__ void __launch_bounds__(256) jagged_kernel(const JaggedDesc) {
     const uint32_t w0 = nwaves == 1 ? 0 : 1;
     jag_issue<NW>(j, m, 0, pm0, w0, nwaves - w0);
     const uint32_t tx = tid - 64 * w0, ntx = nt - 64 * w0;
-    if (d.dst.kind == KIND_SOA) transform_kinds<KIND_AOS, KIND_SOA, true>(d, dm, lt, i0, cnt, tx, ntx);
-    else transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, dm, lt, i0, cnt, tx, ntx);
+    // the two destination kinds of this kernel only (the whole switch of
+    // transform_direct would raise the kernel's registers)
+    if (d.stream_stores) {
+      if (d.dst.kind == KIND_SOA) transform_kinds<KIND_AOS, KIND_SOA, true, true>(d, dm, lt, i0, cnt, tx, ntx);
+      else transform_kinds<KIND_AOS, KIND_AOSOA, true, true>(d, dm, lt, i0, cnt, tx, ntx);
+    } else {
+      if (d.dst.kind == KIND_SOA) transform_kinds<KIND_AOS, KIND_SOA, true>(d, dm, lt, i0, cnt, tx, ntx);
+      else transform_kinds<KIND_AOS, KIND_AOSOA, true>(d, dm, lt, i0, cnt, tx, ntx);
+    }
   }
   if (tid == 0) m.rsum[0] = P;
   __syncthreads();

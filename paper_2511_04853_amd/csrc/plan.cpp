@@ -17,6 +17,9 @@ static constexpr uint32_t kLdsBudget = 64 * 1024;
 static constexpr uint64_t kPipeMinTiles = 16384;
 static constexpr uint32_t kDefaultTile = 512;
 static constexpr uint32_t kMaxTile = 4096;
+// single-pass jagged conversions of at most this many tiles store member
+// columns non-temporally
+static constexpr uint64_t kStreamMembersTiles = 1024;
 
 SideSpec object_side(const rl_layout* L, void* const* bufs, uint64_t index0) {
   SideSpec s;
@@ -240,6 +243,7 @@ static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& sha
   const bool long_run = dense_tiles(st.dense) >= kPipeMinTiles && st.dense.dst_direct &&
                         st.dense.src.kind != KIND_SOA;
   if (shape.pipe != 0 && (long_run || shape.pipe == 1) && 2 * slot <= kLdsBudget) st.dense.pipe_slot = slot;
+  st.dense.stream_stores = shape.stream ? 1u : 0u;
   plan->steps.push_back(st);
   return RL_OK;
 }
@@ -383,6 +387,10 @@ static bool build_jagged(const rl_view& src, const rl_view& dst, uint64_t n, con
   while (jagged_lds_bytes(j) > 40 * 1024 && j.stage > 256) j.stage -= 64;
   if (jagged_lds_bytes(j) > kLdsBudget) return false;
   const uint64_t need = lookback_bytes((n + tile - 1) / tile);
+  // non-temporal member stores pay while the tiles fit one round of
+  // resident work-groups and cost beyond it
+  j.stream_members = (n + tile - 1) / tile <= kStreamMembersTiles ? 1u : 0u;
+  j.dense.stream_stores = shape.stream ? j.stream_members : 0u;
   if (shape.lookback) {
     if (need > shape.lookback_bytes) return false;
     j.lookback = shape.lookback;

@@ -19,6 +19,7 @@ struct PlanShape {
   int pipe = -1;          // dense steps double-buffered (two tile slots in LDS):
                           // -1 for long conversions where two slots fit, 0 never,
                           // 1 wherever two slots fit
+  int stream = 1;         // 1: values stored straight from the transform are non-temporal
   // Look-back memory of single-pass jagged steps given by the caller
   // (zeroed before its first use, used by one stream at a time); null:
   // the library's per-stream buffer.  A step needing more tiles than it

@@ -113,7 +113,7 @@ struct DenseDesc {
   // the source member capacity, total inside the destination's).
   const uint8_t* stage_offsets;
   uint32_t stage_type;     // rl_type of stage_offsets
-  uint32_t pad2;
+  uint32_t stream_stores;  // 1: values stored straight from the transform are non-temporal
   uint64_t stage_src_capacity;
   uint64_t stage_dst_capacity;
   LeafDesc leaf[kMaxLeaves];
@@ -190,6 +190,7 @@ struct JaggedDesc {
   uint32_t off_type;       // rl_type of the offsets
   uint32_t stage;          // members per LDS staging pass
   uint32_t epoch;          // launch number on this look-back buffer (set at enqueue)
+  uint32_t stream_members; // 1: member columns stored non-temporally
 };
 // Look-back memory: one word per tile, zero before its first use; launches
 // on one buffer must be ordered (one stream) and numbered by the host.
