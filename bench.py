@@ -865,16 +865,22 @@ def sweep(P, W, torch, stream, copies=4, schemas=("plain8", "cell"), sizes=(1 <<
     return res
 
 
-def _wall(fn, torch, reps=20, warm=3):
-    """Mean wall seconds of fn() with the device drained before and after."""
+def _wall(fn, torch, reps=20, warm=3, rounds=3):
+    """Wall seconds per fn() call: `rounds` rounds of `reps` back-to-back
+    calls, the device drained before and after each round; the fastest
+    round's mean (one host stall inside a round would otherwise double a
+    transfer of a hundred microseconds)."""
     for _ in range(warm):
         fn()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(reps):
-        fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t) / reps
+    best = float("inf")
+    for _ in range(rounds):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        best = min(best, (time.perf_counter() - t) / reps)
+    return best
 
 
 def h2d(P, W, torch, stream):
