@@ -12,9 +12,6 @@
 namespace rl {
 
 static constexpr uint32_t kLdsBudget = 64 * 1024;
-// tiles of a single conversion from which its work-groups are
-// double-buffered (two tile slots in LDS)
-static constexpr uint64_t kPipeMinTiles = 16384;
 static constexpr uint32_t kDefaultTile = 512;
 static constexpr uint32_t kMaxTile = 4096;
 // single-pass jagged conversions of at most this many tiles store member
@@ -230,19 +227,13 @@ static rl_status push_dense(Plan* plan, const DenseDesc& d, const PlanShape& sha
   if (shape.dma == 0) st.dense.dma = 0;
   st.threads = dense_threads(d.tile, shape);
   st.grid = default_grid(dense_tiles(d), shape);
-  // double-buffered only for long conversions: it halves the resident
-  // work-groups, which pays where each holds many tiles (measured: cell
-  // and plain AoS -> SoA at 2^24 - 2^25 objects, 2-4% faster; at 2^20 -
-  // 2^22 objects and for the step of four 190,000-object conversions,
-  // slower), and only where one source run per tile comes in and the
-  // values go straight out: with a column run per leaf to bring in, or a
-  // destination image to write out, it lost at 2^24 objects (SoA -> AoS
-  // 2.2 against 3.3-3.9 TB/s, SoA -> AoSoA 3.9-4.5 against 5.0,
-  // AoSoA -> AoS 4.1 against 4.2-4.5)
+  // double-buffered only where asked for (RL_PIPELINE=1, a batch tuner
+  // candidate): with records read and values stored non-temporally the
+  // single-slot kernel is faster at every length measured (AoS -> SoA at
+  // 2^24 - 2^25 objects: 5.25-5.50 double-buffered, 5.57-5.86 TB/s single
+  // slot); before those cache policies two slots had won by 2-4% there
   const uint32_t slot = (dense_lds_bytes(st.dense) + 15u) & ~15u;
-  const bool long_run = dense_tiles(st.dense) >= kPipeMinTiles && st.dense.dst_direct &&
-                        st.dense.src.kind != KIND_SOA;
-  if (shape.pipe != 0 && (long_run || shape.pipe == 1) && 2 * slot <= kLdsBudget) st.dense.pipe_slot = slot;
+  if (shape.pipe == 1 && 2 * slot <= kLdsBudget) st.dense.pipe_slot = slot;
   st.dense.stream_stores = shape.stream ? 1u : 0u;
   plan->steps.push_back(st);
   return RL_OK;

@@ -17,8 +17,7 @@ struct PlanShape {
   int fused = -1;         // single-pass jagged kernel: -1 where it applies, 0 never,
                           // 2 required (a jagged records source fails where it does not apply)
   int pipe = -1;          // dense steps double-buffered (two tile slots in LDS):
-                          // -1 for long conversions where two slots fit, 0 never,
-                          // 1 wherever two slots fit
+                          // 1 wherever two slots fit; otherwise (-1, 0) never
   int stream = 1;         // 1: values stored straight from the transform are non-temporal
   // Look-back memory of single-pass jagged steps given by the caller
   // (zeroed before its first use, used by one stream at a time); null:

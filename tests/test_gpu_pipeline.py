@@ -56,9 +56,9 @@ def test_jagged_scan_and_offsets_records_double_buffered(pipelined, monkeypatch)
         _check(W.PARTICLE, pair[0], pair[1], 9_001, seed=12, mean_len=3)
 
 
-def test_long_conversion_takes_the_double_buffered_path_by_default():
-    """Past the tile threshold the default plan double-buffers (checked
-    against the oracle like every conversion)."""
+def test_long_conversion_single_slot_by_default():
+    """A long conversion (16,384 tiles and more) on the default plan, which
+    no longer double-buffers it, against the oracle."""
     _check(W.PLAIN8, ("aos", 0), ("soa", 0), 16384 * 512 + 77, seed=2)
 
 
