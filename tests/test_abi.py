@@ -177,7 +177,23 @@ def test_batch_validation_on_the_host():
     w = ctypes.c_uint32()
     assert P.lib().rl_batch_item_width(h, 0, ctypes.byref(w)) == P.RL_EINVAL    # not finalized
     assert P.lib().rl_batch_launch(h, ctypes.c_void_p(0)) == P.RL_EINVAL
+    info = P.rl_batch_info()
+    assert P.lib().rl_batch_get_info(h, ctypes.byref(info)) == P.RL_EINVAL     # not finalized
+    assert P.lib().rl_batch_get_info(h, None) == P.RL_EINVAL
+    assert P.lib().rl_batch_get_info(None, ctypes.byref(info)) == P.RL_EINVAL
     P.lib().rl_batch_destroy(h)
+
+
+def test_batch_info_struct_matches_header():
+    """rl_batch_info is eight 32-bit words in the header's order."""
+    assert ctypes.sizeof(P.rl_batch_info) == 32
+    names = [f[0] for f in P.rl_batch_info._fields_]
+    assert names == ["double_buffered", "fanout_threads", "fanout_groups", "fanout_steps", "dense_steps",
+                     "stream_stores", "reserved"]
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "relayout.h")).read()
+    body = hdr[hdr.index("typedef struct rl_batch_info {"):hdr.index("} rl_batch_info;")]
+    assert [n for n in names[:-1] if n in body] == names[:-1]
+    assert body.index("double_buffered") < body.index("fanout_threads") < body.index("stream_stores") < body.index("reserved[2]")
 
 
 def test_auto_width_layout_is_batch_only():
