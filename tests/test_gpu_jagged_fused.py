@@ -193,3 +193,28 @@ def test_capacity_and_bounds_statuses(monkeypatch):
     assert st == P.RL_EBOUNDS
     rc, rs, _ = H.run_lib_convert(aos, bad, soa, v.n, [pool], [tot])
     assert rc == P.RL_OK and rs == P.RL_EBOUNDS
+
+
+def test_huge_count_outside_its_pool(monkeypatch):
+    """A record whose count is 2^28 (past its pool): the single-pass
+    kernel's scan then takes its 64-bit path (counts of 2^26 and more);
+    the offsets column is the exact prefix sum of the counts as given,
+    members are stored up to the capacity, and the status is the oracle's."""
+    monkeypatch.setenv("RL_JAGGED_FUSED", "2")
+    v = W.cluster_values(2_000, seed=23)
+    sp = H.SchemaPair(W.CLUSTER)
+    aos, soa = sp.layout("aos"), sp.layout("soa")
+    tot = v.total(0)
+    src = oracle.pack(sp.orc, v, aos.orc, pool_order=True)
+    pool = len(src[1]) // 8
+    bad = [b.copy() for b in src]
+    rec = bad[0].view(np.uint8).reshape(v.n, -1)
+    len_off = aos.lib.slot_offsets[7]
+    lens = np.array(v.lengths[0], dtype=np.uint64)
+    lens[777] = 1 << 28
+    rec[777, len_off:len_off + 4] = np.frombuffer(np.uint32(1 << 28).tobytes(), np.uint8)
+    st, _, _ = H.oracle_convert(aos, bad, soa, v.n, [pool], [tot])
+    rc, rs, got = H.run_lib_convert(aos, bad, soa, v.n, [pool], [tot])
+    assert rc == P.RL_OK and rs == st != P.RL_OK
+    want = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint32)
+    assert np.array_equal(got[6].view(np.uint32)[:v.n + 1], want)
