@@ -380,8 +380,8 @@ static bool build_jagged(const rl_view& src, const rl_view& dst, uint64_t n, con
   const uint64_t need = lookback_bytes((n + tile - 1) / tile);
   // non-temporal member stores pay while the tiles fit one round of
   // resident work-groups and cost beyond it
-  j.stream_members = (n + tile - 1) / tile <= kStreamMembersTiles ? 1u : 0u;
-  j.dense.stream_stores = shape.stream ? j.stream_members : 0u;
+  j.stream_members = shape.stream && (n + tile - 1) / tile <= kStreamMembersTiles ? 1u : 0u;
+  j.dense.stream_stores = j.stream_members;
   if (shape.lookback) {
     if (need > shape.lookback_bytes) return false;
     j.lookback = shape.lookback;
